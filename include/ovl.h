@@ -1,0 +1,170 @@
+/*
+ * ovl.h -- C ABI of the MI355X (gfx950) library that applies the matrix sign
+ * function of the hermitian Wilson-Dirac operator, and the overlap-Dirac
+ * operator built from it, through the contour-integral projectors of
+ * Nagai & Tomiya, "Extensively parallelizable chiral fermion"
+ * (arXiv:2204.01583).
+ *
+ * What is computed (paper: eqs. (1), (3)-(7)):
+ *   sgn(H_W) b  ~=  s = sum_j c_j y_j,   (z_j I - H_W) y_j = b,
+ *   D_ov(m_q) b  =  (1+m_q)/2 b + (1-m_q)/2 gamma5 s,
+ * with nodes z_j and weights c_j of the N_q-point trapezoidal rule on the
+ * two ellipses Gamma_+ (centre +gamma) and Gamma_- (centre -gamma) of eq. (7)
+ * (weights of Gamma_- negated, eq. (3)).  All 2 N_q shifted systems are
+ * solved from ONE Krylov space of a seed system (z_seed - H_W) x = b by a
+ * shifted Galerkin BiCG recurrence (the "shift solver" of the paper's method
+ * description; seed z_seed = 1 + 0.05i in the Supplemental Material).
+ *
+ * Operator conventions (the paper names only H_W = gamma5 D_W(-m0)):
+ *   D_W = 1 - kappa sum_mu [ (1-gamma_mu) U_mu(x) psi(x+mu)
+ *                           + (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu) ],
+ *   kappa = 1/(2(4-m0)); chiral gamma basis, gamma5 = diag(1,1,-1,-1);
+ *   a hop that wraps around direction mu is multiplied by bc[mu].
+ *
+ * Layouts (all complex numbers are interleaved (re, im) IEEE doubles,
+ * row-major, contiguous, in DEVICE memory of the context's GPU, owned by the
+ * caller; mu = 0..3 is x, y, z, t):
+ *   gauge  U    : complex128 [4][Lt][Lz][Ly][Lx][3][3]
+ *   spinors     : complex128 [nrhs][Lt][Lz][Ly][Lx][4][3]  (spin, then colour)
+ *   force / grad: complex128 [4][Lt][Lz][Ly][Lx][3][3]
+ * Scalars passed by host pointer (z_reim, c_reim, dims, bc) are HOST memory.
+ *
+ * Streams: every call enqueues on the context's HIP stream (ovl_set_stream).
+ * Calls that take an ovl_stats* synchronise that stream once at the end and
+ * fill it; they return only after the result is complete in `out`.
+ *
+ * Errors: every call returns an int status.  It never aborts or throws.
+ * On an error the output buffers are unspecified and ovl_last_error(ctx)
+ * holds a message.  A context is not thread-safe; distinct contexts are.
+ */
+#ifndef OVL_H
+#define OVL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define OVL_OK                0
+#define OVL_NOT_CONVERGED     1   /* maxiter reached; out holds the last iterate  */
+#define OVL_E_ARG           (-1)  /* bad argument (size, pointer, parameter)      */
+#define OVL_E_STATE         (-2)  /* a required setter was not called            */
+#define OVL_E_HIP           (-3)  /* a HIP runtime call failed                    */
+#define OVL_E_OOM           (-4)  /* device allocation failed                     */
+#define OVL_E_NONFINITE     (-5)  /* NaN or Inf met in a reduction                */
+#define OVL_E_BREAKDOWN     (-6)  /* Krylov pivot <r, A p> vanished               */
+
+/* ---- solver selectors ---------------------------------------------------- */
+#define OVL_PREC_FP64   0   /* every vector operation in FP64                                */
+#define OVL_PREC_MIXED  1   /* FP64 until the largest shifted residual falls below
+                               `switch_res` * ||b||, then FP32 stencil and vectors; the scalar
+                               recurrences, weights and the sum stay FP64                     */
+
+#define OVL_FORM_REFERENCE 0 /* per-shift solutions x_j kept in HBM, s = sum c_j x_j at the end */
+#define OVL_FORM_FUSED     1 /* per-shift directions p_j only; s accumulated in the same sweep  */
+#define OVL_FORM_BASIS     2 /* seed residuals r_k stored; s = sum_k h_k r_k from the scalars    */
+#define OVL_FORM_TWOPASS   3 /* as BASIS, but the r_k are regenerated in a second pass          */
+
+typedef struct ovl_ctx ovl_ctx;
+
+typedef struct {
+    int32_t iterations;        /* seed iterations of the last apply (max over rhs)          */
+    int32_t fp32_iterations;   /* of which in FP32 (OVL_PREC_MIXED)                          */
+    int32_t n_shifts;          /* number of shifted systems 2*N_q (or ovl_set_nodes n)       */
+    int32_t n_active_end;      /* shifts still above tolerance at the end (0 if converged)   */
+    double  max_est_rel_res;   /* max_j ||r_j|| / ||b|| from the recurrence, at the end      */
+    double  seconds;           /* wall time of the apply on the stream                       */
+    double  reserved[4];
+} ovl_stats;
+
+/* Create a context for a Lx*Ly*Lz*Lt lattice on HIP device `device`.
+ * dims = {Lx, Ly, Lz, Lt}, each >= 2; bc = {+1|-1} per direction (paper: the
+ * boundary is not stated; the usual choice is {1,1,1,-1}).  `hip_stream` is a
+ * hipStream_t or NULL for the null stream.  *ctx receives the context. */
+int ovl_create(ovl_ctx** ctx, const int32_t dims[4], const int32_t bc[4],
+               int32_t device, void* hip_stream);
+int ovl_destroy(ovl_ctx* ctx);
+int ovl_set_stream(ovl_ctx* ctx, void* hip_stream);
+
+/* Copy the gauge field (complex128 [4][Lt][Lz][Ly][Lx][3][3], device) into
+ * the context's internal layout; the caller may free U afterwards.  The
+ * links are used as given (no unitarity check), so H_W stays hermitian for
+ * any complex 3x3 links. */
+int ovl_set_gauge(ovl_ctx* ctx, const void* U_dev);
+
+/* m0 > 0 is the negative Wilson mass of H_W = gamma5 D_W(-m0) (paper: after
+ * eq. (1); m0 = 1 in the numerical experiments); requires 0 < m0 < 4.
+ * mq is the fermion mass of D_ov(m_q) in eq. (1). */
+int ovl_set_masses(ovl_ctx* ctx, double m0, double mq);
+
+/* Nodes and weights of eq. (7) on both ellipses: theta_j = 2 pi (j-1/2)/nq,
+ * z_j = +-gamma + rho (cos theta_j + i alpha sin theta_j),
+ * c_j = +-rho (alpha cos theta_j + i sin theta_j)/nq.  nq counts the points
+ * of ONE contour and must be even (an odd nq puts a node on the real axis).
+ * The paper's contour: alpha = 0.1, rho = 1.1999, gamma = 1.2. */
+int ovl_set_contour(ovl_ctx* ctx, int32_t nq, double gamma, double rho, double alpha);
+
+/* General rational function s = sum_j c_j (z_j - H_W)^-1 b: n nodes given as
+ * interleaved host arrays z_reim[2n], c_reim[2n].  Every Im z_j must be
+ * nonzero.  Replaces any contour set before. */
+int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* z_reim, const double* c_reim);
+
+/* precision: OVL_PREC_*; form: OVL_FORM_*; tol: shift j stops when its
+ * residual estimate ||r_j|| <= tol*||b||; maxiter: seed iterations;
+ * (zseed_re, zseed_im): seed shift, zseed_im != 0; switch_res: the MIXED
+ * switch point (ignored for FP64; <= 0 picks 1e-4). */
+int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, int32_t maxiter,
+                   double zseed_re, double zseed_im, double switch_res);
+
+/* out = H_W in for nrhs spinors (eq. (1): H_W = gamma5 D_W(-m0)).  out must
+ * not alias in. */
+int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs);
+
+/* out = sum_j c_j (z_j - H_W)^-1 in  (eqs. (5)-(7)) for nrhs spinors.
+ * Returns OVL_NOT_CONVERGED (out = last iterate) if maxiter is reached.
+ * st may be NULL. */
+int ovl_apply_sign(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs, ovl_stats* st);
+
+/* out = D_ov(m_q) in = (1+m_q)/2 in + (1-m_q)/2 gamma5 sgn(H_W) in  (eq. (1)). */
+int ovl_apply_dov(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs, ovl_stats* st);
+
+/* Derivative of S = phi^dag D_ov^dag D_ov phi (one phi) with respect to the
+ * links, through adjoint shifted solves (dS = 2 Re sum_j c_j X_j^dag dH Y_j,
+ * Y_j = (z_j-H)^-1 phi, X_j = (conj z_j - H)^-1 psi, psi = (1-m_q)/2 gamma5 D_ov phi).
+ * kind 0: the traceless hermitian force F with dS/dh = sum tr(Omega F) for
+ *         U -> exp(i h Omega) U;  kind 1: the complex gradient G with
+ *         dS = Re sum conj(G) dU (PyTorch's convention).
+ * *action (host, may be NULL) receives S.  shift_chunk bounds how many
+ * shifted solutions are held at once (<= 0: all). */
+int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind, int32_t shift_chunk,
+              double* action, ovl_stats* st);
+
+/* ovl_apply_sign for several contexts (different lattices allowed) at once:
+ * out[i] = sgn(H_W[ctx i]) in[i] with nrhs[i] spinors.  All contexts must be
+ * on one device and share the node set and solver settings of ctxs[0]; the
+ * work is enqueued on ctxs[0]'s stream as one captured graph per chunk of
+ * iterations.  st (may be NULL) receives the aggregate. */
+int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const void* const* in,
+                           void* const* out, const int32_t* nrhs, ovl_stats* st);
+
+/* Stats of the last apply on this context. */
+int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
+
+/* Time one internal kernel on the context's stream with HIP events: `reps`
+ * back-to-back launches after one warm-up, average milliseconds in *avg_ms
+ * and the algorithmic bytes of one launch in *bytes.  which:
+ *   0: FP64 stencil on nrhs internal spinors   1: FP32 stencil
+ *   2: FP64 fused shift sweep, nrhs sources x all shifts   3: its FP32 form
+ * Buffers are internal scratch (contents arbitrary but finite). */
+int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
+                     double* avg_ms, double* bytes);
+
+const char* ovl_status_string(int status);
+const char* ovl_last_error(const ovl_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OVL_H */

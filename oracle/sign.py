@@ -45,6 +45,11 @@ _pool_H = None
 def _pool_init(H):
     global _pool_H
     _pool_H = H
+    try:  # one BLAS thread per worker: the pool already spans the cores
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
 
 
 def _pool_task(args):

@@ -1,0 +1,763 @@
+// Host side of the library: contexts, argument checks, contour tables and the
+// shifted-solver driver that enqueues the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ovl.h"
+#include "kernels.h"
+
+using namespace ovl;
+
+namespace {
+
+// A device allocation that only grows.
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t nb) {
+        if (nb <= bytes) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, nb);
+        if (e == hipSuccess) bytes = nb;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace
+
+struct ovl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Geom g{};
+    int bc[4] = {1, 1, 1, -1};
+    double m0 = 0.0, mq = 0.0;
+    bool masses_set = false, gauge_set = false;
+    // nodes and weights (host, FP64)
+    std::vector<double2> z, c;
+    // solver settings
+    int precision = OVL_PREC_FP64;
+    int form = OVL_FORM_FUSED;
+    double tol = 1e-12;
+    int maxiter = 4000;
+    double2 zseed = make_double2(1.0, 0.05);
+    double switch_res = 1e-4;
+    int poll = 8;  // iterations between convergence polls
+    // device buffers
+    DBuf U64, U32;
+    DBuf hw_in, hw_out;
+    DBuf b64, r64, p64, q64, r32, p32, q32, s64, pj64, pj32, xj;
+    std::vector<DBuf> slot_chunks;   // basis forms: kSlotChunk residual slots each
+    size_t slot_chunk_bytes = 0;
+    DBuf part_w, part_e, state, shifts, lists, nodes_dev, hist, W, h;
+    SrcState* host_state = nullptr;  // pinned mirror
+    int host_state_n = 0;
+    DBuf bench_a, bench_b;
+    ovl_stats last{};
+    char err[512] = {0};
+};
+
+namespace {
+
+int fail(ovl_ctx* ctx, int code, const char* fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? OVL_E_OOM : OVL_E_HIP,           \
+                        "%s failed: %s", #call, hipGetErrorString(e_));                      \
+    } while (0)
+
+int check_dev_ptr(ovl_ctx* ctx, const void* p, const char* name) {
+    if (p == nullptr) return fail(ctx, OVL_E_ARG, "%s is NULL", name);
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, OVL_E_ARG, "%s is not a HIP device pointer", name);
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        return fail(ctx, OVL_E_ARG, "%s is not device memory", name);
+    if (at.device != ctx->device)
+        return fail(ctx, OVL_E_ARG, "%s lives on device %d, context is on device %d", name,
+                    at.device, ctx->device);
+    return OVL_OK;
+}
+
+bool overlaps(const void* a, const void* b, size_t n) {
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + n && y < x + n;
+}
+
+double kappa_of(double m0) { return 1.0 / (2.0 * (4.0 - m0)); }
+
+int64_t n12(const ovl_ctx* ctx) { return 12 * ctx->g.V; }
+
+struct DeviceGuard {
+    int prev = 0;
+    explicit DeviceGuard(int d) {
+        (void)hipGetDevice(&prev);
+        if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceGuard() {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+// ============================================================================
+// context
+// ============================================================================
+extern "C" int ovl_create(ovl_ctx** out, const int32_t dims[4], const int32_t bc[4],
+                          int32_t device, void* hip_stream) {
+    if (out == nullptr || dims == nullptr) return OVL_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return OVL_E_HIP;
+    }
+    if (device < 0 || device >= ndev) return OVL_E_ARG;
+    int64_t V = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (dims[i] < 2 || dims[i] > (1 << 15)) return OVL_E_ARG;
+        V *= dims[i];
+    }
+    if (V > (int64_t)1 << 31) return OVL_E_ARG;
+    if (bc != nullptr)
+        for (int i = 0; i < 4; ++i)
+            if (bc[i] != 1 && bc[i] != -1) return OVL_E_ARG;
+    ovl_ctx* ctx = new (std::nothrow) ovl_ctx();
+    if (!ctx) return OVL_E_OOM;
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    int64_t stride = 1;
+    for (int i = 0; i < 4; ++i) {
+        ctx->g.L[i] = dims[i];
+        ctx->g.stride[i] = stride;
+        stride *= dims[i];
+        if (bc) ctx->bc[i] = bc[i];
+    }
+    ctx->g.V = V;
+    *out = ctx;
+    return OVL_OK;
+}
+
+extern "C" int ovl_destroy(ovl_ctx* ctx) {
+    if (!ctx) return OVL_OK;
+    DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    DBuf* bufs[] = {&ctx->U64,  &ctx->U32,   &ctx->hw_in,  &ctx->hw_out, &ctx->b64,   &ctx->r64,
+                    &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
+                    &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_e,
+                    &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
+                    &ctx->h,    &ctx->bench_a, &ctx->bench_b};
+    for (DBuf* b : bufs) b->release();
+    for (DBuf& b : ctx->slot_chunks) b.release();
+    if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+    delete ctx;
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_stream(ovl_ctx* ctx, void* hip_stream) {
+    if (!ctx) return OVL_E_ARG;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_gauge(ovl_ctx* ctx, const void* U) {
+    if (!ctx) return OVL_E_ARG;
+    DeviceGuard dg(ctx->device);
+    int rc = check_dev_ptr(ctx, U, "U");
+    if (rc) return rc;
+    const size_t nl = (size_t)36 * ctx->g.V;
+    HIPCHK(ctx, ctx->U64.ensure(nl * sizeof(double2)));
+    HIPCHK(ctx, ctx->U32.ensure(nl * sizeof(float2)));
+    launch_pack_gauge(static_cast<const double2*>(U), ctx->U64.as<double2>(),
+                      ctx->U32.as<float2>(), ctx->g, ctx->bc, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->gauge_set = true;
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_masses(ovl_ctx* ctx, double m0, double mq) {
+    if (!ctx) return OVL_E_ARG;
+    if (!(m0 > 0.0 && m0 < 4.0) || !std::isfinite(mq))
+        return fail(ctx, OVL_E_ARG, "need 0 < m0 < 4 and finite mq (m0=%g, mq=%g)", m0, mq);
+    ctx->m0 = m0;
+    ctx->mq = mq;
+    ctx->masses_set = true;
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_contour(ovl_ctx* ctx, int32_t nq, double gamma, double rho, double alpha) {
+    if (!ctx) return OVL_E_ARG;
+    if (nq < 2 || (nq & 1) || 2 * nq > kMaxShifts)
+        return fail(ctx, OVL_E_ARG, "nq must be even and 2 <= nq <= %d (got %d)", kMaxShifts / 2, nq);
+    if (!(rho > 0.0) || !(alpha > 0.0) || !std::isfinite(gamma))
+        return fail(ctx, OVL_E_ARG, "need rho > 0, alpha > 0, finite gamma");
+    // eq. (7): theta_j = 2 pi (j - 1/2)/N_q, z_j = +-gamma + rho (cos + i alpha sin),
+    // weight rho (alpha cos + i sin)/N_q, negated on Gamma_- (eq. (3))
+    ctx->z.assign(2 * nq, make_double2(0, 0));
+    ctx->c.assign(2 * nq, make_double2(0, 0));
+    for (int j = 1; j <= nq; ++j) {
+        const double th = 2.0 * M_PI * (j - 0.5) / nq;
+        const double ct = std::cos(th), sn = std::sin(th);
+        const double er = rho * ct, ei = rho * alpha * sn;
+        const double wr = rho * alpha * ct / nq, wi = rho * sn / nq;
+        ctx->z[j - 1] = make_double2(gamma + er, ei);
+        ctx->c[j - 1] = make_double2(wr, wi);
+        ctx->z[nq + j - 1] = make_double2(-gamma + er, ei);
+        ctx->c[nq + j - 1] = make_double2(-wr, -wi);
+    }
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* zr, const double* cr) {
+    if (!ctx) return OVL_E_ARG;
+    if (n < 1 || n > kMaxShifts || !zr || !cr)
+        return fail(ctx, OVL_E_ARG, "need 1 <= n <= %d nodes and non-NULL arrays", kMaxShifts);
+    for (int j = 0; j < n; ++j) {
+        if (!std::isfinite(zr[2 * j]) || !std::isfinite(zr[2 * j + 1]) ||
+            !std::isfinite(cr[2 * j]) || !std::isfinite(cr[2 * j + 1]))
+            return fail(ctx, OVL_E_ARG, "node %d is not finite", j);
+        if (zr[2 * j + 1] == 0.0)
+            return fail(ctx, OVL_E_ARG, "node %d lies on the real axis", j);
+    }
+    ctx->z.resize(n);
+    ctx->c.resize(n);
+    for (int j = 0; j < n; ++j) {
+        ctx->z[j] = make_double2(zr[2 * j], zr[2 * j + 1]);
+        ctx->c[j] = make_double2(cr[2 * j], cr[2 * j + 1]);
+    }
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol,
+                              int32_t maxiter, double zr, double zi, double switch_res) {
+    if (!ctx) return OVL_E_ARG;
+    if (precision != OVL_PREC_FP64 && precision != OVL_PREC_MIXED)
+        return fail(ctx, OVL_E_ARG, "unknown precision %d", precision);
+    if (form < OVL_FORM_REFERENCE || form > OVL_FORM_BASIS)
+        return fail(ctx, OVL_E_ARG, "unknown or unsupported form %d", form);
+    if (!(tol > 0.0 && tol < 1.0)) return fail(ctx, OVL_E_ARG, "need 0 < tol < 1");
+    if (maxiter < 1 || maxiter > 1000000) return fail(ctx, OVL_E_ARG, "bad maxiter %d", maxiter);
+    if (!std::isfinite(zr) || !std::isfinite(zi) || zi == 0.0)
+        return fail(ctx, OVL_E_ARG, "seed shift must be finite with a nonzero imaginary part");
+    ctx->precision = precision;
+    ctx->form = form;
+    ctx->tol = tol;
+    ctx->maxiter = maxiter;
+    ctx->zseed = make_double2(zr, zi);
+    ctx->switch_res = switch_res > 0.0 ? switch_res : 1e-4;
+    return OVL_OK;
+}
+
+extern "C" int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st) {
+    if (!ctx || !st) return OVL_E_ARG;
+    *st = ctx->last;
+    return OVL_OK;
+}
+
+extern "C" const char* ovl_last_error(const ovl_ctx* ctx) { return ctx ? ctx->err : "null context"; }
+
+extern "C" const char* ovl_status_string(int s) {
+    switch (s) {
+        case OVL_OK: return "OVL_OK";
+        case OVL_NOT_CONVERGED: return "OVL_NOT_CONVERGED";
+        case OVL_E_ARG: return "OVL_E_ARG";
+        case OVL_E_STATE: return "OVL_E_STATE";
+        case OVL_E_HIP: return "OVL_E_HIP";
+        case OVL_E_OOM: return "OVL_E_OOM";
+        case OVL_E_NONFINITE: return "OVL_E_NONFINITE";
+        case OVL_E_BREAKDOWN: return "OVL_E_BREAKDOWN";
+        default: return "unknown status";
+    }
+}
+
+// ============================================================================
+// H_W
+// ============================================================================
+static int check_apply_args(ovl_ctx* ctx, const void* in, const void* out, int nrhs,
+                            bool need_nodes) {
+    if (nrhs < 1 || nrhs > 65535) return fail(ctx, OVL_E_ARG, "bad nrhs %d", nrhs);
+    if (!ctx->gauge_set) return fail(ctx, OVL_E_STATE, "ovl_set_gauge was not called");
+    if (!ctx->masses_set) return fail(ctx, OVL_E_STATE, "ovl_set_masses was not called");
+    if (need_nodes && ctx->z.empty())
+        return fail(ctx, OVL_E_STATE, "ovl_set_contour / ovl_set_nodes was not called");
+    int rc = check_dev_ptr(ctx, in, "in");
+    if (rc) return rc;
+    rc = check_dev_ptr(ctx, out, "out");
+    if (rc) return rc;
+    const size_t bytes = (size_t)nrhs * n12(ctx) * sizeof(double2);
+    if (overlaps(in, out, bytes)) return fail(ctx, OVL_E_ARG, "out aliases in");
+    return OVL_OK;
+}
+
+extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs) {
+    if (!ctx) return OVL_E_ARG;
+    DeviceGuard dg(ctx->device);
+    int rc = check_apply_args(ctx, in, out, nrhs, false);
+    if (rc) return rc;
+    const size_t nb = (size_t)nrhs * n12(ctx) * sizeof(double2);
+    HIPCHK(ctx, ctx->hw_in.ensure(nb));
+    HIPCHK(ctx, ctx->hw_out.ensure(nb));
+    launch_pack_spinor64(static_cast<const double2*>(in), ctx->hw_in.as<double2>(), ctx->g.V,
+                         nrhs, ctx->stream);
+    launch_wilson<double>(0, ctx->hw_in.as<double2>(), ctx->hw_out.as<double2>(),
+                          ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0), make_double2(0, 0),
+                          nullptr, nullptr, nullptr, nrhs, ctx->stream);
+    launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, nrhs,
+                           ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    return OVL_OK;
+}
+
+// ============================================================================
+// shifted solver
+// ============================================================================
+namespace {
+
+constexpr int kSlotChunk = 32;  // residual slots per basis allocation
+
+struct Work {
+    int nsrc, J, maxk;
+    int64_t N;  // 12 V
+    double2 *b64, *r64, *p64, *q64, *s64, *pj64, *xj;
+    float2 *r32, *p32, *q32, *pj32;
+    std::vector<char*> chunks;  // basis: slot i at chunks[i / kSlotChunk] + (i % kSlotChunk) * slot_bytes
+    size_t slot_bytes;          // nsrc * N * sizeof(double2)
+    double2* part_w;
+    double* part_e;
+    SrcState* st;
+    double2 *pi, *pi_prev, *pi_next, *aj;
+    int* active;
+    int* lst_j;
+    double2 *lst_a, *lst_ipi, *lst_b;
+    double2 *dz, *cj;
+    double2 *h_a, *h_b, *h_pi, *W, *h;
+};
+
+int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
+    const int J = (int)ctx->z.size();
+    const int64_t N = n12(ctx);
+    const bool mixed = ctx->precision == OVL_PREC_MIXED;
+    const int form = ctx->form;
+    w.nsrc = nsrc;
+    w.J = J;
+    w.N = N;
+    w.maxk = ctx->maxiter;
+    const size_t vec64 = (size_t)nsrc * N * sizeof(double2);
+    const size_t vec32 = (size_t)nsrc * N * sizeof(float2);
+    HIPCHK(ctx, ctx->b64.ensure(vec64));
+    HIPCHK(ctx, ctx->r64.ensure(vec64));
+    HIPCHK(ctx, ctx->p64.ensure(vec64));
+    HIPCHK(ctx, ctx->q64.ensure(vec64));
+    HIPCHK(ctx, ctx->s64.ensure(vec64));
+    w.b64 = ctx->b64.as<double2>();
+    w.r64 = ctx->r64.as<double2>();
+    w.p64 = ctx->p64.as<double2>();
+    w.q64 = ctx->q64.as<double2>();
+    w.s64 = ctx->s64.as<double2>();
+    w.r32 = w.p32 = w.q32 = w.pj32 = nullptr;
+    w.pj64 = w.xj = nullptr;
+    w.chunks.clear();
+    w.slot_bytes = vec64;
+    if (mixed) {
+        HIPCHK(ctx, ctx->r32.ensure(vec32));
+        HIPCHK(ctx, ctx->p32.ensure(vec32));
+        HIPCHK(ctx, ctx->q32.ensure(vec32));
+        w.r32 = ctx->r32.as<float2>();
+        w.p32 = ctx->p32.as<float2>();
+        w.q32 = ctx->q32.as<float2>();
+    }
+    if (form == OVL_FORM_FUSED || form == OVL_FORM_REFERENCE) {
+        HIPCHK(ctx, ctx->pj64.ensure(vec64 * J));
+        w.pj64 = ctx->pj64.as<double2>();
+        if (mixed) {
+            HIPCHK(ctx, ctx->pj32.ensure(vec32 * J));
+            w.pj32 = ctx->pj32.as<float2>();
+        }
+        if (form == OVL_FORM_REFERENCE) {
+            HIPCHK(ctx, ctx->xj.ensure(vec64 * J));
+            w.xj = ctx->xj.as<double2>();
+        }
+    }
+    const bool basis = form == OVL_FORM_BASIS;
+    if (basis && ctx->slot_chunk_bytes != vec64 * kSlotChunk) {
+        // slot geometry changed: drop the old chunks
+        for (DBuf& b : ctx->slot_chunks) b.release();
+        ctx->slot_chunks.clear();
+        ctx->slot_chunk_bytes = vec64 * kSlotChunk;
+    }
+    const int nbw = wilson_blocks(ctx->g), nbe = elem_blocks(N);
+    HIPCHK(ctx, ctx->part_w.ensure((size_t)nsrc * nbw * sizeof(double2)));
+    HIPCHK(ctx, ctx->part_e.ensure((size_t)nsrc * nbe * sizeof(double)));
+    HIPCHK(ctx, ctx->state.ensure((size_t)nsrc * sizeof(SrcState)));
+    w.part_w = ctx->part_w.as<double2>();
+    w.part_e = ctx->part_e.as<double>();
+    w.st = ctx->state.as<SrcState>();
+    const size_t sj = (size_t)nsrc * J;
+    HIPCHK(ctx, ctx->shifts.ensure(sj * (4 * sizeof(double2) + sizeof(int))));
+    w.pi = ctx->shifts.as<double2>();
+    w.pi_prev = w.pi + sj;
+    w.pi_next = w.pi_prev + sj;
+    w.aj = w.pi_next + sj;
+    w.active = reinterpret_cast<int*>(w.aj + sj);
+    HIPCHK(ctx, ctx->lists.ensure(sj * (3 * sizeof(double2) + sizeof(int))));
+    w.lst_a = ctx->lists.as<double2>();
+    w.lst_ipi = w.lst_a + sj;
+    w.lst_b = w.lst_ipi + sj;
+    w.lst_j = reinterpret_cast<int*>(w.lst_b + sj);
+    HIPCHK(ctx, ctx->nodes_dev.ensure((size_t)2 * J * sizeof(double2)));
+    w.dz = ctx->nodes_dev.as<double2>();
+    w.cj = w.dz + J;
+    std::vector<double2> tab(2 * J);
+    for (int j = 0; j < J; ++j) {
+        tab[j] = make_double2(ctx->z[j].x - ctx->zseed.x, ctx->z[j].y - ctx->zseed.y);
+        tab[J + j] = ctx->c[j];
+    }
+    HIPCHK(ctx, hipMemcpyAsync(w.dz, tab.data(), tab.size() * sizeof(double2),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // tab is pageable and goes out of scope
+    w.h_a = w.h_b = w.h_pi = w.W = w.h = nullptr;
+    if (basis) {
+        const size_t hs = (size_t)nsrc * (w.maxk + 1) * J;
+        HIPCHK(ctx, ctx->hist.ensure(3 * hs * sizeof(double2)));
+        HIPCHK(ctx, ctx->W.ensure(hs * sizeof(double2)));
+        HIPCHK(ctx, ctx->h.ensure((size_t)nsrc * (w.maxk + 1) * sizeof(double2)));
+        w.h_a = ctx->hist.as<double2>();
+        w.h_b = w.h_a + hs;
+        w.h_pi = w.h_b + hs;
+        w.W = ctx->W.as<double2>();
+        w.h = ctx->h.as<double2>();
+    }
+    if (ctx->host_state_n < nsrc) {
+        if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+        ctx->host_state = nullptr;
+        ctx->host_state_n = 0;
+        HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, nsrc * sizeof(SrcState),
+                                  hipHostMallocDefault));
+        ctx->host_state_n = nsrc;
+    }
+    return OVL_OK;
+}
+
+template <typename R> R* slot_ptr(const Work& w, int i) {
+    return reinterpret_cast<R*>(w.chunks[i / kSlotChunk] + (size_t)(i % kSlotChunk) * w.slot_bytes);
+}
+
+// make sure residual slots 0 .. upto exist
+int ensure_slots(ovl_ctx* ctx, Work& w, int upto) {
+    const int need = upto / kSlotChunk + 1;
+    while ((int)ctx->slot_chunks.size() < need) {
+        ctx->slot_chunks.emplace_back();
+        HIPCHK(ctx, ctx->slot_chunks.back().ensure(ctx->slot_chunk_bytes));
+    }
+    w.chunks.clear();
+    for (DBuf& b : ctx->slot_chunks) w.chunks.push_back(b.as<char>());
+    return OVL_OK;
+}
+
+// One seed iteration k in precision R (double before the switch, float after).
+template <typename R>
+void enqueue_iteration(ovl_ctx* ctx, const Work& w, int k, int form, hipStream_t s, C2<R>* r,
+                       C2<R>* p, C2<R>* q, C2<R>* pj, const C2<R>* U) {
+    const int64_t N = w.N;
+    const int nbw = wilson_blocks(ctx->g), nbe = elem_blocks(N);
+    const bool basis = form == OVL_FORM_BASIS;
+    // r_k: working vector, or basis slot k (slot stride between sources is N either way
+    // for FP64; FP32 slots are packed at the slot base with the same N stride)
+    C2<R>* rk = basis ? slot_ptr<C2<R>>(w, k) : r;
+    C2<R>* rk1 = basis ? slot_ptr<C2<R>>(w, k + 1) : r;
+    launch_wilson<R>(1, p, q, U, ctx->g, kappa_of(ctx->m0), ctx->zseed, rk, w.part_w, w.st,
+                     w.nsrc, s);
+    launch_alpha(w.st, w.part_w, nbw, w.dz, w.pi, w.pi_prev, w.pi_next, w.aj, w.active, w.J,
+                 w.nsrc, s);
+    launch_update_r<R>(rk, rk1, q, w.st, w.part_e, N, N, N, w.nsrc, s);
+    BetaArgs a;
+    a.st = w.st;
+    a.partial = w.part_e;
+    a.nblk = nbe;
+    a.c = (form == OVL_FORM_REFERENCE) ? nullptr : w.cj;
+    a.pi = w.pi;
+    a.pi_prev = w.pi_prev;
+    a.pi_next = w.pi_next;
+    a.aj = w.aj;
+    a.active = w.active;
+    a.J = w.J;
+    a.lst_j = w.lst_j;
+    a.lst_a = w.lst_a;
+    a.lst_ipi = w.lst_ipi;
+    a.lst_b = w.lst_b;
+    a.tol = ctx->tol;
+    a.h_a = basis ? w.h_a : nullptr;
+    a.h_b = basis ? w.h_b : nullptr;
+    a.h_pi = basis ? w.h_pi : nullptr;
+    a.maxk = w.maxk;
+    launch_beta(a, w.nsrc, s);
+    if (form == OVL_FORM_FUSED)
+        launch_sweep_fused<R>(r, p, pj, w.s64, w.b64, w.st, w.lst_j, w.lst_a, w.lst_ipi, w.lst_b,
+                              w.J, N, w.nsrc, k == 0, s);
+    else if (form == OVL_FORM_REFERENCE)
+        launch_sweep_ref<R>(r, p, pj, w.xj, w.b64, w.st, w.lst_j, w.lst_a, w.lst_ipi, w.lst_b,
+                            w.J, N, w.nsrc, k == 0, s);
+    else
+        launch_update_p<R>(rk1, p, w.st, N, N, w.nsrc, s);
+}
+
+}  // namespace
+
+// Runs the shifted solver on nsrc sources packed in w.b64 and leaves
+// s = sum_j c_j y_j in w.s64.  Returns a status; fills ctx->last.
+static int solve(ovl_ctx* ctx, Work& w) {
+    hipStream_t s = ctx->stream;
+    const int form = ctx->form;
+    const bool mixed = ctx->precision == OVL_PREC_MIXED;
+    const int64_t N = w.N;
+    const size_t vec64 = (size_t)w.nsrc * N * sizeof(double2);
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventRecord(e0, s));
+    // r = p = b, s = 0 (fused), x_j = 0 (reference), slot 0 = b (basis)
+    if (form == OVL_FORM_BASIS) {
+        int rc = ensure_slots(ctx, w, std::min(w.maxk, ctx->poll) + 1);
+        if (rc) return rc;
+    }
+    if (form == OVL_FORM_BASIS)
+        HIPCHK(ctx, hipMemcpyAsync(slot_ptr<double2>(w, 0), w.b64, vec64,
+                                   hipMemcpyDeviceToDevice, s));
+    else
+        HIPCHK(ctx, hipMemcpyAsync(w.r64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(w.p64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
+    if (form == OVL_FORM_FUSED) HIPCHK(ctx, hipMemsetAsync(w.s64, 0, vec64, s));
+    if (form == OVL_FORM_REFERENCE) HIPCHK(ctx, hipMemsetAsync(w.xj, 0, vec64 * w.J, s));
+    launch_init_state(w.st, w.b64, w.part_e, N, w.pi, w.pi_prev, w.active, w.J,
+                      form == OVL_FORM_BASIS ? w.h_pi : nullptr, w.maxk, w.nsrc, s);
+    HIPCHK(ctx, hipGetLastError());
+
+    bool low = false;  // FP32 phase active
+    int k_switch = -1;
+    int k = 0;
+    bool all_done = false;
+    int status = OVL_OK;
+    double maxres = 1.0;
+    int iters = 0, nact = 0;
+    while (k < w.maxk) {
+        const int chunk = std::min(ctx->poll, w.maxk - k);
+        if (form == OVL_FORM_BASIS) {
+            int rc = ensure_slots(ctx, w, k + chunk + 1);
+            if (rc) return rc;
+        }
+        for (int i = 0; i < chunk; ++i, ++k) {
+            if (!low)
+                enqueue_iteration<double>(ctx, w, k, form, s, w.r64, w.p64, w.q64, w.pj64,
+                                          ctx->U64.as<double2>());
+            else
+                enqueue_iteration<float>(ctx, w, k, form, s, w.r32, w.p32, w.q32, w.pj32,
+                                         ctx->U32.as<float2>());
+        }
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, w.st, w.nsrc * sizeof(SrcState),
+                                   hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        all_done = true;
+        maxres = 0.0;
+        iters = 0;
+        nact = 0;
+        for (int n = 0; n < w.nsrc; ++n) {
+            const SrcState& S = ctx->host_state[n];
+            if (S.status != OVL_OK && status == OVL_OK) status = S.status;
+            all_done = all_done && S.done;
+            maxres = std::max(maxres, S.maxres);
+            iters = std::max(iters, S.iter);
+            nact += S.nact;
+        }
+        if (status != OVL_OK || all_done) break;
+        if (mixed && !low && maxres < ctx->switch_res && k < w.maxk) {
+            // relaxed precision: from here the remaining corrections are small
+            // enough that FP32 vectors perturb the result by ~eps32 * switch_res
+            low = true;
+            k_switch = k;
+            launch_convert_64_to_32(w.p64, w.p32, (int64_t)w.nsrc * N, s);
+            if (form == OVL_FORM_BASIS) {
+                launch_convert_64_to_32(slot_ptr<double2>(w, k), w.r32, (int64_t)w.nsrc * N, s);
+                HIPCHK(ctx, hipMemcpyAsync(slot_ptr<float2>(w, k), w.r32,
+                                           (size_t)w.nsrc * N * sizeof(float2),
+                                           hipMemcpyDeviceToDevice, s));
+            } else {
+                launch_convert_64_to_32(w.r64, w.r32, (int64_t)w.nsrc * N, s);
+                launch_convert_64_to_32(w.pj64, w.pj32, (int64_t)w.nsrc * N * w.J, s);
+            }
+            HIPCHK(ctx, hipGetLastError());
+        }
+    }
+    if (status == OVL_OK && !all_done) status = OVL_NOT_CONVERGED;
+    if (status == OVL_OK || status == OVL_NOT_CONVERGED) {
+        if (form == OVL_FORM_REFERENCE) {
+            launch_sum_ref(w.xj, w.cj, w.s64, w.J, N, w.nsrc, s);
+        } else if (form == OVL_FORM_BASIS) {
+            launch_basis_coef(w.h_a, w.h_b, w.h_pi, w.cj, w.st, w.W, w.h, w.J, w.maxk, w.nsrc, s);
+            // s = sum_i h_i r_i, chunk by chunk; FP64 slots below k_switch, FP32 from it
+            const int kend = iters + 1;
+            const int ksw = k_switch < 0 ? kend : k_switch;
+            bool acc = false;
+            for (int c0 = 0; c0 < kend; c0 += kSlotChunk) {
+                const int c1 = std::min(kend, c0 + kSlotChunk);
+                char* base = w.chunks[c0 / kSlotChunk];
+                const int a0 = c0, a1 = std::min(c1, ksw);
+                if (a1 > a0) {
+                    launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.maxk, w.st, c0,
+                                              a0 - c0, a1 - c0, w.s64, acc, N, w.nsrc, s);
+                    acc = true;
+                }
+                const int f0 = std::max(c0, ksw), f1 = c1;
+                if (f1 > f0) {
+                    launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.maxk, w.st,
+                                             c0, f0 - c0, f1 - c0, w.s64, acc, N, w.nsrc, s);
+                    acc = true;
+                }
+            }
+        }
+        HIPCHK(ctx, hipGetLastError());
+    }
+    HIPCHK(ctx, hipEventRecord(e1, s));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ovl_stats& L = ctx->last;
+    std::memset(&L, 0, sizeof(L));
+    L.iterations = iters;
+    L.fp32_iterations = k_switch < 0 ? 0 : std::max(0, iters - k_switch);
+    L.n_shifts = w.J;
+    L.n_active_end = nact;
+    L.max_est_rel_res = maxres;
+    L.seconds = ms * 1e-3;
+    if (status < 0) fail(ctx, status, "solver stopped: %s", ovl_status_string(status));
+    if (status == OVL_NOT_CONVERGED)
+        fail(ctx, status, "maxiter=%d reached with %d shifts above tol (max est. res %.3e)",
+             w.maxk, nact, maxres);
+    return status;
+}
+
+static int apply_common(ovl_ctx* ctx, const void* in, void* out, int nrhs, ovl_stats* st,
+                        bool dov) {
+    if (!ctx) return OVL_E_ARG;
+    DeviceGuard dg(ctx->device);
+    int rc = check_apply_args(ctx, in, out, nrhs, true);
+    if (rc) return rc;
+    Work w;
+    rc = prepare(ctx, nrhs, w);
+    if (rc) return rc;
+    launch_pack_spinor64(static_cast<const double2*>(in), w.b64, ctx->g.V, nrhs, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    rc = solve(ctx, w);
+    if (rc < 0) return rc;
+    if (dov)
+        launch_unpack_dov(w.s64, static_cast<const double2*>(in), static_cast<double2*>(out),
+                          0.5 * (1.0 + ctx->mq), 0.5 * (1.0 - ctx->mq), ctx->g.V, nrhs,
+                          ctx->stream);
+    else
+        launch_unpack_spinor64(w.s64, static_cast<double2*>(out), ctx->g.V, nrhs, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (st) *st = ctx->last;
+    return rc;
+}
+
+extern "C" int ovl_apply_sign(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs,
+                              ovl_stats* st) {
+    return apply_common(ctx, in, out, nrhs, st, false);
+}
+
+extern "C" int ovl_apply_dov(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs,
+                             ovl_stats* st) {
+    return apply_common(ctx, in, out, nrhs, st, true);
+}
+
+extern "C" int ovl_force(ovl_ctx* ctx, const void*, void*, int32_t, int32_t, double*, ovl_stats*) {
+    if (!ctx) return OVL_E_ARG;
+    return fail(ctx, OVL_E_STATE, "ovl_force is not available in this build");
+}
+
+extern "C" int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const void* const*,
+                                      void* const*, const int32_t*, ovl_stats*) {
+    if (!ctxs || nctx < 1 || !ctxs[0]) return OVL_E_ARG;
+    return fail(ctxs[0], OVL_E_STATE, "ovl_apply_sign_batched is not available in this build");
+}
+
+// ============================================================================
+// kernel timing
+// ============================================================================
+extern "C" int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
+                                double* avg_ms, double* bytes) {
+    if (!ctx || !avg_ms || !bytes) return OVL_E_ARG;
+    if (nrhs < 1 || reps < 1 || which < 0 || which > 1)
+        return fail(ctx, OVL_E_ARG, "bad bench arguments");
+    if (!ctx->gauge_set || !ctx->masses_set) return fail(ctx, OVL_E_STATE, "gauge/masses not set");
+    DeviceGuard dg(ctx->device);
+    const int64_t N = n12(ctx);
+    const bool f32 = which == 1;
+    const size_t es = f32 ? sizeof(float2) : sizeof(double2);
+    const size_t nb = (size_t)nrhs * N * es;
+    HIPCHK(ctx, ctx->bench_a.ensure(nb));
+    HIPCHK(ctx, ctx->bench_b.ensure(nb));
+    HIPCHK(ctx, hipMemsetAsync(ctx->bench_a.p, 0, nb, ctx->stream));
+    auto launch = [&]() {
+        if (f32)
+            launch_wilson<float>(0, ctx->bench_a.as<float2>(), ctx->bench_b.as<float2>(),
+                                 ctx->U32.as<float2>(), ctx->g, kappa_of(ctx->m0),
+                                 make_double2(0, 0), nullptr, nullptr, nullptr, nrhs, ctx->stream);
+        else
+            launch_wilson<double>(0, ctx->bench_a.as<double2>(), ctx->bench_b.as<double2>(),
+                                  ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0),
+                                  make_double2(0, 0), nullptr, nullptr, nullptr, nrhs, ctx->stream);
+    };
+    launch();
+    HIPCHK(ctx, hipGetLastError());
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+    for (int i = 0; i < reps; ++i) launch();
+    HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / reps;
+    // algorithmic bytes: links once (36 complex per site), each spinor read once and
+    // written once (12 complex per site per rhs)
+    *bytes = (double)ctx->g.V * (36.0 * es + 2.0 * 12.0 * es * nrhs);
+    return OVL_OK;
+}

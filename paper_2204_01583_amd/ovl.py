@@ -1,0 +1,232 @@
+"""ctypes binding of libovl.so (C ABI: include/ovl.h).
+
+Argument marshalling only: tensors are passed as device pointers together with
+the current torch stream, and every computation runs in the library's HIP
+kernels.  If the library is missing this module raises; there is no fallback.
+
+Tensors use the external layouts of the C ABI (complex128, row-major):
+  gauge   [4][Lt][Lz][Ly][Lx][3][3]
+  spinors [n][Lt][Lz][Ly][Lx][4][3]
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libovl.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_ARG, E_STATE, E_HIP, E_OOM, E_NONFINITE, E_BREAKDOWN = -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_MIXED = 0, 1
+FORM_REFERENCE, FORM_FUSED, FORM_BASIS, FORM_TWOPASS = 0, 1, 2, 3
+BENCH_STENCIL64, BENCH_STENCIL32 = 0, 1
+
+# every function declared in include/ovl.h
+EXPORTS = [
+    "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
+    "ovl_set_contour", "ovl_set_nodes", "ovl_set_solver", "ovl_apply_hw", "ovl_apply_sign",
+    "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
+    "ovl_bench_kernel", "ovl_status_string", "ovl_last_error",
+]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("fp32_iterations", ctypes.c_int32),
+        ("n_shifts", ctypes.c_int32),
+        ("n_active_end", ctypes.c_int32),
+        ("max_est_rel_res", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("reserved", ctypes.c_double * 4),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class OvlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libovl.so; raises FileNotFoundError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing: build it with "
+                                "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "ovl_create": ([ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I, P], I),
+        "ovl_destroy": ([P], I),
+        "ovl_set_stream": ([P, P], I),
+        "ovl_set_gauge": ([P, P], I),
+        "ovl_set_masses": ([P, D, D], I),
+        "ovl_set_contour": ([P, I, D, D, D], I),
+        "ovl_set_nodes": ([P, I, ctypes.POINTER(D), ctypes.POINTER(D)], I),
+        "ovl_set_solver": ([P, I, I, D, I, D, D, D], I),
+        "ovl_apply_hw": ([P, P, P, I], I),
+        "ovl_apply_sign": ([P, P, P, I, ctypes.POINTER(Stats)], I),
+        "ovl_apply_dov": ([P, P, P, I, ctypes.POINTER(Stats)], I),
+        "ovl_force": ([P, P, P, I, I, ctypes.POINTER(D), ctypes.POINTER(Stats)], I),
+        "ovl_apply_sign_batched": ([ctypes.POINTER(P), I, ctypes.POINTER(P), ctypes.POINTER(P),
+                                    ctypes.POINTER(I), ctypes.POINTER(Stats)], I),
+        "ovl_get_stats": ([P, ctypes.POINTER(Stats)], I),
+        "ovl_bench_kernel": ([P, I, I, I, ctypes.POINTER(D), ctypes.POINTER(D)], I),
+        "ovl_status_string": ([I], ctypes.c_char_p),
+        "ovl_last_error": ([P], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def status_string(s):
+    return load().ovl_status_string(int(s)).decode()
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(t, name, shape_tail, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128, got {t.dtype}")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must live on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [..., {shape_tail}]")
+
+
+class Context:
+    """One lattice (dims = (Lx, Ly, Lz, Lt)) on one GPU; wraps an ovl_ctx."""
+
+    def __init__(self, dims, bc=(1, 1, 1, -1), device=0):
+        self.lib = load()
+        self.dims = tuple(int(d) for d in dims)
+        self.bc = tuple(int(b) for b in bc)
+        self.device = int(device)
+        self._h = ctypes.c_void_p()
+        d = (ctypes.c_int32 * 4)(*self.dims)
+        b = (ctypes.c_int32 * 4)(*self.bc)
+        rc = self.lib.ovl_create(ctypes.byref(self._h), d, b, self.device,
+                                 _stream_ptr(self.device))
+        if rc != OK:
+            raise OvlError(rc, f"ovl_create failed: {status_string(rc)}")
+        Lx, Ly, Lz, Lt = self.dims
+        self.site_shape = (Lt, Lz, Ly, Lx)
+
+    # -- helpers ------------------------------------------------------------
+    def _rc(self, rc, what):
+        if rc < 0:
+            msg = self.lib.ovl_last_error(self._h).decode()
+            raise OvlError(rc, f"{what}: {status_string(rc)}: {msg}")
+        return rc
+
+    def _sync_stream(self):
+        self.lib.ovl_set_stream(self._h, _stream_ptr(self.device))
+
+    def close(self):
+        if self._h:
+            self.lib.ovl_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setters --------------------------------------------------------------
+    def set_gauge(self, U):
+        _check_tensor(U, "U", (4,) + self.site_shape + (3, 3), self.device)
+        self._sync_stream()
+        self._rc(self.lib.ovl_set_gauge(self._h, ctypes.c_void_p(U.data_ptr())), "ovl_set_gauge")
+
+    def set_masses(self, m0, mq):
+        self._rc(self.lib.ovl_set_masses(self._h, float(m0), float(mq)), "ovl_set_masses")
+
+    def set_contour(self, nq, gamma, rho, alpha):
+        self._rc(self.lib.ovl_set_contour(self._h, int(nq), float(gamma), float(rho), float(alpha)),
+                 "ovl_set_contour")
+
+    def set_nodes(self, z, c):
+        import numpy as np
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.complex128))
+        zr = z.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cr = c.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._rc(self.lib.ovl_set_nodes(self._h, int(len(z)), zr, cr), "ovl_set_nodes")
+
+    def set_solver(self, precision=PREC_FP64, form=FORM_FUSED, tol=1e-12, maxiter=4000,
+                   zseed=1 + 0.05j, switch_res=0.0):
+        self._rc(self.lib.ovl_set_solver(self._h, int(precision), int(form), float(tol),
+                                         int(maxiter), float(complex(zseed).real),
+                                         float(complex(zseed).imag), float(switch_res)),
+                 "ovl_set_solver")
+
+    # -- operators ------------------------------------------------------------
+    def _spinor_in(self, x):
+        if x.dim() == len(self.site_shape) + 2:
+            x = x.unsqueeze(0)
+        _check_tensor(x, "x", self.site_shape + (4, 3), self.device)
+        return x
+
+    def apply_hw(self, x):
+        """H_W x for x of shape [n, Lt, Lz, Ly, Lx, 4, 3] (or without n)."""
+        squeeze = x.dim() == len(self.site_shape) + 2
+        x = self._spinor_in(x)
+        out = torch.empty_like(x)
+        self._sync_stream()
+        self._rc(self.lib.ovl_apply_hw(self._h, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), x.shape[0]), "ovl_apply_hw")
+        return out[0] if squeeze else out
+
+    def _apply(self, fn, x, allow_not_converged):
+        squeeze = x.dim() == len(self.site_shape) + 2
+        x = self._spinor_in(x)
+        out = torch.empty_like(x)
+        st = Stats()
+        self._sync_stream()
+        rc = fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                x.shape[0], ctypes.byref(st))
+        self._rc(rc, fn.__name__)
+        if rc == NOT_CONVERGED and not allow_not_converged:
+            raise OvlError(rc, self.lib.ovl_last_error(self._h).decode())
+        return (out[0] if squeeze else out), st
+
+    def apply_sign(self, x, allow_not_converged=False):
+        """(sum_j c_j (z_j - H_W)^-1 x, Stats)."""
+        return self._apply(self.lib.ovl_apply_sign, x, allow_not_converged)
+
+    def apply_dov(self, x, allow_not_converged=False):
+        """(D_ov(m_q) x, Stats)."""
+        return self._apply(self.lib.ovl_apply_dov, x, allow_not_converged)
+
+    def bench_kernel(self, which, nrhs, reps):
+        ms, nb = ctypes.c_double(), ctypes.c_double()
+        self._sync_stream()
+        self._rc(self.lib.ovl_bench_kernel(self._h, int(which), int(nrhs), int(reps),
+                                           ctypes.byref(ms), ctypes.byref(nb)), "ovl_bench_kernel")
+        return ms.value, nb.value
+
+    def stats(self):
+        st = Stats()
+        self._rc(self.lib.ovl_get_stats(self._h, ctypes.byref(st)), "ovl_get_stats")
+        return st

@@ -1,0 +1,210 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import freefield as ff
+from oracle.contour import nodes, scalar_filter
+from oracle.sign import overlap
+from tests.gpu_util import CIRCLE, gauge, make_ctx, oracle_H, oracle_sign, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(module):
+    import torch
+    from paper_2204_01583_amd import ovl
+    ovl.load()                      # fails loudly if the library was not built
+    assert torch.cuda.is_available()
+
+
+# ---------------------------------------------------------------- stencil
+@pytest.mark.parametrize("dims,r", [((4, 4, 4, 4), 0.3), ((8, 8, 8, 8), 0.3),
+                                    ((3, 5, 4, 6), 0.4), ((2, 2, 2, 2), 0.2)])
+def test_hw_matches_oracle(dims, r):
+    U = gauge(dims, r, 0)
+    ctx = make_ctx(dims, U)
+    b = si.gaussian_sources(dims, 3)
+    out = ctx.apply_hw(to_dev(b)).cpu().numpy()
+    H = oracle_H(dims, r, 0, 1.4)
+    for i in range(3):
+        ref = H @ b[i].ravel()
+        err = float(np.abs(out[i].ravel() - ref).max() / np.abs(ref).max())
+        assert err < 1e-14, err
+    ctx.close()
+
+
+def test_hw_periodic_time_and_other_mass():
+    dims = (4, 4, 2, 6)
+    U = gauge(dims, 0.3, 2)
+    ctx = make_ctx(dims, U, m0=1.0, bc=(1, -1, 1, 1))
+    b = si.gaussian_sources(dims, 1)
+    out = ctx.apply_hw(to_dev(b)).cpu().numpy()
+    from oracle.wilson import hermitian_wilson
+    ref = hermitian_wilson(U, 1.0, bc=(1, -1, 1, 1)) @ b[0].ravel()
+    assert relerr(out[0], ref) < 1e-14
+    ctx.close()
+
+
+def test_hw_free_plane_wave_16():
+    dims = (16, 16, 16, 16)
+    ctx = make_ctx(dims, si.unit_gauge(dims))
+    rng = np.random.default_rng(3)
+    for n in [(0, 0, 0, 0), (3, 7, 11, 5), (15, 1, 8, 12)]:
+        chi = rng.normal(size=4) + 1j * rng.normal(size=4)
+        col = rng.normal(size=3) + 1j * rng.normal(size=3)
+        pw = ff.plane_wave(dims, n, chi, col)
+        p = [np.array(2 * np.pi * (n[m] + (0.5 if m == 3 else 0)) / 16) for m in range(4)]
+        ref = ff.plane_wave(dims, n, ff.h_of_p(p, 1.4) @ chi, col)
+        out = ctx.apply_hw(to_dev(pw)).cpu().numpy()
+        # the reference's own phases 2 pi n x / L carry ~1e-14 relative rounding
+        err = float(np.abs(out - ref).max() / np.abs(ref).max())
+        assert err < 5e-14, err
+    ctx.close()
+
+
+# ---------------------------------------------------------------- sign
+CFG0 = dict(dims=(4, 4, 4, 4), r=0.3, seed=0, m0=1.4, mq=0.1, nq=32)
+
+
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_sign_4x4_fp64_all_forms(form):
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    ctx = make_ctx(c["dims"], U, c["m0"], c["mq"], c["nq"], form=form)
+    b = si.gaussian_sources(c["dims"], 1)[0]
+    s, st = ctx.apply_sign(to_dev(b))
+    ref = oracle_sign(c["dims"], c["r"], c["seed"], c["m0"], c["nq"], CIRCLE, 1000)
+    err = relerr(s.cpu().numpy(), ref)
+    print(f"form {form}: err {err:.2e} iters {st.iterations}")
+    assert err < 1e-11
+    assert st.n_active_end == 0 and st.max_est_rel_res <= 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_sign_4x4_mixed(form):
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    ctx = make_ctx(c["dims"], U, c["m0"], c["mq"], c["nq"], precision=1, form=form)
+    b = si.gaussian_sources(c["dims"], 1)[0]
+    s, st = ctx.apply_sign(to_dev(b))
+    ref = oracle_sign(c["dims"], c["r"], c["seed"], c["m0"], c["nq"], CIRCLE, 1000)
+    err = relerr(s.cpu().numpy(), ref)
+    print(f"mixed form {form}: err {err:.2e} iters {st.iterations} fp32 {st.fp32_iterations}")
+    assert st.fp32_iterations > 0
+    assert err < 1e-10
+    ctx.close()
+
+
+def test_dov_4x4_multi_rhs():
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    ctx = make_ctx(c["dims"], U, c["m0"], c["mq"], c["nq"], form=1)
+    b = si.gaussian_sources(c["dims"], 2)
+    d, st = ctx.apply_dov(to_dev(b))
+    d = d.cpu().numpy()
+    for i in range(2):
+        s_ref = oracle_sign(c["dims"], c["r"], c["seed"], c["m0"], c["nq"], CIRCLE, 1000 + i)
+        ref = overlap(b[i].ravel(), s_ref, c["mq"])
+        assert relerr(d[i], ref) < 1e-11
+    ctx.close()
+
+
+REF8 = os.path.join(os.path.dirname(__file__), "golden",
+                    "sign_8x8x8x8_r0.3_m1.4_nq64_circle_src1000.npy")
+
+
+@pytest.mark.parametrize("precision,form,tol", [(0, 1, 1e-11), (0, 2, 1e-11), (1, 2, 1e-10)])
+def test_sign_8x8(precision, form, tol):
+    """8^4, 2 x 64 nodes, against the stored oracle result (make_oracle_refs.py)."""
+    dims, nq = (8, 8, 8, 8), 64
+    U = gauge(dims, 0.3, 0)
+    ctx = make_ctx(dims, U, 1.4, 0.05, nq, precision=precision, form=form)
+    b = si.gaussian_sources(dims, 1)[0]
+    s, st = ctx.apply_sign(to_dev(b))
+    ref = np.load(REF8)
+    err = relerr(s.cpu().numpy(), ref)
+    print(f"8^4 prec {precision} form {form}: err {err:.2e} iters {st.iterations} "
+          f"fp32 {st.fp32_iterations} {st.seconds:.3f}s")
+    assert err < tol
+    ctx.close()
+
+
+def test_sign_free_field_16_fft():
+    """16^4 unit links: against the momentum-space oracle at full size."""
+    dims, nq = (16, 16, 16, 16), 32
+    ctx = make_ctx(dims, si.unit_gauge(dims), 1.4, 0.1, nq, form=2)
+    b = si.gaussian_sources(dims, 1)[0]
+    s, st = ctx.apply_sign(to_dev(b))
+    z, c = nodes(nq, *CIRCLE)
+    ref = ff.apply_function(b, dims, 1.4, lambda l: scalar_filter(l, z, c))
+    err = relerr(s.cpu().numpy(), ref)
+    print(f"16^4 free err {err:.2e} iters {st.iterations}")
+    assert err < 1e-11
+    ctx.close()
+
+
+# ---------------------------------------------------------------- errors
+def test_error_paths():
+    from paper_2204_01583_amd import ovl
+    dims = (4, 4, 4, 4)
+    U = gauge(dims, 0.3, 0)
+    b = to_dev(si.gaussian_sources(dims, 1))
+    ctx = ovl.Context(dims)
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.apply_hw(b)
+    assert e.value.status == ovl.E_STATE
+    ctx.set_gauge(to_dev(U))
+    ctx.set_masses(1.4, 0.1)
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.apply_sign(b)
+    assert e.value.status == ovl.E_STATE
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.set_contour(33, *CIRCLE)
+    assert e.value.status == ovl.E_ARG
+    with pytest.raises(ovl.OvlError):
+        ctx.set_masses(4.5, 0.0)
+    with pytest.raises(ovl.OvlError):
+        ctx.set_nodes([1.0 + 0j], [1.0 + 0j])       # node on the real axis
+    ctx.set_contour(16, *CIRCLE)
+    ctx.set_solver(0, 1, tol=1e-12, maxiter=1)
+    s, st = ctx.apply_sign(b, allow_not_converged=True)
+    assert st.iterations == 1 and st.n_active_end > 0
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.apply_sign(b)
+    assert e.value.status == ovl.NOT_CONVERGED
+    ctx.set_solver(0, 1, tol=1e-12, maxiter=500)
+    bad = b.clone()
+    bad[0, 1, 2, 3, 0, 1, 2] = float("nan")
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.apply_sign(bad)
+    assert e.value.status == ovl.E_NONFINITE
+    # aliasing in/out through the raw ABI
+    import ctypes
+    rc = ctx.lib.ovl_apply_hw(ctx._h, ctypes.c_void_p(b.data_ptr()),
+                              ctypes.c_void_p(b.data_ptr()), 1)
+    assert rc == ovl.E_ARG
+    # host pointer rejected
+    hb = b.cpu()
+    rc = ctx.lib.ovl_apply_hw(ctx._h, ctypes.c_void_p(hb.data_ptr()),
+                              ctypes.c_void_p(b.data_ptr()), 1)
+    assert rc == ovl.E_ARG
+    # zero source gives zero
+    z0 = b * 0
+    s, st = ctx.apply_sign(z0)
+    assert float(s.abs().max()) == 0.0
+    ctx.close()
+
+
+def test_deterministic():
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    ctx = make_ctx(c["dims"], U, c["m0"], c["mq"], c["nq"], form=2)
+    b = to_dev(si.gaussian_sources(c["dims"], 2))
+    s1, _ = ctx.apply_sign(b)
+    s2, _ = ctx.apply_sign(b)
+    assert bool((s1 == s2).all())
+    ctx.close()
