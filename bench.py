@@ -1,0 +1,238 @@
+"""Benchmark of the contour-integral sign function / overlap operator on one MI355X.
+
+Workload (one "step"): D_ov(m_q) applied to 4 complex Gaussian sources on a
+16^4 lattice with a seeded SU(3) field (roughness 0.3, seed 0), m0 = 1.4,
+m_q = 0.1, a circle contour with 128 nodes per contour (256 shifted systems),
+seed shift 1 + 0.05i, shifted residuals to 1e-12 * ||b||, mixed precision
+(FP64, then FP32 vectors once every shifted residual is below 1e-4 ||b||),
+stored seed-residual basis form.  The step runs the whole path: layout
+packing, the shifted solver (stencil, reductions, shift scalars, vector
+updates), the quadrature sum and the D_ov assembly.  Inputs are resident in
+HBM before the timed region.
+
+Prints ONE JSON line.  `value` is sgn(H_W)b applications per second
+(sources x steps / seconds).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+DIMS = (16, 16, 16, 16)
+NSRC = 4
+NQ = 128
+CIRCLE = (1.3, 1.2999, 1.0)
+M0, MQ = 1.4, 0.1
+TOL = 1e-12
+SWITCH = 1e-4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(torch, ovl):
+    import numpy as np
+    import seeded_inputs as si
+    U = si.gauge_field(DIMS, 0.3, seed=0)
+    B = si.gaussian_sources(DIMS, NSRC, first_seed=1000)
+    dev = torch.device("cuda:0")
+    Ud = torch.from_numpy(U).to(dev)
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+    ctx = ovl.Context(DIMS, device=0)
+    ctx.set_gauge(Ud)
+    ctx.set_masses(M0, MQ)
+    ctx.set_contour(NQ, *CIRCLE)
+    return ctx, Ud, Bd, U, B
+
+
+def relerrs(a, b):
+    import torch
+    d = (a - b).reshape(a.shape[0], -1)
+    r = b.reshape(b.shape[0], -1)
+    return [float(torch.linalg.vector_norm(d[i]) / torch.linalg.vector_norm(r[i]))
+            for i in range(a.shape[0])]
+
+
+def roofline_from_profile(prof):
+    """Dominant kernel class (largest summed time) -> roofline dict."""
+    kern = {k: v for k, v in prof.items() if k != "scalars" and v[1] > 0}
+    name = max(kern, key=lambda k: kern[k][0])
+    ms, n, nb = kern[name]
+    avg_ms = ms / n
+    gbs = (nb / n) / (avg_ms * 1e-3) / 1e9
+    return name, {
+        "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": name, "avg_launch_ms": round(avg_ms, 5), "launches": n,
+        "algorithmic_bytes_per_launch": nb / n,
+    }
+
+
+def cpu_baseline(U, B, nsample):
+    """The FP64 oracle (independent GMRES solve per node) on a stratified sample
+    of the 256 shifted systems of source 0, one node per host core."""
+    import numpy as np
+    from oracle.contour import nodes
+    from oracle.sign import sign_by_solves
+    from oracle.wilson import hermitian_wilson
+    cores = min(16, len(os.sched_getaffinity(0)))
+    t0 = time.time()
+    H = hermitian_wilson(U, M0)
+    t_build = time.time() - t0
+    z, c = nodes(NQ, *CIRCLE)
+    step = len(z) // nsample
+    pick = np.arange(step // 2, len(z), step)[:nsample]
+    t0 = time.time()
+    sign_by_solves(H, B[0].ravel(), z[pick], c[pick], method="gmres", rtol=1e-14,
+                   processes=min(cores, nsample))
+    wall = time.time() - t0
+    used = min(cores, nsample)
+    # sample throughput extrapolated linearly to the 256 systems of one application
+    per_apply_s = wall * len(z) / nsample
+    return {
+        "value": 1.0 / per_apply_s, "unit": "sgn(H_W)b applies/s", "cores": used,
+        "kind": "oracle",
+        "sample": (f"{nsample} of the {len(z)} shifted systems of source 0 (every {step}th node), "
+                   f"each solved on its own by GMRES(100) to true residual 1e-14 on one core, "
+                   f"{used} in parallel; {wall:.1f}s wall, extrapolated linearly to all "
+                   f"{len(z)} systems; H_W CSR build ({t_build:.1f}s) not included"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only-steps", action="store_true",
+                    help="only the warm-up and timed steps (for profiler runs)")
+    ap.add_argument("--cpu-nodes", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path shards over contour nodes with one "
+              "final reduction, which this build does not run; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2204_01583_amd import ovl
+    ovl.load()
+    ctx, Ud, Bd, U, B = setup(torch, ovl)
+    ctx.set_solver(ovl.PREC_MIXED, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=SWITCH)
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        out, st = ctx.apply_dov(Bd)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, st = ctx.apply_dov(Bd)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = NSRC * args.steps / dt
+    log(f"{ms_per_step:.2f} ms/step, {value:.2f} applies/s, iters {st.iterations} "
+        f"(fp32 {st.fp32_iterations})")
+
+    rec = {
+        "metric": "sgn(H_W)b applies/s + stencil HBM GB/s, 16^4, mixed vs FP64 @1e-10",
+        "value": round(value, 3),
+        "unit": "sgn(H_W)b applies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "D_ov(m_q) on 4 Gaussian sources, 16^4 SU(3) field (roughness 0.3, seed 0), "
+                        "m0=1.4, m_q=0.1, circle contour 2x128 nodes, tol 1e-12, "
+                        "mixed FP64->FP32 (switch 1e-4), stored-basis shifted solver",
+            "lattice": list(DIMS), "sources": NSRC, "shifts": 2 * NQ,
+            "iterations": st.iterations, "fp32_iterations": st.fp32_iterations,
+        },
+    }
+    if args.only_steps:
+        print(json.dumps(rec), flush=True)
+        return
+
+    # ---- dominant kernel, timed with HIP events on the library's stream
+    ctx.set_profiling(True)
+    ctx.apply_dov(Bd)
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    name, roof = roofline_from_profile(prof)
+    rec["roofline"] = roof
+    rec["kernel_profile"] = {k: {"ms": round(v[0], 3), "launches": v[1],
+                                 "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+                             for k, v in prof.items() if v[1] > 0}
+    log(f"dominant kernel {name}: {roof['achieved']} GB/s ({roof['frac']:.2%})")
+
+    # ---- accuracy of the mixed path against the FP64 path on the same inputs
+    s_mix, _ = ctx.apply_sign(Bd)
+    ctx.set_solver(ovl.PREC_FP64, ovl.FORM_BASIS, tol=TOL, maxiter=3000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s64, st64 = ctx.apply_sign(Bd)
+    torch.cuda.synchronize()
+    t_basis64 = time.perf_counter() - t0
+    err = relerrs(s_mix, s64)
+    rec["accuracy"] = {"mixed_vs_fp64_rel_err": err, "max": max(err), "target": 1e-10}
+    log(f"mixed vs fp64 err {max(err):.2e}")
+
+    # ---- the other solver forms (one application each), FP64 and mixed
+    forms = {"fp64_basis": t_basis64}
+    for label, prec, form in [("fp64_fused", ovl.PREC_FP64, ovl.FORM_FUSED),
+                              ("fp64_reference", ovl.PREC_FP64, ovl.FORM_REFERENCE),
+                              ("mixed_fused", ovl.PREC_MIXED, ovl.FORM_FUSED)]:
+        ctx.set_solver(prec, form, tol=TOL, maxiter=3000, switch_res=SWITCH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sf, stf = ctx.apply_sign(Bd)
+        torch.cuda.synchronize()
+        forms[label] = time.perf_counter() - t0
+        e = max(relerrs(sf, s64))
+        log(f"{label}: {forms[label]:.3f}s err vs fp64 basis {e:.2e}")
+        forms[label + "_err_vs_fp64_basis"] = e
+        del sf
+    t_mixed = ms_per_step * 1e-3
+    rec["forms"] = {
+        "seconds_per_application_of_4_sources": {k: round(v, 4) for k, v in forms.items()
+                                                 if not k.endswith("err_vs_fp64_basis")},
+        "err_vs_fp64_basis": {k[:-len("_err_vs_fp64_basis")]: v for k, v in forms.items()
+                              if k.endswith("err_vs_fp64_basis")},
+        "mixed_basis_speedup_vs_fp64_basis": round(forms["fp64_basis"] / t_mixed, 3),
+        "mixed_basis_speedup_vs_fp64_fused": round(forms["fp64_fused"] / t_mixed, 3),
+        "mixed_basis_speedup_vs_fp64_reference": round(forms["fp64_reference"] / t_mixed, 3),
+    }
+
+    # ---- the stencil on a batch far larger than the 256 MB last-level cache
+    sten = {}
+    for label, which, n in [("fp64_n1024", ovl.BENCH_STENCIL64, 1024),
+                            ("fp32_n1024", ovl.BENCH_STENCIL32, 1024),
+                            ("fp64_n4", ovl.BENCH_STENCIL64, 4), ("fp32_n4", ovl.BENCH_STENCIL32, 4)]:
+        ms, nb = ctx.bench_kernel(which, n, 5 if n > 64 else 50)
+        sten[label] = {"avg_ms": round(ms, 4), "GB/s": round(nb / (ms * 1e-3) / 1e9, 1),
+                       "frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "algorithmic_bytes": nb}
+        log(f"stencil {label}: {sten[label]['GB/s']} GB/s")
+    rec["stencil"] = sten
+    ctx.close()
+    del Ud, Bd
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle sample)")
+        rec["cpu_baseline"] = cpu_baseline(U, B, args.cpu_nodes)
+        log(f"cpu baseline {rec['cpu_baseline']['value']:.3e} applies/s")
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

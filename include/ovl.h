@@ -161,6 +161,21 @@ int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
 int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
                      double* avg_ms, double* bytes);
 
+/* Per-kernel timing of the solver's own launches, for benchmarks.  While
+ * enabled, every launch of the classes below is bracketed by HIP events on
+ * the context's stream; ovl_get_profile returns the summed duration, the
+ * number of launches and the summed algorithmic bytes since the last
+ * ovl_set_profiling(ctx, 1).  kclass:
+ *   0 stencil FP64 (q = z_s p - H p with <r,q>)   1 the same in FP32
+ *   2 vector updates FP64 (r and p updates)        3 the same in FP32
+ *   4 shift sweep FP64                             5 shift sweep FP32
+ *   6 basis sum s = sum h_k r_k                    7 scalar kernels
+ * Algorithmic bytes count every array element the kernel must read or write
+ * once (links once per launch, neighbour spinors once). */
+int ovl_set_profiling(ovl_ctx* ctx, int32_t enable);
+int ovl_get_profile(const ovl_ctx* ctx, int32_t kclass, double* total_ms, int64_t* launches,
+                    double* bytes);
+
 const char* ovl_status_string(int status);
 const char* ovl_last_error(const ovl_ctx* ctx);
 

@@ -28,9 +28,12 @@ def _solve_one(H, zj, b, method, rtol):
         y = spla.splu(A).solve(b)
     elif method == "gmres":
         # unrestarted GMRES; the stopping test is re-checked on the true residual
+        # GMRES(m), m = min(n, 100): scipy preallocates the m-vector basis, and
+        # these shifted systems converge without stagnation under restarts.
         # The Arnoldi residual estimate can stall a little above rtol near
         # machine precision, so the acceptance test is the true residual below.
-        y, info = spla.gmres(A.tocsr(), b, rtol=rtol, atol=0.0, restart=n, maxiter=1)
+        m = min(n, 100)
+        y, info = spla.gmres(A.tocsr(), b, rtol=rtol, atol=0.0, restart=m, maxiter=200)
     else:
         raise ValueError(method)
     res = np.linalg.norm(b - A @ y) / np.linalg.norm(b)

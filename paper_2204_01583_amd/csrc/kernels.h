@@ -19,62 +19,37 @@ void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, const Geom
 void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t s);
 
 // ---- Wilson stencil --------------------------------------------------------
-// out = H_W in                                      (mode 0)
-// out = zs*in - H_W in, partial[src][blk] = <r,out> (mode 1, per-block dot)
-// `done` (mode 1, may be null) skips converged sources.
+// out = H_W in                                               (mode 0)
+// out = zs*in - H_W in, partial[src][blk] = <r,out> (mode 1); sources that are
+// not live at iteration k (see kernels.hip) are skipped.
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                    double kappa, double2 zs, const C2<R>* r, double2* partial,
-                   const SrcState* stt, int nrhs, hipStream_t s);
+                   const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s);
 int wilson_blocks(const Geom& g);
 
-// ---- Krylov scalars and vector updates --------------------------------------
-int elem_blocks(int64_t n12);
-// alpha_k and shifted pi_{k+1}, alpha^j (one block per source)
-void launch_alpha(SrcState* st, const double2* partial, int nblk, const double2* dz,
-                  const double2* pi, const double2* pi_prev, double2* pi_next, double2* aj,
-                  const int* active, int J, int nsrc, hipStream_t s);
-// r_out = r_in - alpha q ; partial[src][blk] = ||r_out||^2
+// ---- seed iteration k, kernels K2 and K3 (vector grids of nbe blocks/source) --
+int vec_blocks(int64_t n12, int nslices);
+// alpha_k, pi_{k+1}^j, alpha^j; r_out = r_in - alpha q; part_e = ||r_out||^2 partials
 template <typename R>
-void launch_update_r(const C2<R>* rin, C2<R>* rout, const C2<R>* q, const SrcState* st,
-                     double* partial, int64_t n12, int64_t src_stride_in,
-                     int64_t src_stride_out, int nsrc, hipStream_t s);
-// beta, beta^j, residual estimates, deactivation, sweep list (one block per source).
-// form: 0 reference (list coefficient alpha^j), 1 fused (c_j alpha^j),
-// 2 basis (records history, list coefficient c_j alpha^j).
-struct BetaArgs {
-    SrcState* st; const double* partial; int nblk;
-    const double2* c; double2* pi; double2* pi_prev; const double2* pi_next; const double2* aj;
-    int* active; int J;
-    int* lst_j; double2* lst_a; double2* lst_ipi; double2* lst_b;
-    double tol;
-    // history (basis forms), may be null: [src][maxk+1][J]
-    double2* h_a; double2* h_b; double2* h_pi; int maxk;
-};
-void launch_beta(const BetaArgs& a, int nsrc, hipStream_t s);
-// fused sweep: s += sum_l lst_a[l] p_{j_l};  p_{j_l} = r*lst_ipi + lst_b p_{j_l};  p = r + beta p
+void launch_update_r(const C2<R>* rin, C2<R>* rout, const C2<R>* q, SrcState* st,
+                     const double2* part_w, int nsb, double* part_e, int nbe, int64_t n12,
+                     const ShiftDev& sh, int k, hipStream_t s);
+// beta_k, beta^j, residuals, deactivation (+ history); p = r + beta p
 template <typename R>
-void launch_sweep_fused(const C2<R>* r, C2<R>* p, C2<R>* pj, double2* sacc, const double2* b0,
-                        const SrcState* st, const int* lst_j, const double2* lst_a,
-                        const double2* lst_ipi, const double2* lst_b, int J, int64_t n12,
-                        int nsrc, bool first, hipStream_t s);
-// reference sweep: x_j += alpha^j p_j (x_j FP64); p_j update; seed p update
+void launch_update_p(const C2<R>* r, C2<R>* p, SrcState* st, const double* part_e, int nbe,
+                     int64_t n12, const ShiftDev& sh, int k, hipStream_t s);
+// the same scalars, then the fused (s += c_j alpha^j p_j) or reference
+// (x_j += alpha^j p_j) shift sweep with p_j and p updates
 template <typename R>
-void launch_sweep_ref(const C2<R>* r, C2<R>* p, C2<R>* pj, double2* xj, const double2* b0,
-                      const SrcState* st, const int* lst_j, const double2* lst_a,
-                      const double2* lst_ipi, const double2* lst_b, int J, int64_t n12,
-                      int nsrc, bool first, hipStream_t s);
+void launch_sweep(bool ref, const C2<R>* r, C2<R>* p, C2<R>* pj, double2* acc,
+                  const double2* b0, SrcState* st, const double* part_e, int nbe, int64_t n12,
+                  const ShiftDev& sh, int k, hipStream_t s);
 void launch_sum_ref(const double2* xj, const double2* c, double2* sacc, int J, int64_t n12,
                     int nsrc, hipStream_t s);
-// p = r + beta p
-template <typename R>
-void launch_update_p(const C2<R>* r, C2<R>* p, const SrcState* st, int64_t n12,
-                     int64_t src_stride_r, int nsrc, hipStream_t s);
-
-// ||b||^2 and the initial solver state (r = p = b, pi = 1, all shifts active)
-void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t n12, double2* pi,
-                       double2* pi_prev, int* active, int J, double2* h_pi, int maxk, int nsrc,
-                       hipStream_t s);
+// ||b||^2 and the iteration-0 state
+void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t n12,
+                       const ShiftDev& sh, hipStream_t s);
 
 // ---- basis forms ------------------------------------------------------------
 // h[src][i] = sum_j c_j P_i^j / pi_i^j with P_i = alpha_i^j + beta_i^j P_{i+1}

@@ -166,83 +166,106 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 //   (1 -+ gamma_mu) psi = [ h ; -+ A^dag h ],  h = psi_up -+ A_mu d,
 // so each hop moves a 2-spin x 3-colour half-spinor through the link.
 
-// h = psi_up - A d (FWD) or psi_up + A d (backward), colour c
-template <typename R, int MU, bool FWD>
-__device__ __forceinline__ void project(cx<R> p0, cx<R> p1, cx<R> p2, cx<R> p3, cx<R>& h0,
-                                        cx<R>& h1) {
+// h = psi_up - A d (forward, sg = -1) or psi_up + A d (backward, sg = +1)
+template <typename R>
+__device__ __forceinline__ void project(int mu, R sg, cx<R> p0, cx<R> p1, cx<R> p2, cx<R> p3,
+                                        cx<R>& h0, cx<R>& h1) {
     cx<R> a0, a1;  // A_mu (p2, p3)
-    if constexpr (MU == 0) { a0 = tmi(p3); a1 = tmi(p2); }
-    else if constexpr (MU == 1) { a0 = -p3; a1 = p2; }
-    else if constexpr (MU == 2) { a0 = tmi(p2); a1 = ti(p3); }
-    else { a0 = p2; a1 = p3; }
-    if constexpr (FWD) { h0 = p0 - a0; h1 = p1 - a1; }
-    else { h0 = p0 + a0; h1 = p1 + a1; }
+    switch (mu) {
+        case 0: a0 = tmi(p3); a1 = tmi(p2); break;
+        case 1: a0 = -p3; a1 = p2; break;
+        case 2: a0 = tmi(p2); a1 = ti(p3); break;
+        default: a0 = p2; a1 = p3; break;
+    }
+    h0 = p0 + sg * a0;
+    h1 = p1 + sg * a1;
 }
 
-// acc_up += u ; acc_dn -+= A_mu^dag u
-template <typename R, int MU, bool FWD>
-__device__ __forceinline__ void reconstruct(cx<R> (&acc)[4][3], const cx<R> (&u)[2][3]) {
+// acc_up += u ; acc_dn += sg * A_mu^dag u
+template <typename R>
+__device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
+                                            const cx<R> (&u)[2][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const cx<R> u0 = u[0][c], u1 = u[1][c];
         cx<R> b0, b1;  // A^dag (u0, u1)
-        if constexpr (MU == 0) { b0 = ti(u1); b1 = ti(u0); }
-        else if constexpr (MU == 1) { b0 = u1; b1 = -u0; }
-        else if constexpr (MU == 2) { b0 = ti(u0); b1 = tmi(u1); }
-        else { b0 = u0; b1 = u1; }
+        switch (mu) {
+            case 0: b0 = ti(u1); b1 = ti(u0); break;
+            case 1: b0 = u1; b1 = -u0; break;
+            case 2: b0 = ti(u0); b1 = tmi(u1); break;
+            default: b0 = u0; b1 = u1; break;
+        }
         acc[0][c] = acc[0][c] + u0;
         acc[1][c] = acc[1][c] + u1;
-        if constexpr (FWD) { acc[2][c] = acc[2][c] - b0; acc[3][c] = acc[3][c] - b1; }
-        else { acc[2][c] = acc[2][c] + b0; acc[3][c] = acc[3][c] + b1; }
+        acc[2][c] = acc[2][c] + sg * b0;
+        acc[3][c] = acc[3][c] + sg * b1;
     }
 }
 
-template <typename R, int MU, bool FWD>
-__device__ __forceinline__ void hop(cx<R> (&acc)[4][3], const C2<R>* __restrict__ psi,
-                                    const C2<R>* __restrict__ U, int64_t V, int64_t nb,
-                                    int64_t lsite) {
+// One hop: project the neighbour spinor to a half-spinor, move it through
+// the link (U_mu(x) forward, U_mu(x-mu)^dag backward), reconstruct into acc.
+// Per-lane offsets are 32-bit element indices from uniform base pointers.
+template <typename R>
+__device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[4][3],
+                                    const C2<R>* __restrict__ psi, const C2<R>* __restrict__ Um,
+                                    uint32_t V, uint32_t nb, uint32_t lsite) {
+    const R sg = fwd ? R(-1) : R(1);
     cx<R> h[2][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const cx<R> p0 = ld<R>(psi, (0 + c) * V + nb), p1 = ld<R>(psi, (3 + c) * V + nb);
-        const cx<R> p2 = ld<R>(psi, (6 + c) * V + nb), p3 = ld<R>(psi, (9 + c) * V + nb);
-        project<R, MU, FWD>(p0, p1, p2, p3, h[0][c], h[1][c]);
+        const cx<R> p0 = ld<R>(psi, (uint32_t)(0 + c) * V + nb), p1 = ld<R>(psi, (uint32_t)(3 + c) * V + nb);
+        const cx<R> p2 = ld<R>(psi, (uint32_t)(6 + c) * V + nb), p3 = ld<R>(psi, (uint32_t)(9 + c) * V + nb);
+        project<R>(mu, sg, p0, p1, p2, p3, h[0][c], h[1][c]);
     }
-    const C2<R>* Um = U + (int64_t)MU * 9 * V + lsite;
+    // element (a,b) of the hop matrix: U[a][b] forward, conj(U[b][a]) backward
+    const R ci = fwd ? R(1) : R(-1);
     cx<R> u[2][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         u[0][a] = mk<R>(0, 0);
         u[1][a] = mk<R>(0, 0);
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            if constexpr (FWD) {  // U_mu(x) h
-                const cx<R> l = ld<R>(Um, (int64_t)(3 * a + b) * V);
-                fma_(u[0][a], l, h[0][b]);
-                fma_(u[1][a], l, h[1][b]);
-            } else {  // U_mu(x-mu)^dag h : element (a,b) = conj(U[b][a])
-                const cx<R> l = ld<R>(Um, (int64_t)(3 * b + a) * V);
-                fmac_(u[0][a], l, h[0][b]);
-                fmac_(u[1][a], l, h[1][b]);
-            }
+            const uint32_t e = fwd ? (uint32_t)(3 * a + b) : (uint32_t)(3 * b + a);
+            cx<R> l = ld<R>(Um, e * V + lsite);
+            l.im *= ci;
+            fma_(u[0][a], l, h[0][b]);
+            fma_(u[1][a], l, h[1][b]);
         }
     }
-    reconstruct<R, MU, FWD>(acc, u);
+    reconstruct<R>(mu, sg, acc, u);
 }
 
-template <typename R, int MU>
-__device__ __forceinline__ void hop_pair(cx<R> (&acc)[4][3], const C2<R>* __restrict__ psi,
-                                         const C2<R>* __restrict__ U, const Geom& g,
-                                         int64_t s, int coord) {
-    const int64_t sd = g.stride[MU];
-    const int L = g.L[MU];
-    const int64_t fw = (coord == L - 1) ? s - (int64_t)(L - 1) * sd : s + sd;
-    const int64_t bw = (coord == 0) ? s + (int64_t)(L - 1) * sd : s - sd;
-    hop<R, MU, true>(acc, psi, U, g.V, fw, s);
-    hop<R, MU, false>(acc, psi, U, g.V, bw, bw);
+// acc = sum over the 8 hops.  The hop loop is kept rolled so that one hop's
+// loads are live at a time (unrolled, the scheduler hoists every neighbour's
+// loads and the kernel spills).
+template <typename R>
+__device__ __forceinline__ void dslash_site(cx<R> (&acc)[4][3], const C2<R>* __restrict__ psi,
+                                            const C2<R>* __restrict__ U, const Geom& g,
+                                            uint32_t s, const int (&coord)[4]) {
+    const uint32_t V = (uint32_t)g.V;
+#pragma unroll 1
+    for (int d = 0; d < 8; ++d) {
+        const int mu = d >> 1;
+        const bool fwd = (d & 1) == 0;
+        const uint32_t sd = (uint32_t)g.stride[mu];
+        const int L = g.L[mu];
+        const int cm = coord[mu];
+        uint32_t nb;
+        if (fwd) nb = (cm == L - 1) ? s - (uint32_t)(L - 1) * sd : s + sd;
+        else nb = (cm == 0) ? s + (uint32_t)(L - 1) * sd : s - sd;
+        hop<R>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb);
+    }
+}
+
+__device__ __forceinline__ bool src_live(const SrcState& S, const ShiftDev& sh, int n, int k);
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap the linear block id so that XCD k works on one contiguous range of
+// (rhs, site tile): the z and t neighbours of a tile then sit in the same L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+    const unsigned per = nb / 8u;
+    return (b < per * 8u) ? (b % 8u) * per + b / 8u : b;
 }
 
 template <typename R, int MODE>
@@ -252,50 +275,53 @@ __global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
                                                    double zsr, double zsi,
                                                    const C2<R>* __restrict__ rdot,
                                                    double2* __restrict__ partial,
-                                                   const SrcState* __restrict__ stt) {
-    const int n = blockIdx.y;
+                                                   const SrcState* __restrict__ stt,
+                                                   ShiftDev sh, int k, int nsb, int nrhs) {
+    // rhs fastest: the blocks of one site tile (all rhs) run back to back on
+    // one XCD and share its links through L2
+    const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
+    const int n = (int)uniform(tile % (unsigned)nrhs);
+    const int sb = (int)uniform(tile / (unsigned)nrhs);
     if constexpr (MODE == 1) {
-        if (stt != nullptr && stt[n].done) return;
+        if (!src_live(stt[n], sh, n, k)) return;
     }
-    const int64_t V = g.V;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t V = (uint32_t)g.V;
+    const uint32_t s = (uint32_t)sb * kBlock + threadIdx.x;
     const bool valid = s < V;
     double dre = 0.0, dim = 0.0;
     if (valid) {
-        const C2<R>* psi = in + (int64_t)n * 12 * V;
-        int64_t rem = s;
-        const int x = (int)(rem % g.L[0]); rem /= g.L[0];
-        const int y = (int)(rem % g.L[1]); rem /= g.L[1];
-        const int z = (int)(rem % g.L[2]);
-        const int t = (int)(rem / g.L[2]);
+        const C2<R>* psi = in + (size_t)n * 12 * V;
+        uint32_t rem = s;
+        int coord[4];
+        coord[0] = (int)(rem % (uint32_t)g.L[0]); rem /= (uint32_t)g.L[0];
+        coord[1] = (int)(rem % (uint32_t)g.L[1]); rem /= (uint32_t)g.L[1];
+        coord[2] = (int)(rem % (uint32_t)g.L[2]);
+        coord[3] = (int)(rem / (uint32_t)g.L[2]);
         cx<R> acc[4][3];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[a][c] = mk<R>(0, 0);
-        hop_pair<R, 0>(acc, psi, U, g, s, x);
-        hop_pair<R, 1>(acc, psi, U, g, s, y);
-        hop_pair<R, 2>(acc, psi, U, g, s, z);
-        hop_pair<R, 3>(acc, psi, U, g, s, t);
-        C2<R>* o = out + (int64_t)n * 12 * V + s;
-        const C2<R>* rd = (MODE == 1) ? rdot + (int64_t)n * 12 * V + s : nullptr;
+        dslash_site<R>(acc, psi, U, g, s, coord);
+        C2<R>* o = out + (size_t)n * 12 * V;
+        const C2<R>* rd = (MODE == 1) ? rdot + (size_t)n * 12 * V : nullptr;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int comp = 3 * a + c;
-                const cx<R> p = ld<R>(psi + s, (int64_t)comp * V);
+                const cx<R> p = ld<R>(psi, (uint32_t)comp * V + s);
                 // D psi = psi - kappa acc ; H = gamma5 D
                 cx<R> hv = p - kappa * acc[a][c];
                 if (a >= 2) hv = -hv;
                 if constexpr (MODE == 0) {
-                    stc<R>(o, (int64_t)comp * V, hv);
+                    stc<R>(o, (uint32_t)comp * V + s, hv);
                 } else {
                     // q = zs p - H p
                     const R zr = (R)zsr, zi = (R)zsi;
                     cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
-                    stc<R>(o, (int64_t)comp * V, q);
-                    const cx<R> r = ld<R>(rd, (int64_t)comp * V);
+                    stc<R>(o, (uint32_t)comp * V + s, q);
+                    const cx<R> r = ld<R>(rd, (uint32_t)comp * V + s);
                     // <r, q> = sum conj(r) q, accumulated in FP64
                     dre += (double)r.re * (double)q.re + (double)r.im * (double)q.im;
                     dim += (double)r.re * (double)q.im - (double)r.im * (double)q.re;
@@ -307,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
         __shared__ double sh[kBlock / 64];
         const double tr = block_sum<kBlock>(dre, sh);
         const double ti_ = block_sum<kBlock>(dim, sh);
-        if (threadIdx.x == 0) partial[(int64_t)n * gridDim.x + blockIdx.x] = make_double2(tr, ti_);
+        if (threadIdx.x == 0) partial[(int64_t)n * nsb + sb] = make_double2(tr, ti_);
     }
 }
 
@@ -316,24 +342,27 @@ int wilson_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                    double kappa, double2 zs, const C2<R>* r, double2* partial,
-                   const SrcState* stt, int nrhs, hipStream_t s) {
-    dim3 grid(wilson_blocks(g), nrhs);
+                   const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s) {
+    ShiftDev none{};
+    const ShiftDev& shv = sh ? *sh : none;
+    const int nsb = wilson_blocks(g);
+    dim3 grid((unsigned)nsb * (unsigned)nrhs);
     if (mode == 0)
         hipLaunchKernelGGL((k_wilson<R, 0>), grid, dim3(kBlock), 0, s, in, out, U, g, (R)kappa,
-                           zs.x, zs.y, r, partial, stt);
+                           zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
     else
         hipLaunchKernelGGL((k_wilson<R, 1>), grid, dim3(kBlock), 0, s, in, out, U, g, (R)kappa,
-                           zs.x, zs.y, r, partial, stt);
+                           zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
 }
 template void launch_wilson<double>(int, const double2*, double2*, const double2*, const Geom&,
                                     double, double2, const double2*, double2*, const SrcState*,
-                                    int, hipStream_t);
+                                    const ShiftDev*, int, int, hipStream_t);
 template void launch_wilson<float>(int, const float2*, float2*, const float2*, const Geom&,
                                    double, double2, const float2*, double2*, const SrcState*,
-                                   int, hipStream_t);
+                                   const ShiftDev*, int, int, hipStream_t);
 
 // ============================================================================
-// Krylov scalars
+// complex helpers (FP64 scalars)
 // ============================================================================
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -353,117 +382,232 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 __device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 
-// One block per source.  alpha_k = ||r_k||^2 / <r_k, A_s p_k>; for every active
-// shift j (Delta_j = z_j - z_s):
-//   pi_{k+1} = (1 + alpha_k Delta_j) pi_k + (alpha_k beta_{k-1}/alpha_{k-1}) (pi_k - pi_{k-1})
-//   alpha^j  = alpha_k pi_k / pi_{k+1}
-__global__ __launch_bounds__(kBlock) void k_alpha(SrcState* __restrict__ st,
-                                                  const double2* __restrict__ partial, int nblk,
-                                                  const double2* __restrict__ dz,
-                                                  const double2* __restrict__ pi,
-                                                  const double2* __restrict__ pi_prev,
-                                                  double2* __restrict__ pi_next,
-                                                  double2* __restrict__ aj,
-                                                  const int* __restrict__ active, int J) {
-    const int n = blockIdx.x;
-    SrcState& S = st[n];
-    if (S.done) {
-        if (threadIdx.x == 0) S.nlist = 0;
-        return;
-    }
-    __shared__ double sh[kBlock / 64];
+// ============================================================================
+// The seed iteration k is three kernels:
+//   K1  q = z_s p - H p and per-block <r, q>                (k_wilson, mode 1)
+//   K2  alpha_k (every block, from K1's partials), shifted pi_{k+1}, alpha^j
+//       (blocks 0..nslices-1, one lane per shift), r <- r - alpha q, ||r||^2
+//   K3  beta_k (every block, from K2's partials), shifted beta^j, residual
+//       estimates and deactivation (blocks 0..nslices-1), then p <- r + beta p
+//       or the shift sweep.
+// Quantities written in iteration k live in parity (k&1) or mod-3 buffers, so
+// no block reads what another block of the same kernel writes:
+//   SrcState.rr[k&1] = ||r_k||^2, alpha[k&1], beta[k&1];
+//   pi[k%3] = pi_k^j; active[k&1][j] = shift j active at the start of k;
+//   cnt[k&1][slice] = active shifts per 256-shift slice (a source is live at
+//   iteration k while status == 0 and some count is nonzero).
+// ============================================================================
+__device__ __forceinline__ bool src_live(const SrcState& S, const ShiftDev& sh, int n, int k) {
+    if (S.status != 0) return false;
+    const int* c = sh.cnt + ((size_t)(k & 1) * sh.nsrc + n) * kMaxSlices;
+    int t = 0;
+    for (int i = 0; i < sh.nslices; ++i) t += c[i];
+    return t > 0;
+}
+
+// sum of partial[0..nb) in a fixed order (strided per lane, then block_sum)
+template <typename T>
+__device__ __forceinline__ double sum_partials_re(const T* p, int nb, double* sh);
+template <>
+__device__ __forceinline__ double sum_partials_re<double>(const double* p, int nb, double* sh) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) v += p[b];
+    return block_sum<kBlock>(v, sh);
+}
+__device__ __forceinline__ double2 sum_partials_c(const double2* p, int nb, double* sh) {
     double re = 0.0, im = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
-        const double2 v = partial[(int64_t)n * nblk + b];
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        const double2 v = p[b];
         re += v.x;
         im += v.y;
     }
     re = block_sum<kBlock>(re, sh);
     im = block_sum<kBlock>(im, sh);
-    const double2 rq = make_double2(re, im);
+    return make_double2(re, im);
+}
+
+int vec_blocks(int64_t n12, int nslices) {
+    int nb = (int)((n12 + 4 * kBlock - 1) / (4 * kBlock));
+    if (nb > 512) nb = 512;
+    if (nb < nslices) nb = nslices;
+    return nb;
+}
+
+// K2: alpha, shifted pi / alpha^j, r update and ||r_{k+1}||^2 partials
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_update_r(const C2<R>* __restrict__ rin,
+                                                     C2<R>* __restrict__ rout,
+                                                     const C2<R>* __restrict__ q,
+                                                     SrcState* __restrict__ st,
+                                                     const double2* __restrict__ part_w, int nsb,
+                                                     double* __restrict__ part_e, int64_t n12,
+                                                     ShiftDev sh, int k) {
+    const int n = blockIdx.y;
+    SrcState& S = st[n];
+    if (!src_live(S, sh, n, k)) return;
+    __shared__ double shm[kBlock / 64];
+    const double2 rq = sum_partials_c(part_w + (size_t)n * nsb, nsb, shm);
+    const double rr = S.rr[k & 1];
     const bool bad = !finite2(rq);
-    const bool brk = cabs2(rq) <= 1e-300 * (S.rr > 0 ? S.rr : 1.0);
-    const double2 alpha = (bad || brk) ? make_double2(0, 0) : cdiv(make_double2(S.rr, 0.0), rq);
-    if (!bad && !brk) {
-        const double2 c1 = cdiv(cmul(alpha, S.beta_prev), S.alpha_prev);
-        for (int j = threadIdx.x; j < J; j += kBlock) {
-            const int64_t o = (int64_t)n * J + j;
-            if (!active[o]) continue;
-            const double2 p = pi[o], pp = pi_prev[o];
-            const double2 one_ad = make_double2(1.0 + (alpha.x * dz[j].x - alpha.y * dz[j].y),
-                                                alpha.x * dz[j].y + alpha.y * dz[j].x);
+    const bool brk = !bad && cabs2(rq) <= 1e-300 * rr;
+    if (bad || brk) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) S.status = bad ? OVL_E_NONFINITE : OVL_E_BREAKDOWN;
+        return;
+    }
+    const double2 alpha = cdiv(make_double2(rr, 0.0), rq);
+    if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[k & 1] = alpha;
+    if ((int)blockIdx.x < sh.nslices) {
+        // pi_{k+1} = (1 + alpha Dz) pi_k + (alpha beta_{k-1} / alpha_{k-1}) (pi_k - pi_{k-1})
+        const int j = blockIdx.x * kBlock + threadIdx.x;
+        const size_t o = (size_t)n * sh.J + j;
+        const size_t stride3 = (size_t)sh.nsrc * sh.J;
+        if (j < sh.J && sh.active[(size_t)(k & 1) * stride3 + o]) {
+            const double2 c1 = cdiv(cmul(alpha, S.beta[(k + 1) & 1]), S.alpha[(k + 1) & 1]);
+            const double2 p = sh.pi[(size_t)(k % 3) * stride3 + o];
+            const double2 pp = sh.pi[(size_t)((k + 2) % 3) * stride3 + o];
+            const double2 dz = sh.dz[j];
+            const double2 one_ad = make_double2(1.0 + (alpha.x * dz.x - alpha.y * dz.y),
+                                                alpha.x * dz.y + alpha.y * dz.x);
             const double2 pn = cadd(cmul(one_ad, p), cmul(c1, csub(p, pp)));
-            pi_next[o] = pn;
-            aj[o] = cdiv(cmul(alpha, p), pn);
+            sh.pi[(size_t)((k + 1) % 3) * stride3 + o] = pn;
+            sh.aj[o] = cdiv(cmul(alpha, p), pn);
         }
     }
-    if (threadIdx.x == 0) {
-        S.alpha = alpha;
-        if (bad || brk) {
-            S.status = bad ? OVL_E_NONFINITE : OVL_E_BREAKDOWN;
-            S.done = 1;
-            S.nlist = 0;
+    const R ar = (R)alpha.x, ai = (R)alpha.y;
+    const C2<R>* ri = rin + (size_t)n * n12;
+    C2<R>* ro = rout + (size_t)n * n12;
+    const C2<R>* qq = q + (size_t)n * n12;
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
+        const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e);
+        const cx<R> rn = mk<R>(r.re - (ar * qv.re - ai * qv.im), r.im - (ar * qv.im + ai * qv.re));
+        stc<R>(ro, e, rn);
+        acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
+    }
+    const double t = block_sum<kBlock>(acc, shm);
+    if (threadIdx.x == 0) part_e[(size_t)n * gridDim.x + blockIdx.x] = t;
+}
+
+// K3 scalar part, shared by the p update and the sweeps.  Returns false if
+// the source is not live (then the shift slices publish zero counts).
+// On return beta = beta_k.
+__device__ __forceinline__ bool k3_scalars(SrcState& S, const ShiftDev& sh, const double* part_e,
+                                           int nbe, int n, int k, double2& beta, double* shm) {
+    const size_t stride3 = (size_t)sh.nsrc * sh.J;
+    int* cnt_next = sh.cnt + ((size_t)((k + 1) & 1) * sh.nsrc + n) * kMaxSlices;
+    if (!src_live(S, sh, n, k)) {
+        if ((int)blockIdx.x < sh.nslices && threadIdx.x == 0) cnt_next[blockIdx.x] = 0;
+        return false;
+    }
+    const double rrn = sum_partials_re<double>(part_e + (size_t)n * nbe, nbe, shm);
+    const double2 al = S.alpha[k & 1];
+    const double2 ph = cdiv(al, make_double2(al.x, -al.y));  // alpha / conj(alpha)
+    const double ratio = rrn / S.rr[k & 1];
+    beta = make_double2(ph.x * ratio, ph.y * ratio);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S.beta[k & 1] = beta;
+        S.rr[(k + 1) & 1] = rrn;
+        S.iter = k + 1;
+        if (!isfinite(rrn)) S.status = OVL_E_NONFINITE;
+    }
+    if ((int)blockIdx.x < sh.nslices) {
+        const int j = blockIdx.x * kBlock + threadIdx.x;
+        const size_t o = (size_t)n * sh.J + j;
+        int stay = 0;
+        double res = 0.0;
+        if (j < sh.J) {
+            const bool act = sh.active[(size_t)(k & 1) * stride3 + o] != 0;
+            double2 bj = make_double2(0, 0);
+            if (act) {
+                const double2 pn = sh.pi[(size_t)((k + 1) % 3) * stride3 + o];
+                const double2 p = sh.pi[(size_t)(k % 3) * stride3 + o];
+                const double2 rt = cdiv(p, pn);
+                bj = cmul(cmul(rt, rt), beta);
+                res = sqrt(rrn / cabs2(pn) / S.bb);
+                stay = (res > sh.tol && isfinite(res)) ? 1 : 0;
+                sh.res[o] = res;
+            }
+            sh.active[(size_t)((k + 1) & 1) * stride3 + o] = stay;
+            if (sh.h_a != nullptr) {
+                const size_t ho = ((size_t)n * (sh.maxk + 1) + k) * sh.J + j;
+                sh.h_a[ho] = act ? sh.aj[o] : make_double2(0, 0);
+                sh.h_b[ho] = bj;
+                sh.h_pi[ho + sh.J] = act ? sh.pi[(size_t)((k + 1) % 3) * stride3 + o]
+                                         : make_double2(1, 0);
+            }
         }
+        const double tot = block_sum<kBlock>((double)stay, shm);
+        const double mx = block_max<kBlock>(res, shm);
+        if (threadIdx.x == 0) {
+            cnt_next[blockIdx.x] = (int)(tot + 0.5);
+            sh.mres[(size_t)n * kMaxSlices + blockIdx.x] = mx;
+        }
+    }
+    return true;
+}
+
+// K3, basis forms: p <- r_{k+1} + beta p
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_update_p(const C2<R>* __restrict__ r,
+                                                     C2<R>* __restrict__ p, SrcState* st,
+                                                     const double* __restrict__ part_e, int nbe,
+                                                     int64_t n12, ShiftDev sh, int k) {
+    const int n = blockIdx.y;
+    __shared__ double shm[kBlock / 64];
+    double2 beta;
+    if (!k3_scalars(st[n], sh, part_e, nbe, n, k, beta, shm)) return;
+    const R br = (R)beta.x, bi = (R)beta.y;
+    const C2<R>* rr = r + (size_t)n * n12;
+    C2<R>* pp = p + (size_t)n * n12;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
+        const cx<R> rv = ld<R>(rr, e), po = ld<R>(pp, e);
+        stc<R>(pp, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
     }
 }
 
-void launch_alpha(SrcState* st, const double2* partial, int nblk, const double2* dz,
-                  const double2* pi, const double2* pi_prev, double2* pi_next, double2* aj,
-                  const int* active, int J, int nsrc, hipStream_t s) {
-    hipLaunchKernelGGL(k_alpha, dim3(nsrc), dim3(kBlock), 0, s, st, partial, nblk, dz, pi,
-                       pi_prev, pi_next, aj, active, J);
-}
-
-// One block per source.  beta_k = (alpha_k / conj(alpha_k)) ||r_{k+1}||^2 / ||r_k||^2,
-// beta^j = (pi_k / pi_{k+1})^2 beta_k; shift j's residual estimate is
-// ||r_{k+1}|| / |pi_{k+1}^j|.  Shifts active at the start of this iteration
-// enter the sweep list; those now below tol*||b|| are deactivated afterwards.
-__global__ __launch_bounds__(kBlock) void k_beta(BetaArgs a) {
-    const int n = blockIdx.x;
-    SrcState& S = a.st[n];
-    if (S.done) return;
-    __shared__ double sh[kBlock / 64];
+// K3, sweep forms.  Every block rebuilds the list of shifts active at the
+// start of iteration k in LDS: coefficient (c_j alpha^j, or alpha^j for the
+// reference form), 1/pi_{k+1}^j and beta^j.  Then, per component:
+//   s += sum_l coef_l p_{j_l}   (fused)  or  x_j += alpha^j p_j (reference)
+//   p_{j_l} <- r / pi_{k+1} + beta^j p_{j_l};   p <- r + beta p
+// In the first iteration p_j = b for every j, read from b0 instead.
+template <typename R, bool REF>
+__global__ __launch_bounds__(kBlock) void k_sweep(const C2<R>* __restrict__ r,
+                                                  C2<R>* __restrict__ p, C2<R>* __restrict__ pj,
+                                                  double2* __restrict__ acc_out,
+                                                  const double2* __restrict__ b0, SrcState* st,
+                                                  const double* __restrict__ part_e, int nbe,
+                                                  int64_t n12, ShiftDev sh, int k) {
+    const int n = blockIdx.y;
+    __shared__ double shm[kBlock / 64];
+    extern __shared__ unsigned char lds_raw[];
+    double2* l_coef = reinterpret_cast<double2*>(lds_raw);
+    double2* l_ipi = l_coef + sh.J;
+    double2* l_b = l_ipi + sh.J;
+    int* l_j = reinterpret_cast<int*>(l_b + sh.J);
     __shared__ int wcount[kBlock / 64];
     __shared__ int base;
-    double v = 0.0;
-    for (int b = threadIdx.x; b < a.nblk; b += kBlock) v += a.partial[(int64_t)n * a.nblk + b];
-    const double rrn = block_sum<kBlock>(v, sh);
-    const double2 al = S.alpha;
-    // alpha / conj(alpha) has unit modulus
-    const double2 ph = cdiv(al, make_double2(al.x, -al.y));
-    const double ratio = rrn / S.rr;
-    const double2 beta = make_double2(ph.x * ratio, ph.y * ratio);
-    const double rn = sqrt(rrn), bn = sqrt(S.bb);
-    const int k = S.iter;
+    double2 beta;
+    SrcState& S = st[n];
+    if (!k3_scalars(S, sh, part_e, nbe, n, k, beta, shm)) return;
+    const size_t stride3 = (size_t)sh.nsrc * sh.J;
     if (threadIdx.x == 0) base = 0;
     __syncthreads();
-    double mres = 0.0;
-    int nstay = 0;
-    for (int j0 = 0; j0 < a.J; j0 += kBlock) {
+    for (int j0 = 0; j0 < sh.J; j0 += kBlock) {
         const int j = j0 + threadIdx.x;
-        const int64_t o = (int64_t)n * a.J + j;
-        const bool act = (j < a.J) && a.active[o];
-        double2 bj = make_double2(0, 0), ipi = make_double2(0, 0), coef = make_double2(0, 0);
+        const size_t o = (size_t)n * sh.J + j;
+        const bool act = j < sh.J && sh.active[(size_t)(k & 1) * stride3 + o] != 0;
+        double2 coef = make_double2(0, 0), ipi = coef, bj = coef;
         if (act) {
-            const double2 pn = a.pi_next[o], p = a.pi[o];
-            const double2 rt = cdiv(p, pn);
+            const double2 pn = sh.pi[(size_t)((k + 1) % 3) * stride3 + o];
+            const double2 pk = sh.pi[(size_t)(k % 3) * stride3 + o];
+            const double2 rt = cdiv(pk, pn);
             bj = cmul(cmul(rt, rt), beta);
             ipi = cdiv(make_double2(1.0, 0.0), pn);
-            const double2 aj = a.aj[o];
-            coef = (a.c != nullptr) ? cmul(a.c[j], aj) : aj;
-            const double res = rn / sqrt(cabs2(pn)) / bn;
-            mres = fmax(mres, res);
-            a.pi_prev[o] = p;
-            a.pi[o] = pn;
-            if (res <= a.tol) a.active[o] = 0; else ++nstay;
+            coef = REF ? sh.aj[o] : cmul(sh.c[j], sh.aj[o]);
         }
-        if (a.h_a != nullptr && j < a.J) {
-            const int64_t ho = ((int64_t)n * (a.maxk + 1) + k) * a.J + j;
-            a.h_a[ho] = act ? a.aj[o] : make_double2(0, 0);
-            a.h_b[ho] = bj;
-            a.h_pi[ho + a.J] = act ? a.pi_next[o] : a.pi[o];
-        }
-        // compact the active shifts into the sweep list (order of j kept)
         const unsigned long long m = __ballot(act);
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         const int before = __popcll(m & ((1ull << lane) - 1ull));
@@ -472,11 +616,10 @@ __global__ __launch_bounds__(kBlock) void k_beta(BetaArgs a) {
         int off = base;
         for (int i = 0; i < w; ++i) off += wcount[i];
         if (act) {
-            const int64_t lo = (int64_t)n * a.J + off + before;
-            a.lst_j[lo] = j;
-            a.lst_a[lo] = coef;
-            a.lst_ipi[lo] = ipi;
-            a.lst_b[lo] = bj;
+            l_j[off + before] = j;
+            l_coef[off + before] = coef;
+            l_ipi[off + before] = ipi;
+            l_b[off + before] = bj;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -486,159 +629,82 @@ __global__ __launch_bounds__(kBlock) void k_beta(BetaArgs a) {
         }
         __syncthreads();
     }
-    const double mall = block_max<kBlock>(mres, sh);
-    const double nall = block_sum<kBlock>((double)nstay, sh);
-    if (threadIdx.x == 0) {
-        const int tot = (int)(nall + 0.5);
-        S.nlist = base;
-        S.nact = tot;
-        S.maxres = mall;
-        S.rr = rrn;
-        S.alpha_prev = al;
-        S.beta_prev = beta;
-        S.iter = k + 1;
-        if (tot == 0) S.done = 1;
-        if (!isfinite(rrn)) {
-            S.status = OVL_E_NONFINITE;
-            S.done = 1;
-        }
-    }
-}
-
-void launch_beta(const BetaArgs& a, int nsrc, hipStream_t s) {
-    hipLaunchKernelGGL(k_beta, dim3(nsrc), dim3(kBlock), 0, s, a);
-}
-
-
-// ============================================================================
-// vector kernels: one lane per complex component, grid.y = source
-// ============================================================================
-int elem_blocks(int64_t n12) { return (int)((n12 + kBlock - 1) / kBlock); }
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_update_r(const C2<R>* __restrict__ rin,
-                                                     C2<R>* __restrict__ rout,
-                                                     const C2<R>* __restrict__ q,
-                                                     const SrcState* __restrict__ st,
-                                                     double* __restrict__ partial, int64_t n12,
-                                                     int64_t sin_, int64_t sout) {
-    const int n = blockIdx.y;
-    if (st[n].done) return;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double acc = 0.0;
-    if (e < n12) {
-        const double2 al = st[n].alpha;
-        const cx<R> r = ld<R>(rin + n * sin_, e), qq = ld<R>(q + n * n12, e);
-        const R ar = (R)al.x, ai = (R)al.y;
-        cx<R> rn = mk<R>(r.re - (ar * qq.re - ai * qq.im), r.im - (ar * qq.im + ai * qq.re));
-        stc<R>(rout + n * sout, e, rn);
-        acc = (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
-    }
-    __shared__ double sh[kBlock / 64];
-    const double t = block_sum<kBlock>(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)n * gridDim.x + blockIdx.x] = t;
-}
-
-template <typename R>
-void launch_update_r(const C2<R>* rin, C2<R>* rout, const C2<R>* q, const SrcState* st,
-                     double* partial, int64_t n12, int64_t src_stride_in,
-                     int64_t src_stride_out, int nsrc, hipStream_t s) {
-    dim3 grid(elem_blocks(n12), nsrc);
-    hipLaunchKernelGGL(k_update_r<R>, grid, dim3(kBlock), 0, s, rin, rout, q, st, partial, n12,
-                       src_stride_in, src_stride_out);
-}
-template void launch_update_r<double>(const double2*, double2*, const double2*, const SrcState*,
-                                      double*, int64_t, int64_t, int64_t, int, hipStream_t);
-template void launch_update_r<float>(const float2*, float2*, const float2*, const SrcState*,
-                                     double*, int64_t, int64_t, int64_t, int, hipStream_t);
-
-// The fused sweep: for every shift in this iteration's list (uniform per
-// source, read through the scalar cache)
-//   s += (c_j alpha^j) p_j ;  p_j <- r / pi_{k+1}^j + beta^j p_j
-// and the seed direction p <- r + beta p, in one pass over the components.
-// In the first iteration p_j = b for every j, read from b0 instead.
-template <typename R, bool REF>
-__global__ __launch_bounds__(kBlock) void k_sweep(const C2<R>* __restrict__ r,
-                                                  C2<R>* __restrict__ p, C2<R>* __restrict__ pj,
-                                                  double2* __restrict__ acc_out,
-                                                  const double2* __restrict__ b0,
-                                                  const SrcState* __restrict__ st,
-                                                  const int* __restrict__ lst_j,
-                                                  const double2* __restrict__ lst_a,
-                                                  const double2* __restrict__ lst_ipi,
-                                                  const double2* __restrict__ lst_b, int J,
-                                                  int64_t n12, int first) {
-    const int n = blockIdx.y;
-    const int nl = st[n].nlist;
-    if (nl == 0) return;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= n12) return;
-    const cx<R> rv = ld<R>(r + n * n12, e);
-    const double2 beta = st[n].beta_prev;
-    const int64_t lb = (int64_t)n * J;
-    const cx<R> bfirst = first ? mk<R>((R)b0[n * n12 + e].x, (R)b0[n * n12 + e].y) : mk<R>(0, 0);
-    double sre = 0.0, sim = 0.0;
-    for (int l = 0; l < nl; ++l) {
-        const int j = lst_j[lb + l];
-        const double2 ca = lst_a[lb + l], ip = lst_ipi[lb + l], bj = lst_b[lb + l];
-        C2<R>* pp = pj + ((int64_t)n * J + j) * n12;
-        const cx<R> pv = first ? bfirst : ld<R>(pp, e);
-        if constexpr (REF) {
-            // x_j += alpha^j p_j  (x_j kept in FP64)
-            double2* xp = acc_out + ((int64_t)n * J + j) * n12;
-            double2 x = xp[e];
-            x.x += ca.x * (double)pv.re - ca.y * (double)pv.im;
-            x.y += ca.x * (double)pv.im + ca.y * (double)pv.re;
-            xp[e] = x;
-        } else {
-            sre += ca.x * (double)pv.re - ca.y * (double)pv.im;
-            sim += ca.x * (double)pv.im + ca.y * (double)pv.re;
-        }
-        const R ipr = (R)ip.x, ipi = (R)ip.y, br = (R)bj.x, bi = (R)bj.y;
-        cx<R> np = mk<R>(rv.re * ipr - rv.im * ipi + br * pv.re - bi * pv.im,
-                         rv.re * ipi + rv.im * ipr + br * pv.im + bi * pv.re);
-        stc<R>(pp, e, np);
-    }
-    if constexpr (!REF) {
-        double2 sv = acc_out[n * n12 + e];
-        sv.x += sre;
-        sv.y += sim;
-        acc_out[n * n12 + e] = sv;
-    }
-    const cx<R> po = ld<R>(p + n * n12, e);
+    const int nl = base;
     const R br = (R)beta.x, bi = (R)beta.y;
-    stc<R>(p + n * n12, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
+    const C2<R>* rr = r + (size_t)n * n12;
+    C2<R>* pp = p + (size_t)n * n12;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
+        const cx<R> rv = ld<R>(rr, e);
+        const cx<R> bfirst = (k == 0) ? mk<R>((R)b0[(size_t)n * n12 + e].x, (R)b0[(size_t)n * n12 + e].y)
+                                      : mk<R>(0, 0);
+        double sre = 0.0, sim = 0.0;
+        for (int l = 0; l < nl; ++l) {
+            const int j = l_j[l];
+            const double2 ca = l_coef[l], ip = l_ipi[l], bj = l_b[l];
+            C2<R>* pjp = pj + ((size_t)n * sh.J + j) * n12;
+            const cx<R> pv = (k == 0) ? bfirst : ld<R>(pjp, e);
+            if constexpr (REF) {
+                double2* xp = acc_out + ((size_t)n * sh.J + j) * n12;
+                double2 x = xp[e];
+                x.x += ca.x * (double)pv.re - ca.y * (double)pv.im;
+                x.y += ca.x * (double)pv.im + ca.y * (double)pv.re;
+                xp[e] = x;
+            } else {
+                sre += ca.x * (double)pv.re - ca.y * (double)pv.im;
+                sim += ca.x * (double)pv.im + ca.y * (double)pv.re;
+            }
+            const R ipr = (R)ip.x, ipi_ = (R)ip.y, bjr = (R)bj.x, bji = (R)bj.y;
+            stc<R>(pjp, e, mk<R>(rv.re * ipr - rv.im * ipi_ + bjr * pv.re - bji * pv.im,
+                                 rv.re * ipi_ + rv.im * ipr + bjr * pv.im + bji * pv.re));
+        }
+        if constexpr (!REF) {
+            double2 sv = acc_out[(size_t)n * n12 + e];
+            sv.x += sre;
+            sv.y += sim;
+            acc_out[(size_t)n * n12 + e] = sv;
+        }
+        const cx<R> po = ld<R>(pp, e);
+        stc<R>(pp, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
+    }
 }
 
 template <typename R>
-void launch_sweep_fused(const C2<R>* r, C2<R>* p, C2<R>* pj, double2* sacc, const double2* b0,
-                        const SrcState* st, const int* lst_j, const double2* lst_a,
-                        const double2* lst_ipi, const double2* lst_b, int J, int64_t n12,
-                        int nsrc, bool first, hipStream_t s) {
-    dim3 grid(elem_blocks(n12), nsrc);
-    hipLaunchKernelGGL((k_sweep<R, false>), grid, dim3(kBlock), 0, s, r, p, pj, sacc, b0, st,
-                       lst_j, lst_a, lst_ipi, lst_b, J, n12, (int)first);
+void launch_update_r(const C2<R>* rin, C2<R>* rout, const C2<R>* q, SrcState* st,
+                     const double2* part_w, int nsb, double* part_e, int nbe, int64_t n12,
+                     const ShiftDev& sh, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_update_r<R>, dim3(nbe, sh.nsrc), dim3(kBlock), 0, s, rin, rout, q, st,
+                       part_w, nsb, part_e, n12, sh, k);
 }
 template <typename R>
-void launch_sweep_ref(const C2<R>* r, C2<R>* p, C2<R>* pj, double2* xj, const double2* b0,
-                      const SrcState* st, const int* lst_j, const double2* lst_a,
-                      const double2* lst_ipi, const double2* lst_b, int J, int64_t n12,
-                      int nsrc, bool first, hipStream_t s) {
-    dim3 grid(elem_blocks(n12), nsrc);
-    hipLaunchKernelGGL((k_sweep<R, true>), grid, dim3(kBlock), 0, s, r, p, pj, xj, b0, st,
-                       lst_j, lst_a, lst_ipi, lst_b, J, n12, (int)first);
+void launch_update_p(const C2<R>* r, C2<R>* p, SrcState* st, const double* part_e, int nbe,
+                     int64_t n12, const ShiftDev& sh, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_update_p<R>, dim3(nbe, sh.nsrc), dim3(kBlock), 0, s, r, p, st, part_e,
+                       nbe, n12, sh, k);
 }
-#define OVL_INST_SWEEP(R)                                                                      \
-    template void launch_sweep_fused<R>(const C2<R>*, C2<R>*, C2<R>*, double2*, const double2*, \
-                                        const SrcState*, const int*, const double2*,            \
-                                        const double2*, const double2*, int, int64_t, int,      \
-                                        bool, hipStream_t);                                     \
-    template void launch_sweep_ref<R>(const C2<R>*, C2<R>*, C2<R>*, double2*, const double2*,   \
-                                      const SrcState*, const int*, const double2*,              \
-                                      const double2*, const double2*, int, int64_t, int, bool,  \
-                                      hipStream_t);
-OVL_INST_SWEEP(double)
-OVL_INST_SWEEP(float)
+template <typename R>
+void launch_sweep(bool ref, const C2<R>* r, C2<R>* p, C2<R>* pj, double2* acc,
+                  const double2* b0, SrcState* st, const double* part_e, int nbe, int64_t n12,
+                  const ShiftDev& sh, int k, hipStream_t s) {
+    const size_t lds = (size_t)sh.J * (3 * sizeof(double2) + sizeof(int));
+    if (ref)
+        hipLaunchKernelGGL((k_sweep<R, true>), dim3(nbe, sh.nsrc), dim3(kBlock), lds, s, r, p, pj,
+                           acc, b0, st, part_e, nbe, n12, sh, k);
+    else
+        hipLaunchKernelGGL((k_sweep<R, false>), dim3(nbe, sh.nsrc), dim3(kBlock), lds, s, r, p, pj,
+                           acc, b0, st, part_e, nbe, n12, sh, k);
+}
+#define OVL_INST_K23(R)                                                                         \
+    template void launch_update_r<R>(const C2<R>*, C2<R>*, const C2<R>*, SrcState*,            \
+                                     const double2*, int, double*, int, int64_t,                \
+                                     const ShiftDev&, int, hipStream_t);                        \
+    template void launch_update_p<R>(const C2<R>*, C2<R>*, SrcState*, const double*, int,      \
+                                     int64_t, const ShiftDev&, int, hipStream_t);               \
+    template void launch_sweep<R>(bool, const C2<R>*, C2<R>*, C2<R>*, double2*, const double2*, \
+                                  SrcState*, const double*, int, int64_t, const ShiftDev&, int, \
+                                  hipStream_t);
+OVL_INST_K23(double)
+OVL_INST_K23(float)
 
 // s = sum_j c_j x_j (reference form, once at the end; fixed order in j)
 __global__ __launch_bounds__(kBlock) void k_sum_ref(const double2* __restrict__ xj,
@@ -659,35 +725,9 @@ __global__ __launch_bounds__(kBlock) void k_sum_ref(const double2* __restrict__ 
 }
 void launch_sum_ref(const double2* xj, const double2* c, double2* sacc, int J, int64_t n12,
                     int nsrc, hipStream_t s) {
-    dim3 grid(elem_blocks(n12), nsrc);
+    dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock), nsrc);
     hipLaunchKernelGGL(k_sum_ref, grid, dim3(kBlock), 0, s, xj, c, sacc, J, n12);
 }
-
-// p = r + beta p (basis forms; the sweep kernel does this in the sweep forms)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_update_p(const C2<R>* __restrict__ r,
-                                                     C2<R>* __restrict__ p,
-                                                     const SrcState* __restrict__ st,
-                                                     int64_t n12, int64_t sr) {
-    const int n = blockIdx.y;
-    if (st[n].nlist == 0) return;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= n12) return;
-    const double2 beta = st[n].beta_prev;
-    const cx<R> rv = ld<R>(r + n * sr, e), po = ld<R>(p + n * n12, e);
-    const R br = (R)beta.x, bi = (R)beta.y;
-    stc<R>(p + n * n12, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
-}
-template <typename R>
-void launch_update_p(const C2<R>* r, C2<R>* p, const SrcState* st, int64_t n12,
-                     int64_t src_stride_r, int nsrc, hipStream_t s) {
-    dim3 grid(elem_blocks(n12), nsrc);
-    hipLaunchKernelGGL(k_update_p<R>, grid, dim3(kBlock), 0, s, r, p, st, n12, src_stride_r);
-}
-template void launch_update_p<double>(const double2*, double2*, const SrcState*, int64_t, int64_t,
-                                      int, hipStream_t);
-template void launch_update_p<float>(const float2*, float2*, const SrcState*, int64_t, int64_t,
-                                     int, hipStream_t);
 
 // ============================================================================
 // basis forms
@@ -775,7 +815,7 @@ template <typename R>
 void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_stride,
                        const double2* h, int maxk, const SrcState* st, int g0, int l0, int l1,
                        double2* sacc, bool accumulate, int64_t n12, int nsrc, hipStream_t s) {
-    dim3 grid(elem_blocks(n12), nsrc);
+    dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock), nsrc);
     hipLaunchKernelGGL(k_gemv<R>, grid, dim3(kBlock), 0, s, (const C2<R>*)slots, slot_stride,
                        src_stride, h, maxk, st, g0, l0, l1, sacc, (int)accumulate, n12);
 }
@@ -793,60 +833,62 @@ template void launch_basis_gemv<float>(const void*, int64_t, int64_t, const doub
 __global__ __launch_bounds__(kBlock) void k_norm2(const double2* __restrict__ b,
                                                   double* __restrict__ partial, int64_t n12) {
     const int n = blockIdx.y;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double acc = 0.0;
-    if (e < n12) {
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
         const double2 v = b[n * n12 + e];
-        acc = v.x * v.x + v.y * v.y;
+        acc += v.x * v.x + v.y * v.y;
     }
     __shared__ double sh[kBlock / 64];
     const double t = block_sum<kBlock>(acc, sh);
     if (threadIdx.x == 0) partial[(int64_t)n * gridDim.x + blockIdx.x] = t;
 }
-// r = p = b, pi = pi_prev = 1, every shift active, alpha_{-1} = 1, beta_{-1} = 0
+// Iteration 0 state: r = p = b, pi_0 = pi_{-1} = 1, every shift active,
+// alpha_{-1} = 1, beta_{-1} = 0.  One block per (slice, source).
 __global__ __launch_bounds__(kBlock) void k_init_state(SrcState* __restrict__ st,
                                                        const double* __restrict__ partial,
-                                                       int nblk, double2* __restrict__ pi,
-                                                       double2* __restrict__ pi_prev,
-                                                       int* __restrict__ active, int J,
-                                                       double2* __restrict__ h_pi, int maxk) {
-    const int n = blockIdx.x;
-    __shared__ double sh[kBlock / 64];
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) v += partial[(int64_t)n * nblk + b];
-    const double bb = block_sum<kBlock>(v, sh);
-    const bool zero = !(bb > 0.0);
-    for (int j = threadIdx.x; j < J; j += kBlock) {
-        const int64_t o = (int64_t)n * J + j;
-        pi[o] = make_double2(1, 0);
-        pi_prev[o] = make_double2(1, 0);
-        active[o] = zero ? 0 : 1;
-        if (h_pi != nullptr) h_pi[(int64_t)n * (maxk + 1) * J + j] = make_double2(1, 0);
+                                                       int nblk, ShiftDev sh) {
+    const int n = blockIdx.y;
+    __shared__ double shm[kBlock / 64];
+    const double bb = sum_partials_re<double>(partial + (size_t)n * nblk, nblk, shm);
+    const bool ok = bb > 0.0 && isfinite(bb);
+    const size_t stride3 = (size_t)sh.nsrc * sh.J;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j < sh.J) {
+        const size_t o = (size_t)n * sh.J + j;
+        sh.pi[o] = make_double2(1, 0);
+        sh.pi[2 * stride3 + o] = make_double2(1, 0);
+        sh.active[o] = ok ? 1 : 0;
+        sh.res[o] = ok ? 1.0 : 0.0;
+        if (sh.h_pi != nullptr) sh.h_pi[(size_t)n * (sh.maxk + 1) * sh.J + j] = make_double2(1, 0);
     }
     if (threadIdx.x == 0) {
+        int c = sh.J - blockIdx.x * kBlock;
+        c = c > kBlock ? kBlock : c;
+        sh.cnt[(size_t)n * kMaxSlices + blockIdx.x] = ok ? c : 0;
+        sh.mres[(size_t)n * kMaxSlices + blockIdx.x] = ok ? 1.0 : 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         SrcState S;
-        S.rr = bb;
         S.bb = bb;
-        S.alpha = make_double2(0, 0);
-        S.alpha_prev = make_double2(1, 0);
-        S.beta_prev = make_double2(0, 0);
-        S.maxres = zero ? 0.0 : 1.0;
+        S.rr[0] = bb;
+        S.rr[1] = 0.0;
+        S.alpha[0] = make_double2(0, 0);
+        S.alpha[1] = make_double2(1, 0);
+        S.beta[0] = make_double2(0, 0);
+        S.beta[1] = make_double2(0, 0);
         S.iter = 0;
-        S.nact = zero ? 0 : J;
-        S.done = (zero || !isfinite(bb)) ? 1 : 0;
         S.status = isfinite(bb) ? 0 : OVL_E_NONFINITE;
-        S.nlist = 0;
-        S.pad = 0;
+        S.pad[0] = S.pad[1] = 0;
         st[n] = S;
     }
 }
-void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t n12, double2* pi,
-                       double2* pi_prev, int* active, int J, double2* h_pi, int maxk, int nsrc,
-                       hipStream_t s) {
-    const int nb = elem_blocks(n12);
-    hipLaunchKernelGGL(k_norm2, dim3(nb, nsrc), dim3(kBlock), 0, s, b, partial, n12);
-    hipLaunchKernelGGL(k_init_state, dim3(nsrc), dim3(kBlock), 0, s, st, partial, nb, pi, pi_prev,
-                       active, J, h_pi, maxk);
+void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t n12,
+                       const ShiftDev& sh, hipStream_t s) {
+    const int nb = vec_blocks(n12, sh.nslices);
+    hipLaunchKernelGGL(k_norm2, dim3(nb, sh.nsrc), dim3(kBlock), 0, s, b, partial, n12);
+    hipLaunchKernelGGL(k_init_state, dim3(sh.nslices, sh.nsrc), dim3(kBlock), 0, s, st, partial,
+                       nb, sh);
 }
 
 }  // namespace ovl

@@ -67,6 +67,15 @@ struct ovl_ctx {
     SrcState* host_state = nullptr;  // pinned mirror
     int host_state_n = 0;
     DBuf bench_a, bench_b;
+    // per-kernel-class event timing (ovl_set_profiling)
+    static constexpr int kClasses = 8;
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct ProfRec { int cls; int ev; double bytes; };
+    std::vector<ProfRec> prof_pending;
+    double prof_ms[kClasses] = {0};
+    int64_t prof_n[kClasses] = {0};
+    double prof_bytes[kClasses] = {0};
     ovl_stats last{};
     char err[512] = {0};
 };
@@ -129,7 +138,63 @@ struct DeviceGuard {
     }
 };
 
+// Brackets one launch of class `cls` with two events (profiling only).
+struct ProfScope {
+    ovl_ctx* ctx;
+    int idx = -1;
+    ProfScope(ovl_ctx* c, int cls, double bytes) : ctx(c) {
+        if (!ctx->prof_on) return;
+        const size_t need = 2 * (ctx->prof_pending.size() + 1);
+        while (ctx->ev_pool.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            ctx->ev_pool.push_back(e);
+        }
+        idx = (int)ctx->prof_pending.size();
+        ctx->prof_pending.push_back({cls, 2 * idx, bytes});
+        (void)hipEventRecord(ctx->ev_pool[2 * idx], ctx->stream);
+    }
+    ~ProfScope() {
+        if (idx >= 0) (void)hipEventRecord(ctx->ev_pool[2 * idx + 1], ctx->stream);
+    }
+};
+
+// After a stream synchronisation: fold the pending event pairs into the totals.
+void prof_collect(ovl_ctx* ctx) {
+    for (const auto& r : ctx->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->ev_pool[r.ev], ctx->ev_pool[r.ev + 1]) == hipSuccess) {
+            ctx->prof_ms[r.cls] += ms;
+            ctx->prof_n[r.cls] += 1;
+            ctx->prof_bytes[r.cls] += r.bytes;
+        }
+    }
+    ctx->prof_pending.clear();
+}
+
 }  // namespace
+
+extern "C" int ovl_set_profiling(ovl_ctx* ctx, int32_t enable) {
+    if (!ctx) return OVL_E_ARG;
+    ctx->prof_on = enable != 0;
+    ctx->prof_pending.clear();
+    for (int i = 0; i < ovl_ctx::kClasses; ++i) {
+        ctx->prof_ms[i] = 0;
+        ctx->prof_n[i] = 0;
+        ctx->prof_bytes[i] = 0;
+    }
+    return OVL_OK;
+}
+
+extern "C" int ovl_get_profile(const ovl_ctx* ctx, int32_t kclass, double* total_ms,
+                               int64_t* launches, double* bytes) {
+    if (!ctx || kclass < 0 || kclass >= ovl_ctx::kClasses || !total_ms || !launches || !bytes)
+        return OVL_E_ARG;
+    *total_ms = ctx->prof_ms[kclass];
+    *launches = ctx->prof_n[kclass];
+    *bytes = ctx->prof_bytes[kclass];
+    return OVL_OK;
+}
 
 // ============================================================================
 // context
@@ -180,6 +245,7 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
                     &ctx->h,    &ctx->bench_a, &ctx->bench_b};
     for (DBuf* b : bufs) b->release();
     for (DBuf& b : ctx->slot_chunks) b.release();
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
     delete ctx;
     return OVL_OK;
@@ -332,7 +398,7 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
                          nrhs, ctx->stream);
     launch_wilson<double>(0, ctx->hw_in.as<double2>(), ctx->hw_out.as<double2>(),
                           ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0), make_double2(0, 0),
-                          nullptr, nullptr, nullptr, nrhs, ctx->stream);
+                          nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream);
     launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, nrhs,
                            ctx->stream);
     HIPCHK(ctx, hipGetLastError());
@@ -355,14 +421,20 @@ struct Work {
     size_t slot_bytes;          // nsrc * N * sizeof(double2)
     double2* part_w;
     double* part_e;
-    SrcState* st;
-    double2 *pi, *pi_prev, *pi_next, *aj;
-    int* active;
-    int* lst_j;
-    double2 *lst_a, *lst_ipi, *lst_b;
+    int nbw, nbe;          // partials per source of K1 and of the vector kernels
+    SrcState* st;          // device state block: st | cnt | mres (one copy to the host)
+    size_t state_bytes;
+    ShiftDev sh;
     double2 *dz, *cj;
     double2 *h_a, *h_b, *h_pi, *W, *h;
 };
+
+// layout of the state block shared by the device and its pinned host mirror
+size_t state_cnt_off(int nsrc) { return ((size_t)nsrc * sizeof(SrcState) + 255) & ~(size_t)255; }
+size_t state_mres_off(int nsrc) {
+    return (state_cnt_off(nsrc) + (size_t)2 * nsrc * kMaxSlices * sizeof(int) + 255) & ~(size_t)255;
+}
+size_t state_bytes_for(int nsrc) { return state_mres_off(nsrc) + (size_t)nsrc * kMaxSlices * sizeof(double); }
 
 int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     const int J = (int)ctx->z.size();
@@ -416,28 +488,35 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
         ctx->slot_chunks.clear();
         ctx->slot_chunk_bytes = vec64 * kSlotChunk;
     }
-    const int nbw = wilson_blocks(ctx->g), nbe = elem_blocks(N);
-    HIPCHK(ctx, ctx->part_w.ensure((size_t)nsrc * nbw * sizeof(double2)));
-    HIPCHK(ctx, ctx->part_e.ensure((size_t)nsrc * nbe * sizeof(double)));
-    HIPCHK(ctx, ctx->state.ensure((size_t)nsrc * sizeof(SrcState)));
+    const int nslices = (J + 255) / 256;
+    w.nbw = wilson_blocks(ctx->g);
+    w.nbe = vec_blocks(N, nslices);
+    HIPCHK(ctx, ctx->part_w.ensure((size_t)nsrc * w.nbw * sizeof(double2)));
+    HIPCHK(ctx, ctx->part_e.ensure((size_t)nsrc * w.nbe * sizeof(double)));
+    w.state_bytes = state_bytes_for(nsrc);
+    HIPCHK(ctx, ctx->state.ensure(w.state_bytes));
     w.part_w = ctx->part_w.as<double2>();
     w.part_e = ctx->part_e.as<double>();
     w.st = ctx->state.as<SrcState>();
     const size_t sj = (size_t)nsrc * J;
-    HIPCHK(ctx, ctx->shifts.ensure(sj * (4 * sizeof(double2) + sizeof(int))));
-    w.pi = ctx->shifts.as<double2>();
-    w.pi_prev = w.pi + sj;
-    w.pi_next = w.pi_prev + sj;
-    w.aj = w.pi_next + sj;
-    w.active = reinterpret_cast<int*>(w.aj + sj);
-    HIPCHK(ctx, ctx->lists.ensure(sj * (3 * sizeof(double2) + sizeof(int))));
-    w.lst_a = ctx->lists.as<double2>();
-    w.lst_ipi = w.lst_a + sj;
-    w.lst_b = w.lst_ipi + sj;
-    w.lst_j = reinterpret_cast<int*>(w.lst_b + sj);
+    HIPCHK(ctx, ctx->shifts.ensure(sj * (4 * sizeof(double2) + sizeof(double) + 2 * sizeof(int))));
+    ShiftDev& sh = w.sh;
+    sh.pi = ctx->shifts.as<double2>();          // [3][nsrc][J]
+    sh.aj = sh.pi + 3 * sj;
+    sh.res = reinterpret_cast<double*>(sh.aj + sj);
+    sh.active = reinterpret_cast<int*>(sh.res + sj);  // [2][nsrc][J]
+    sh.cnt = reinterpret_cast<int*>(ctx->state.as<char>() + state_cnt_off(nsrc));
+    sh.mres = reinterpret_cast<double*>(ctx->state.as<char>() + state_mres_off(nsrc));
+    sh.J = J;
+    sh.nsrc = nsrc;
+    sh.nslices = nslices;
+    sh.tol = ctx->tol;
+    sh.maxk = w.maxk;
     HIPCHK(ctx, ctx->nodes_dev.ensure((size_t)2 * J * sizeof(double2)));
     w.dz = ctx->nodes_dev.as<double2>();
     w.cj = w.dz + J;
+    sh.dz = w.dz;
+    sh.c = w.cj;
     std::vector<double2> tab(2 * J);
     for (int j = 0; j < J; ++j) {
         tab[j] = make_double2(ctx->z[j].x - ctx->zseed.x, ctx->z[j].y - ctx->zseed.y);
@@ -458,13 +537,15 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
         w.W = ctx->W.as<double2>();
         w.h = ctx->h.as<double2>();
     }
-    if (ctx->host_state_n < nsrc) {
+    sh.h_a = w.h_a;
+    sh.h_b = w.h_b;
+    sh.h_pi = w.h_pi;
+    if ((size_t)ctx->host_state_n < w.state_bytes) {
         if (ctx->host_state) (void)hipHostFree(ctx->host_state);
         ctx->host_state = nullptr;
         ctx->host_state_n = 0;
-        HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, nsrc * sizeof(SrcState),
-                                  hipHostMallocDefault));
-        ctx->host_state_n = nsrc;
+        HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, w.state_bytes, hipHostMallocDefault));
+        ctx->host_state_n = (int)w.state_bytes;
     }
     return OVL_OK;
 }
@@ -485,51 +566,41 @@ int ensure_slots(ovl_ctx* ctx, Work& w, int upto) {
     return OVL_OK;
 }
 
-// One seed iteration k in precision R (double before the switch, float after).
+// One seed iteration k in precision R (double before the switch, float after):
+// K1 stencil + <r,q>, K2 r update, K3 p update or shift sweep.
 template <typename R>
 void enqueue_iteration(ovl_ctx* ctx, const Work& w, int k, int form, hipStream_t s, C2<R>* r,
-                       C2<R>* p, C2<R>* q, C2<R>* pj, const C2<R>* U) {
+                       C2<R>* p, C2<R>* q, C2<R>* pj, const C2<R>* U, int nact_total) {
     const int64_t N = w.N;
-    const int nbw = wilson_blocks(ctx->g), nbe = elem_blocks(N);
     const bool basis = form == OVL_FORM_BASIS;
-    // r_k: working vector, or basis slot k (slot stride between sources is N either way
-    // for FP64; FP32 slots are packed at the slot base with the same N stride)
+    const double es = sizeof(C2<R>);
+    const int c32 = sizeof(R) == 4 ? 1 : 0;
+    const double V = (double)ctx->g.V;
+    // r_k: working vector, or basis slot k (FP32 slots are packed at the slot base)
     C2<R>* rk = basis ? slot_ptr<C2<R>>(w, k) : r;
     C2<R>* rk1 = basis ? slot_ptr<C2<R>>(w, k + 1) : r;
-    launch_wilson<R>(1, p, q, U, ctx->g, kappa_of(ctx->m0), ctx->zseed, rk, w.part_w, w.st,
-                     w.nsrc, s);
-    launch_alpha(w.st, w.part_w, nbw, w.dz, w.pi, w.pi_prev, w.pi_next, w.aj, w.active, w.J,
-                 w.nsrc, s);
-    launch_update_r<R>(rk, rk1, q, w.st, w.part_e, N, N, N, w.nsrc, s);
-    BetaArgs a;
-    a.st = w.st;
-    a.partial = w.part_e;
-    a.nblk = nbe;
-    a.c = (form == OVL_FORM_REFERENCE) ? nullptr : w.cj;
-    a.pi = w.pi;
-    a.pi_prev = w.pi_prev;
-    a.pi_next = w.pi_next;
-    a.aj = w.aj;
-    a.active = w.active;
-    a.J = w.J;
-    a.lst_j = w.lst_j;
-    a.lst_a = w.lst_a;
-    a.lst_ipi = w.lst_ipi;
-    a.lst_b = w.lst_b;
-    a.tol = ctx->tol;
-    a.h_a = basis ? w.h_a : nullptr;
-    a.h_b = basis ? w.h_b : nullptr;
-    a.h_pi = basis ? w.h_pi : nullptr;
-    a.maxk = w.maxk;
-    launch_beta(a, w.nsrc, s);
-    if (form == OVL_FORM_FUSED)
-        launch_sweep_fused<R>(r, p, pj, w.s64, w.b64, w.st, w.lst_j, w.lst_a, w.lst_ipi, w.lst_b,
-                              w.J, N, w.nsrc, k == 0, s);
-    else if (form == OVL_FORM_REFERENCE)
-        launch_sweep_ref<R>(r, p, pj, w.xj, w.b64, w.st, w.lst_j, w.lst_a, w.lst_ipi, w.lst_b,
-                            w.J, N, w.nsrc, k == 0, s);
-    else
-        launch_update_p<R>(rk1, p, w.st, N, N, w.nsrc, s);
+    {   // links once, p read, q written, r read for <r,q>
+        ProfScope ps(ctx, 0 + c32, V * es * (36.0 + 36.0 * w.nsrc));
+        launch_wilson<R>(1, p, q, U, ctx->g, kappa_of(ctx->m0), ctx->zseed, rk, w.part_w, w.st,
+                         &w.sh, k, w.nsrc, s);
+    }
+    {
+        ProfScope ps(ctx, 2 + c32, 3.0 * es * N * w.nsrc);
+        launch_update_r<R>(rk, rk1, q, w.st, w.part_w, w.nbw, w.part_e, w.nbe, N, w.sh, k, s);
+    }
+    if (basis) {
+        ProfScope ps(ctx, 2 + c32, 3.0 * es * N * w.nsrc);
+        launch_update_p<R>(rk1, p, w.st, w.part_e, w.nbe, N, w.sh, k, s);
+    } else {
+        // r read, p read+write, s read+write (FP64) per source; p_j read+write
+        // (and x_j read+write in FP64 for the reference form) per active shift
+        const bool ref = form == OVL_FORM_REFERENCE;
+        const double b = (double)N * (w.nsrc * (3.0 * es + (ref ? 0.0 : 32.0)) +
+                                      nact_total * (2.0 * es + (ref ? 32.0 : 0.0)));
+        ProfScope ps(ctx, 4 + c32, b);
+        launch_sweep<R>(ref, r, p, pj, ref ? w.xj : w.s64, w.b64, w.st, w.part_e, w.nbe, N, w.sh,
+                        k, s);
+    }
 }
 
 }  // namespace
@@ -559,8 +630,7 @@ static int solve(ovl_ctx* ctx, Work& w) {
     HIPCHK(ctx, hipMemcpyAsync(w.p64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
     if (form == OVL_FORM_FUSED) HIPCHK(ctx, hipMemsetAsync(w.s64, 0, vec64, s));
     if (form == OVL_FORM_REFERENCE) HIPCHK(ctx, hipMemsetAsync(w.xj, 0, vec64 * w.J, s));
-    launch_init_state(w.st, w.b64, w.part_e, N, w.pi, w.pi_prev, w.active, w.J,
-                      form == OVL_FORM_BASIS ? w.h_pi : nullptr, w.maxk, w.nsrc, s);
+    launch_init_state(w.st, w.b64, w.part_e, N, w.sh, s);
     HIPCHK(ctx, hipGetLastError());
 
     bool low = false;  // FP32 phase active
@@ -570,6 +640,7 @@ static int solve(ovl_ctx* ctx, Work& w) {
     int status = OVL_OK;
     double maxres = 1.0;
     int iters = 0, nact = 0;
+    int nact_known = w.J * w.nsrc;  // active shifts at the last poll (profiling bytes)
     while (k < w.maxk) {
         const int chunk = std::min(ctx->poll, w.maxk - k);
         if (form == OVL_FORM_BASIS) {
@@ -579,27 +650,36 @@ static int solve(ovl_ctx* ctx, Work& w) {
         for (int i = 0; i < chunk; ++i, ++k) {
             if (!low)
                 enqueue_iteration<double>(ctx, w, k, form, s, w.r64, w.p64, w.q64, w.pj64,
-                                          ctx->U64.as<double2>());
+                                          ctx->U64.as<double2>(), nact_known);
             else
                 enqueue_iteration<float>(ctx, w, k, form, s, w.r32, w.p32, w.q32, w.pj32,
-                                         ctx->U32.as<float2>());
+                                         ctx->U32.as<float2>(), nact_known);
         }
         HIPCHK(ctx, hipGetLastError());
-        HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, w.st, w.nsrc * sizeof(SrcState),
-                                   hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, w.st, w.state_bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
+        prof_collect(ctx);
         all_done = true;
         maxres = 0.0;
         iters = 0;
         nact = 0;
+        const char* hb = reinterpret_cast<const char*>(ctx->host_state);
+        const int* hcnt = reinterpret_cast<const int*>(hb + state_cnt_off(w.nsrc)) +
+                          (size_t)(k & 1) * w.nsrc * kMaxSlices;
+        const double* hmres = reinterpret_cast<const double*>(hb + state_mres_off(w.nsrc));
         for (int n = 0; n < w.nsrc; ++n) {
             const SrcState& S = ctx->host_state[n];
             if (S.status != OVL_OK && status == OVL_OK) status = S.status;
-            all_done = all_done && S.done;
-            maxres = std::max(maxres, S.maxres);
+            int na = 0;
+            for (int i = 0; i < w.sh.nslices; ++i) {
+                na += hcnt[n * kMaxSlices + i];
+                maxres = std::max(maxres, hmres[n * kMaxSlices + i]);
+            }
+            all_done = all_done && (na == 0 || S.status != OVL_OK);
             iters = std::max(iters, S.iter);
-            nact += S.nact;
+            nact += na;
         }
+        nact_known = nact;
         if (status != OVL_OK || all_done) break;
         if (mixed && !low && maxres < ctx->switch_res && k < w.maxk) {
             // relaxed precision: from here the remaining corrections are small
@@ -634,12 +714,14 @@ static int solve(ovl_ctx* ctx, Work& w) {
                 char* base = w.chunks[c0 / kSlotChunk];
                 const int a0 = c0, a1 = std::min(c1, ksw);
                 if (a1 > a0) {
+                    ProfScope ps(ctx, 6, (double)N * w.nsrc * (16.0 * (a1 - a0) + 32.0));
                     launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.maxk, w.st, c0,
                                               a0 - c0, a1 - c0, w.s64, acc, N, w.nsrc, s);
                     acc = true;
                 }
                 const int f0 = std::max(c0, ksw), f1 = c1;
                 if (f1 > f0) {
+                    ProfScope ps(ctx, 6, (double)N * w.nsrc * (8.0 * (f1 - f0) + 32.0));
                     launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.maxk, w.st,
                                              c0, f0 - c0, f1 - c0, w.s64, acc, N, w.nsrc, s);
                     acc = true;
@@ -650,6 +732,7 @@ static int solve(ovl_ctx* ctx, Work& w) {
     }
     HIPCHK(ctx, hipEventRecord(e1, s));
     HIPCHK(ctx, hipEventSynchronize(e1));
+    prof_collect(ctx);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
@@ -736,11 +819,11 @@ extern "C" int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32
         if (f32)
             launch_wilson<float>(0, ctx->bench_a.as<float2>(), ctx->bench_b.as<float2>(),
                                  ctx->U32.as<float2>(), ctx->g, kappa_of(ctx->m0),
-                                 make_double2(0, 0), nullptr, nullptr, nullptr, nrhs, ctx->stream);
+                                 make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream);
         else
             launch_wilson<double>(0, ctx->bench_a.as<double2>(), ctx->bench_b.as<double2>(),
                                   ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0),
-                                  make_double2(0, 0), nullptr, nullptr, nullptr, nrhs, ctx->stream);
+                                  make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream);
     };
     launch();
     HIPCHK(ctx, hipGetLastError());

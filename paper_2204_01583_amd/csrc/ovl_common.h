@@ -22,6 +22,19 @@ template <typename R> __device__ __forceinline__ cx<R> ld(const C2<R>* p, int64_
     C2<R> v = p[i];
     return cx<R>{v.x, v.y};
 }
+// 32-bit element index from a wave-uniform base: the byte offset is formed
+// in 32 bits, so the load can use a scalar base plus one VGPR offset.
+template <typename R> __device__ __forceinline__ cx<R> ld(const C2<R>* p, uint32_t i) {
+    const uint32_t off = i * (uint32_t)sizeof(C2<R>);
+    C2<R> v = *reinterpret_cast<const C2<R>*>(reinterpret_cast<const char*>(p) + off);
+    return cx<R>{v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ void stc(C2<R>* p, uint32_t i, cx<R> v) {
+    C2<R> w; w.x = v.re; w.y = v.im;
+    const uint32_t off = i * (uint32_t)sizeof(C2<R>);
+    *reinterpret_cast<C2<R>*>(reinterpret_cast<char*>(p) + off) = w;
+}
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 template <typename R> __device__ __forceinline__ void stc(C2<R>* p, int64_t i, cx<R> v) {
     C2<R> w; w.x = v.re; w.y = v.im;
     p[i] = w;
@@ -64,20 +77,35 @@ struct Geom {
 constexpr int kBlock = 256;           // threads per block of the site kernels
 constexpr int kMaxShifts = 1024;      // shifted systems per apply
 
-// Per-source solver state in device memory (one struct per right-hand side).
+constexpr int kMaxSlices = kMaxShifts / 256;  // 256-shift slices
+
+// Per-source scalar state of the seed recurrence, in device memory.  Values
+// produced in iteration k are stored at parity k&1 (see kernels.hip).
 struct SrcState {
-    double rr;          // ||r_k||^2 of the seed residual
     double bb;          // ||b||^2
-    double2 alpha;      // alpha_k
-    double2 alpha_prev; // alpha_{k-1}
-    double2 beta_prev;  // beta_{k-1}
-    double maxres;      // max over active shifts of ||r_j|| / ||b|| (estimate)
+    double rr[2];       // ||r_k||^2 at [k&1]
+    double2 alpha[2];   // alpha_k at [k&1]
+    double2 beta[2];    // beta_k at [k&1]
     int iter;           // iterations done
-    int nact;           // shifts still active
-    int done;           // 1 when no shift is active or on error
     int status;         // OVL_OK / error code
-    int nlist;          // entries in this iteration's sweep list
-    int pad;
+    int pad[2];
+};
+
+// Device arrays of the shifted systems (all [..][nsrc][J] unless noted).
+struct ShiftDev {
+    double2* pi;        // [3][nsrc][J]: pi_k^j at [k%3]
+    int* active;        // [2][nsrc][J]: shift active at the start of iteration k, at [k&1]
+    double2* aj;        // alpha^j of the current iteration
+    double* res;        // latest residual estimate ||r_j|| / ||b||
+    int* cnt;           // [2][nsrc][kMaxSlices]: active shifts per slice at [k&1]
+    double* mres;       // [nsrc][kMaxSlices]: max residual estimate per slice
+    const double2* dz;  // [J] z_j - z_seed
+    const double2* c;   // [J] quadrature weights
+    int J, nsrc, nslices;
+    double tol;
+    // basis forms, may be null: [nsrc][maxk+1][J]
+    double2 *h_a, *h_b, *h_pi;
+    int maxk;
 };
 
 }  // namespace ovl

@@ -27,8 +27,11 @@ EXPORTS = [
     "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
     "ovl_set_contour", "ovl_set_nodes", "ovl_set_solver", "ovl_apply_hw", "ovl_apply_sign",
     "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
-    "ovl_bench_kernel", "ovl_status_string", "ovl_last_error",
+    "ovl_bench_kernel", "ovl_set_profiling", "ovl_get_profile", "ovl_status_string",
+    "ovl_last_error",
 ]
+PROFILE_CLASSES = ["stencil64", "stencil32", "vector64", "vector32", "sweep64", "sweep32",
+                   "basis_sum", "scalars"]
 
 
 class Stats(ctypes.Structure):
@@ -82,6 +85,9 @@ def load():
                                     ctypes.POINTER(I), ctypes.POINTER(Stats)], I),
         "ovl_get_stats": ([P, ctypes.POINTER(Stats)], I),
         "ovl_bench_kernel": ([P, I, I, I, ctypes.POINTER(D), ctypes.POINTER(D)], I),
+        "ovl_set_profiling": ([P, I], I),
+        "ovl_get_profile": ([P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(D)], I),
         "ovl_status_string": ([I], ctypes.c_char_p),
         "ovl_last_error": ([P], ctypes.c_char_p),
     }
@@ -225,6 +231,19 @@ class Context:
         self._rc(self.lib.ovl_bench_kernel(self._h, int(which), int(nrhs), int(reps),
                                            ctypes.byref(ms), ctypes.byref(nb)), "ovl_bench_kernel")
         return ms.value, nb.value
+
+    def set_profiling(self, on=True):
+        self._rc(self.lib.ovl_set_profiling(self._h, 1 if on else 0), "ovl_set_profiling")
+
+    def profile(self):
+        """{class: (total_ms, launches, algorithmic_bytes)} since set_profiling(True)."""
+        out = {}
+        for k, name in enumerate(PROFILE_CLASSES):
+            ms, n, nb = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+            self._rc(self.lib.ovl_get_profile(self._h, k, ctypes.byref(ms), ctypes.byref(n),
+                                              ctypes.byref(nb)), "ovl_get_profile")
+            out[name] = (ms.value, n.value, nb.value)
+        return out
 
     def stats(self):
         st = Stats()
