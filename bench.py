@@ -74,6 +74,26 @@ def roofline_from_profile(prof):
     }
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_stencil32_insolver_16x16x16x16_n4.json")
+
+
+def measured_traffic(variant32):
+    """HBM bytes per launch of the in-solver FP32 stencil from the committed
+    rocprofv3 counter summary, or None if that kernel (source or variant) has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(COUNTERS))
+        src = open(os.path.join(ROOT, "paper_2204_01583_amd", "csrc", "stencil.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
+        return None
+    if rec.get("variant") != variant32:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(U, B, nsample):
     """The FP64 oracle (independent GMRES solve per node) on a stratified sample
     of the 256 shifted systems of source 0, one node per host core."""
@@ -114,6 +134,9 @@ def main():
     ap.add_argument("--only-steps", action="store_true",
                     help="only the warm-up and timed steps (for profiler runs)")
     ap.add_argument("--cpu-nodes", type=int, default=16)
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="copy this many GiB once before the steps (reference kernel of known "
+                         "size for scaling the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path shards over contour nodes with one "
@@ -126,6 +149,14 @@ def main():
     ctx, Ud, Bd, U, B = setup(torch, ovl)
     ctx.set_solver(ovl.PREC_MIXED, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=SWITCH)
 
+    if args.calib_copy_gib > 0:
+        nel = int(args.calib_copy_gib * 2 ** 30 / 8)
+        a = torch.ones(nel, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"calibration copy of {args.calib_copy_gib} GiB done")
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         out, st = ctx.apply_dov(Bd)
@@ -168,6 +199,9 @@ def main():
     prof = ctx.profile()
     ctx.set_profiling(False)
     name, roof = roofline_from_profile(prof)
+    if name == "stencil32":
+        roof["traffic"] = measured_traffic(st.stencil_variant32)
+    roof["stencil_variant"] = st.stencil_variant32 if name.endswith("32") else st.stencil_variant64
     rec["roofline"] = roof
     rec["kernel_profile"] = {k: {"ms": round(v[0], 3), "launches": v[1],
                                  "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}

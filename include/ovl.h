@@ -76,7 +76,9 @@ typedef struct {
     int32_t n_active_end;      /* shifts still above tolerance at the end (0 if converged)   */
     double  max_est_rel_res;   /* max_j ||r_j|| / ||b|| from the recurrence, at the end      */
     double  seconds;           /* wall time of the apply on the stream                       */
-    double  reserved[4];
+    int32_t stencil_variant64; /* stencil variant used in FP64 (autotuned, see ovl_bench_kernel) */
+    int32_t stencil_variant32; /* ... in FP32, or -1                                        */
+    double  reserved[3];
 } ovl_stats;
 
 /* Create a context for a Lx*Ly*Lz*Lt lattice on HIP device `device`.
@@ -155,8 +157,15 @@ int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
 /* Time one internal kernel on the context's stream with HIP events: `reps`
  * back-to-back launches after one warm-up, average milliseconds in *avg_ms
  * and the algorithmic bytes of one launch in *bytes.  which:
- *   0: FP64 stencil on nrhs internal spinors   1: FP32 stencil
- *   2: FP64 fused shift sweep, nrhs sources x all shifts   3: its FP32 form
+ *   0: FP64 stencil (out = H_W in) on nrhs internal spinors, autotuned variant
+ *   1: the same in FP32
+ *   100+v, 200+v: FP64 / FP32 stencil variant v (0..7),
+ *      v = 4*order + 2*(rhs per lane - 1) + (hops per loop step - 1): one or
+ *      both hops of a direction per step, one or two rhs per lane sharing each
+ *      link load, blocks ordered rhs-fastest (0) or site-fastest (1).
+ * The first use of a (lattice, nrhs, precision) picks the fastest variant by
+ * timing all eight; OVL_STENCIL_VARIANT=v forces one, OVL_AUTOTUNE=0 keeps 0,
+ * OVL_AUTOTUNE_CACHE=path persists the choices as a JSON object.
  * Buffers are internal scratch (contents arbitrary but finite). */
 int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
                      double* avg_ms, double* bytes);

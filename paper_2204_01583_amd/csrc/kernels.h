@@ -22,10 +22,15 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 // out = H_W in                                               (mode 0)
 // out = zs*in - H_W in, partial[src][blk] = <r,out> (mode 1); sources that are
 // not live at iteration k (see kernels.hip) are skipped.
+// variant v = 4*order + 2*(rhs per lane - 1) + (hops per loop step - 1):
+// hops per step 1 or 2 (both directions of one mu), 1 or 2 rhs per lane
+// sharing each link load, block order 0 (rhs fastest) or 1 (sites fastest).
+constexpr int kStencilVariants = 8;
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                    double kappa, double2 zs, const C2<R>* r, double2* partial,
-                   const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s);
+                   const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s,
+                   int variant = 0);
 int wilson_blocks(const Geom& g);
 
 // ---- seed iteration k, kernels K2 and K3 (vector grids of nbe blocks/source) --

@@ -1,50 +1,14 @@
-// HIP kernels for gfx950: layout conversion, the hermitian Wilson stencil,
-// deterministic Krylov reductions, shifted-system scalars and the shift
-// sweeps.  Everything here is bandwidth bound (no dense contraction), so the
-// kernels are written for coalesced structure-of-arrays access: one lane per
-// site (stencil) or per complex component (vector kernels).
+// HIP kernels for gfx950: layout conversion, the seed iteration's vector
+// kernels with their deterministic reductions and shifted-system scalars, the
+// shift sweeps and the basis-form sum.  Everything here is bandwidth bound (no
+// dense contraction), so the kernels stream structure-of-arrays vectors with
+// one lane per complex component.  The stencil is in stencil.hip.
 #include <hip/hip_runtime.h>
 
+#include "device_util.h"
 #include "kernels.h"
-#include "../../include/ovl.h"
 
 namespace ovl {
-
-// ============================================================================
-// reductions (fixed order: butterfly within a wave, serial over waves)
-// ============================================================================
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) t += sh[i];
-    __syncthreads();
-    return t;
-}
-
-template <int NT>
-__device__ __forceinline__ double block_max(double v, double* sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) t = fmax(t, sh[i]);
-    __syncthreads();
-    return t;
-}
 
 // ============================================================================
 // layout conversion
@@ -159,230 +123,6 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 }
 
 // ============================================================================
-// Wilson stencil
-// ============================================================================
-// Chiral basis: gamma_mu = [[0, A_mu], [A_mu^dag, 0]] with A_k = -i sigma_k,
-// A_4 = 1.  For the lower half-spinor d = (psi_2, psi_3):
-//   (1 -+ gamma_mu) psi = [ h ; -+ A^dag h ],  h = psi_up -+ A_mu d,
-// so each hop moves a 2-spin x 3-colour half-spinor through the link.
-
-// h = psi_up - A d (forward, sg = -1) or psi_up + A d (backward, sg = +1)
-template <typename R>
-__device__ __forceinline__ void project(int mu, R sg, cx<R> p0, cx<R> p1, cx<R> p2, cx<R> p3,
-                                        cx<R>& h0, cx<R>& h1) {
-    cx<R> a0, a1;  // A_mu (p2, p3)
-    switch (mu) {
-        case 0: a0 = tmi(p3); a1 = tmi(p2); break;
-        case 1: a0 = -p3; a1 = p2; break;
-        case 2: a0 = tmi(p2); a1 = ti(p3); break;
-        default: a0 = p2; a1 = p3; break;
-    }
-    h0 = p0 + sg * a0;
-    h1 = p1 + sg * a1;
-}
-
-// acc_up += u ; acc_dn += sg * A_mu^dag u
-template <typename R>
-__device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
-                                            const cx<R> (&u)[2][3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const cx<R> u0 = u[0][c], u1 = u[1][c];
-        cx<R> b0, b1;  // A^dag (u0, u1)
-        switch (mu) {
-            case 0: b0 = ti(u1); b1 = ti(u0); break;
-            case 1: b0 = u1; b1 = -u0; break;
-            case 2: b0 = ti(u0); b1 = tmi(u1); break;
-            default: b0 = u0; b1 = u1; break;
-        }
-        acc[0][c] = acc[0][c] + u0;
-        acc[1][c] = acc[1][c] + u1;
-        acc[2][c] = acc[2][c] + sg * b0;
-        acc[3][c] = acc[3][c] + sg * b1;
-    }
-}
-
-// One hop: project the neighbour spinor to a half-spinor, move it through
-// the link (U_mu(x) forward, U_mu(x-mu)^dag backward), reconstruct into acc.
-// Per-lane offsets are 32-bit element indices from uniform base pointers.
-template <typename R>
-__device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[4][3],
-                                    const C2<R>* __restrict__ psi, const C2<R>* __restrict__ Um,
-                                    uint32_t V, uint32_t nb, uint32_t lsite) {
-    const R sg = fwd ? R(-1) : R(1);
-    cx<R> h[2][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const cx<R> p0 = ld<R>(psi, (uint32_t)(0 + c) * V + nb), p1 = ld<R>(psi, (uint32_t)(3 + c) * V + nb);
-        const cx<R> p2 = ld<R>(psi, (uint32_t)(6 + c) * V + nb), p3 = ld<R>(psi, (uint32_t)(9 + c) * V + nb);
-        project<R>(mu, sg, p0, p1, p2, p3, h[0][c], h[1][c]);
-    }
-    // element (a,b) of the hop matrix: U[a][b] forward, conj(U[b][a]) backward
-    const R ci = fwd ? R(1) : R(-1);
-    cx<R> u[2][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        u[0][a] = mk<R>(0, 0);
-        u[1][a] = mk<R>(0, 0);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const uint32_t e = fwd ? (uint32_t)(3 * a + b) : (uint32_t)(3 * b + a);
-            cx<R> l = ld<R>(Um, e * V + lsite);
-            l.im *= ci;
-            fma_(u[0][a], l, h[0][b]);
-            fma_(u[1][a], l, h[1][b]);
-        }
-    }
-    reconstruct<R>(mu, sg, acc, u);
-}
-
-// acc = sum over the 8 hops.  The hop loop is kept rolled so that one hop's
-// loads are live at a time (unrolled, the scheduler hoists every neighbour's
-// loads and the kernel spills).
-template <typename R>
-__device__ __forceinline__ void dslash_site(cx<R> (&acc)[4][3], const C2<R>* __restrict__ psi,
-                                            const C2<R>* __restrict__ U, const Geom& g,
-                                            uint32_t s, const int (&coord)[4]) {
-    const uint32_t V = (uint32_t)g.V;
-#pragma unroll 1
-    for (int d = 0; d < 8; ++d) {
-        const int mu = d >> 1;
-        const bool fwd = (d & 1) == 0;
-        const uint32_t sd = (uint32_t)g.stride[mu];
-        const int L = g.L[mu];
-        const int cm = coord[mu];
-        uint32_t nb;
-        if (fwd) nb = (cm == L - 1) ? s - (uint32_t)(L - 1) * sd : s + sd;
-        else nb = (cm == 0) ? s + (uint32_t)(L - 1) * sd : s - sd;
-        hop<R>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb);
-    }
-}
-
-__device__ __forceinline__ bool src_live(const SrcState& S, const ShiftDev& sh, int n, int k);
-
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Remap the linear block id so that XCD k works on one contiguous range of
-// (rhs, site tile): the z and t neighbours of a tile then sit in the same L2.
-__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
-    const unsigned per = nb / 8u;
-    return (b < per * 8u) ? (b % 8u) * per + b / 8u : b;
-}
-
-template <typename R, int MODE>
-__global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
-                                                   C2<R>* __restrict__ out,
-                                                   const C2<R>* __restrict__ U, Geom g, R kappa,
-                                                   double zsr, double zsi,
-                                                   const C2<R>* __restrict__ rdot,
-                                                   double2* __restrict__ partial,
-                                                   const SrcState* __restrict__ stt,
-                                                   ShiftDev sh, int k, int nsb, int nrhs) {
-    // rhs fastest: the blocks of one site tile (all rhs) run back to back on
-    // one XCD and share its links through L2
-    const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
-    const int n = (int)uniform(tile % (unsigned)nrhs);
-    const int sb = (int)uniform(tile / (unsigned)nrhs);
-    if constexpr (MODE == 1) {
-        if (!src_live(stt[n], sh, n, k)) return;
-    }
-    const uint32_t V = (uint32_t)g.V;
-    const uint32_t s = (uint32_t)sb * kBlock + threadIdx.x;
-    const bool valid = s < V;
-    double dre = 0.0, dim = 0.0;
-    if (valid) {
-        const C2<R>* psi = in + (size_t)n * 12 * V;
-        uint32_t rem = s;
-        int coord[4];
-        coord[0] = (int)(rem % (uint32_t)g.L[0]); rem /= (uint32_t)g.L[0];
-        coord[1] = (int)(rem % (uint32_t)g.L[1]); rem /= (uint32_t)g.L[1];
-        coord[2] = (int)(rem % (uint32_t)g.L[2]);
-        coord[3] = (int)(rem / (uint32_t)g.L[2]);
-        cx<R> acc[4][3];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[a][c] = mk<R>(0, 0);
-        dslash_site<R>(acc, psi, U, g, s, coord);
-        C2<R>* o = out + (size_t)n * 12 * V;
-        const C2<R>* rd = (MODE == 1) ? rdot + (size_t)n * 12 * V : nullptr;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int comp = 3 * a + c;
-                const cx<R> p = ld<R>(psi, (uint32_t)comp * V + s);
-                // D psi = psi - kappa acc ; H = gamma5 D
-                cx<R> hv = p - kappa * acc[a][c];
-                if (a >= 2) hv = -hv;
-                if constexpr (MODE == 0) {
-                    stc<R>(o, (uint32_t)comp * V + s, hv);
-                } else {
-                    // q = zs p - H p
-                    const R zr = (R)zsr, zi = (R)zsi;
-                    cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
-                    stc<R>(o, (uint32_t)comp * V + s, q);
-                    const cx<R> r = ld<R>(rd, (uint32_t)comp * V + s);
-                    // <r, q> = sum conj(r) q, accumulated in FP64
-                    dre += (double)r.re * (double)q.re + (double)r.im * (double)q.im;
-                    dim += (double)r.re * (double)q.im - (double)r.im * (double)q.re;
-                }
-            }
-        }
-    }
-    if constexpr (MODE == 1) {
-        __shared__ double sh[kBlock / 64];
-        const double tr = block_sum<kBlock>(dre, sh);
-        const double ti_ = block_sum<kBlock>(dim, sh);
-        if (threadIdx.x == 0) partial[(int64_t)n * nsb + sb] = make_double2(tr, ti_);
-    }
-}
-
-int wilson_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
-
-template <typename R>
-void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
-                   double kappa, double2 zs, const C2<R>* r, double2* partial,
-                   const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s) {
-    ShiftDev none{};
-    const ShiftDev& shv = sh ? *sh : none;
-    const int nsb = wilson_blocks(g);
-    dim3 grid((unsigned)nsb * (unsigned)nrhs);
-    if (mode == 0)
-        hipLaunchKernelGGL((k_wilson<R, 0>), grid, dim3(kBlock), 0, s, in, out, U, g, (R)kappa,
-                           zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
-    else
-        hipLaunchKernelGGL((k_wilson<R, 1>), grid, dim3(kBlock), 0, s, in, out, U, g, (R)kappa,
-                           zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
-}
-template void launch_wilson<double>(int, const double2*, double2*, const double2*, const Geom&,
-                                    double, double2, const double2*, double2*, const SrcState*,
-                                    const ShiftDev*, int, int, hipStream_t);
-template void launch_wilson<float>(int, const float2*, float2*, const float2*, const Geom&,
-                                   double, double2, const float2*, double2*, const SrcState*,
-                                   const ShiftDev*, int, int, hipStream_t);
-
-// ============================================================================
-// complex helpers (FP64 scalars)
-// ============================================================================
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-    // Smith's algorithm keeps the quotient finite for |b| far from 1
-    if (fabs(b.x) >= fabs(b.y)) {
-        const double r = b.y / b.x, d = b.x + b.y * r;
-        return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
-    } else {
-        const double r = b.x / b.y, d = b.x * r + b.y;
-        return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
-    }
-}
-__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
-__device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
-
-// ============================================================================
 // The seed iteration k is three kernels:
 //   K1  q = z_s p - H p and per-block <r, q>                (k_wilson, mode 1)
 //   K2  alpha_k (every block, from K1's partials), shifted pi_{k+1}, alpha^j
@@ -397,13 +137,6 @@ __device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isf
 //   cnt[k&1][slice] = active shifts per 256-shift slice (a source is live at
 //   iteration k while status == 0 and some count is nonzero).
 // ============================================================================
-__device__ __forceinline__ bool src_live(const SrcState& S, const ShiftDev& sh, int n, int k) {
-    if (S.status != 0) return false;
-    const int* c = sh.cnt + ((size_t)(k & 1) * sh.nsrc + n) * kMaxSlices;
-    int t = 0;
-    for (int i = 0; i < sh.nslices; ++i) t += c[i];
-    return t > 0;
-}
 
 // sum of partial[0..nb) in a fixed order (strided per lane, then block_sum)
 template <typename T>

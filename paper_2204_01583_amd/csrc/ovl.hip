@@ -4,6 +4,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -76,6 +80,8 @@ struct ovl_ctx {
     double prof_ms[kClasses] = {0};
     int64_t prof_n[kClasses] = {0};
     double prof_bytes[kClasses] = {0};
+    // stencil variant chosen per (nrhs, precision) by the autotuner
+    std::map<std::pair<int, int>, int> stencil_variant;
     ovl_stats last{};
     char err[512] = {0};
 };
@@ -368,6 +374,152 @@ extern "C" const char* ovl_status_string(int s) {
 }
 
 // ============================================================================
+// stencil autotuner
+// ============================================================================
+// The four stencil variants trade registers for loads in flight; which one
+// wins depends on the lattice volume, the number of right-hand sides and the
+// precision (how many waves the launch can keep resident).  The first use of a
+// (lattice, nrhs, precision) times each variant with HIP events on the
+// context's stream and keeps the fastest.  OVL_STENCIL_VARIANT=v forces a
+// variant; OVL_AUTOTUNE=0 keeps variant 0; OVL_AUTOTUNE_CACHE=path keeps the
+// choices in a flat JSON object {"key": variant} shared by processes.
+namespace {
+
+std::mutex g_tune_mu;
+
+std::string tune_key(const ovl_ctx* ctx, int nrhs, int prec) {
+    hipDeviceProp_t prop;
+    const char* arch = "gpu";
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+    int rt = 0;
+    (void)hipRuntimeGetVersion(&rt);
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|hip%d|%dx%dx%dx%d|n%d|%s", arch, rt, ctx->g.L[0], ctx->g.L[1],
+             ctx->g.L[2], ctx->g.L[3], nrhs, prec ? "fp32" : "fp64");
+    std::string k(buf);
+    for (char& c : k)
+        if (c == '"' || c == '\\') c = '_';
+    return k;
+}
+
+std::map<std::string, int> read_cache(const char* path) {
+    std::map<std::string, int> m;
+    FILE* f = fopen(path, "r");
+    if (!f) return m;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, n);
+    fclose(f);
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+        const size_t j = txt.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const size_t c = txt.find(':', j);
+        if (c == std::string::npos) break;
+        m[txt.substr(i + 1, j - i - 1)] = atoi(txt.c_str() + c + 1);
+        i = txt.find_first_of(",}", c);
+        if (i == std::string::npos) break;
+    }
+    return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, int>& m) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{");
+    bool first = true;
+    for (const auto& kv : m) {
+        fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+        first = false;
+    }
+    fprintf(f, "\n}\n");
+    fclose(f);
+    (void)rename(tmp.c_str(), path);
+}
+
+template <typename R>
+double time_variant(ovl_ctx* ctx, int v, int nrhs, C2<R>* a, C2<R>* b, const C2<R>* U) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 1e30;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return 1e30;
+    }
+    auto run = [&]() {
+        launch_wilson<R>(0, a, b, U, ctx->g, kappa_of(ctx->m0), make_double2(0, 0), nullptr, nullptr,
+                         nullptr, nullptr, 0, nrhs, ctx->stream, v);
+    };
+    run();
+    const int reps = 4;
+    float best = 1e30f;
+    for (int trial = 0; trial < 3; ++trial) {  // best of 3 trials damps timing noise
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int i = 0; i < reps; ++i) run();
+        (void)hipEventRecord(e1, ctx->stream);
+        float ms = 1e30f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            ms = 1e30f;
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best / reps;
+}
+
+}  // namespace
+
+// Variant of the stencil for nrhs right-hand sides in precision prec (0 FP64, 1 FP32).
+static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec) {
+    const char* force = getenv("OVL_STENCIL_VARIANT");
+    if (force && *force) {
+        const int v = atoi(force);
+        if (v >= 0 && v < kStencilVariants) return v;
+    }
+    const auto key = std::make_pair(nrhs, prec);
+    auto it = ctx->stencil_variant.find(key);
+    if (it != ctx->stencil_variant.end()) return it->second;
+    const char* at = getenv("OVL_AUTOTUNE");
+    if (at && at[0] == '0') return ctx->stencil_variant[key] = 0;
+    const char* path = getenv("OVL_AUTOTUNE_CACHE");
+    const std::string k = tune_key(ctx, nrhs, prec);
+    if (path && *path) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto m = read_cache(path);
+        auto f = m.find(k);
+        if (f != m.end() && f->second >= 0 && f->second < kStencilVariants)
+            return ctx->stencil_variant[key] = f->second;
+    }
+    const size_t es = prec ? sizeof(float2) : sizeof(double2);
+    const size_t nb = (size_t)nrhs * n12(ctx) * es;
+    int best = 0;
+    if (ctx->bench_a.ensure(nb) == hipSuccess && ctx->bench_b.ensure(nb) == hipSuccess &&
+        hipMemsetAsync(ctx->bench_a.p, 0, nb, ctx->stream) == hipSuccess) {
+        double tbest = 1e30;
+        for (int v = 0; v < kStencilVariants; ++v) {
+            const double t = prec ? time_variant<float>(ctx, v, nrhs, ctx->bench_a.as<float2>(),
+                                                        ctx->bench_b.as<float2>(), ctx->U32.as<float2>())
+                                  : time_variant<double>(ctx, v, nrhs, ctx->bench_a.as<double2>(),
+                                                         ctx->bench_b.as<double2>(), ctx->U64.as<double2>());
+            if (t < tbest) {
+                tbest = t;
+                best = v;
+            }
+        }
+    }
+    (void)hipGetLastError();
+    ctx->stencil_variant[key] = best;
+    if (path && *path) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto m = read_cache(path);
+        m[k] = best;
+        write_cache(path, m);
+    }
+    return best;
+}
+
+// ============================================================================
 // H_W
 // ============================================================================
 static int check_apply_args(ovl_ctx* ctx, const void* in, const void* out, int nrhs,
@@ -396,9 +548,10 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
     HIPCHK(ctx, ctx->hw_out.ensure(nb));
     launch_pack_spinor64(static_cast<const double2*>(in), ctx->hw_in.as<double2>(), ctx->g.V,
                          nrhs, ctx->stream);
+    const int var = stencil_variant(ctx, nrhs, 0);
     launch_wilson<double>(0, ctx->hw_in.as<double2>(), ctx->hw_out.as<double2>(),
                           ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0), make_double2(0, 0),
-                          nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream);
+                          nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, var);
     launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, nrhs,
                            ctx->stream);
     HIPCHK(ctx, hipGetLastError());
@@ -425,6 +578,7 @@ struct Work {
     SrcState* st;          // device state block: st | cnt | mres (one copy to the host)
     size_t state_bytes;
     ShiftDev sh;
+    int var64, var32;      // stencil variants (autotuned)
     double2 *dz, *cj;
     double2 *h_a, *h_b, *h_pi, *W, *h;
 };
@@ -582,7 +736,7 @@ void enqueue_iteration(ovl_ctx* ctx, const Work& w, int k, int form, hipStream_t
     {   // links once, p read, q written, r read for <r,q>
         ProfScope ps(ctx, 0 + c32, V * es * (36.0 + 36.0 * w.nsrc));
         launch_wilson<R>(1, p, q, U, ctx->g, kappa_of(ctx->m0), ctx->zseed, rk, w.part_w, w.st,
-                         &w.sh, k, w.nsrc, s);
+                         &w.sh, k, w.nsrc, s, c32 ? w.var32 : w.var64);
     }
     {
         ProfScope ps(ctx, 2 + c32, 3.0 * es * N * w.nsrc);
@@ -613,6 +767,8 @@ static int solve(ovl_ctx* ctx, Work& w) {
     const bool mixed = ctx->precision == OVL_PREC_MIXED;
     const int64_t N = w.N;
     const size_t vec64 = (size_t)w.nsrc * N * sizeof(double2);
+    w.var64 = stencil_variant(ctx, w.nsrc, 0);
+    w.var32 = mixed ? stencil_variant(ctx, w.nsrc, 1) : 0;
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
@@ -745,6 +901,8 @@ static int solve(ovl_ctx* ctx, Work& w) {
     L.n_active_end = nact;
     L.max_est_rel_res = maxres;
     L.seconds = ms * 1e-3;
+    L.stencil_variant64 = w.var64;
+    L.stencil_variant32 = mixed ? w.var32 : -1;
     if (status < 0) fail(ctx, status, "solver stopped: %s", ovl_status_string(status));
     if (status == OVL_NOT_CONVERGED)
         fail(ctx, status, "maxiter=%d reached with %d shifts above tol (max est. res %.3e)",
@@ -804,14 +962,18 @@ extern "C" int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const 
 extern "C" int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
                                 double* avg_ms, double* bytes) {
     if (!ctx || !avg_ms || !bytes) return OVL_E_ARG;
-    if (nrhs < 1 || reps < 1 || which < 0 || which > 1)
+    // which 0/1: FP64/FP32 stencil with the autotuned variant; 100+v / 200+v: FP64/FP32 variant v
+    const bool explicit_v = (which >= 100 && which < 100 + kStencilVariants) ||
+                            (which >= 200 && which < 200 + kStencilVariants);
+    if (nrhs < 1 || reps < 1 || !(which == 0 || which == 1 || explicit_v))
         return fail(ctx, OVL_E_ARG, "bad bench arguments");
     if (!ctx->gauge_set || !ctx->masses_set) return fail(ctx, OVL_E_STATE, "gauge/masses not set");
     DeviceGuard dg(ctx->device);
     const int64_t N = n12(ctx);
-    const bool f32 = which == 1;
+    const bool f32 = which == 1 || which >= 200;
     const size_t es = f32 ? sizeof(float2) : sizeof(double2);
     const size_t nb = (size_t)nrhs * N * es;
+    const int var = explicit_v ? which % 100 : stencil_variant(ctx, nrhs, f32 ? 1 : 0);
     HIPCHK(ctx, ctx->bench_a.ensure(nb));
     HIPCHK(ctx, ctx->bench_b.ensure(nb));
     HIPCHK(ctx, hipMemsetAsync(ctx->bench_a.p, 0, nb, ctx->stream));
@@ -819,11 +981,11 @@ extern "C" int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32
         if (f32)
             launch_wilson<float>(0, ctx->bench_a.as<float2>(), ctx->bench_b.as<float2>(),
                                  ctx->U32.as<float2>(), ctx->g, kappa_of(ctx->m0),
-                                 make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream);
+                                 make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, var);
         else
             launch_wilson<double>(0, ctx->bench_a.as<double2>(), ctx->bench_b.as<double2>(),
                                   ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0),
-                                  make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream);
+                                  make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, var);
     };
     launch();
     HIPCHK(ctx, hipGetLastError());

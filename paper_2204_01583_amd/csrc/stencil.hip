@@ -1,0 +1,279 @@
+// The hermitian Wilson stencil H_W = gamma5 D_W(-m0) for gfx950 (HIP).
+// Bandwidth bound (at most ~3.6 flop per algorithmic byte in FP64), so no
+// matrix cores: one lane per site (and rhs), structure-of-arrays spinors and
+// links, 32-bit offsets from uniform bases, an XCD-aware block order, and
+// eight register/latency trade-off variants chosen by the autotuner.
+#include <hip/hip_runtime.h>
+
+#include "device_util.h"
+#include "kernels.h"
+
+namespace ovl {
+
+// ============================================================================
+// Wilson stencil
+// ============================================================================
+// Chiral basis: gamma_mu = [[0, A_mu], [A_mu^dag, 0]] with A_k = -i sigma_k,
+// A_4 = 1.  For the lower half-spinor d = (psi_2, psi_3):
+//   (1 -+ gamma_mu) psi = [ h ; -+ A^dag h ],  h = psi_up -+ A_mu d,
+// so each hop moves a 2-spin x 3-colour half-spinor through the link.
+
+// h = psi_up - A d (forward, sg = -1) or psi_up + A d (backward, sg = +1)
+template <typename R>
+__device__ __forceinline__ void project(int mu, R sg, cx<R> p0, cx<R> p1, cx<R> p2, cx<R> p3,
+                                        cx<R>& h0, cx<R>& h1) {
+    cx<R> a0, a1;  // A_mu (p2, p3)
+    switch (mu) {
+        case 0: a0 = tmi(p3); a1 = tmi(p2); break;
+        case 1: a0 = -p3; a1 = p2; break;
+        case 2: a0 = tmi(p2); a1 = ti(p3); break;
+        default: a0 = p2; a1 = p3; break;
+    }
+    h0 = p0 + sg * a0;
+    h1 = p1 + sg * a1;
+}
+
+// acc_up += u ; acc_dn += sg * A_mu^dag u
+template <typename R>
+__device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
+                                            const cx<R> (&u)[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<R> u0 = u[0][c], u1 = u[1][c];
+        cx<R> b0, b1;  // A^dag (u0, u1)
+        switch (mu) {
+            case 0: b0 = ti(u1); b1 = ti(u0); break;
+            case 1: b0 = u1; b1 = -u0; break;
+            case 2: b0 = ti(u0); b1 = tmi(u1); break;
+            default: b0 = u0; b1 = u1; break;
+        }
+        acc[0][c] = acc[0][c] + u0;
+        acc[1][c] = acc[1][c] + u1;
+        acc[2][c] = acc[2][c] + sg * b0;
+        acc[3][c] = acc[3][c] + sg * b1;
+    }
+}
+
+// One hop for RPT right-hand sides sharing the link: project each neighbour
+// spinor to a half-spinor, move it through the link (U_mu(x) forward,
+// U_mu(x-mu)^dag backward), reconstruct into acc.  Per-lane offsets are 32-bit
+// element indices from uniform base pointers.
+template <typename R, int RPT>
+__device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
+                                    const C2<R>* const (&psi)[RPT],
+                                    const C2<R>* __restrict__ Um, uint32_t V, uint32_t nb,
+                                    uint32_t lsite) {
+    const R sg = fwd ? R(-1) : R(1);
+    cx<R> h[RPT][2][3];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cx<R> p0 = ld<R>(psi[r], (uint32_t)(0 + c) * V + nb);
+            const cx<R> p1 = ld<R>(psi[r], (uint32_t)(3 + c) * V + nb);
+            const cx<R> p2 = ld<R>(psi[r], (uint32_t)(6 + c) * V + nb);
+            const cx<R> p3 = ld<R>(psi[r], (uint32_t)(9 + c) * V + nb);
+            project<R>(mu, sg, p0, p1, p2, p3, h[r][0][c], h[r][1][c]);
+        }
+    }
+    // element (a,b) of the hop matrix: U[a][b] forward, conj(U[b][a]) backward
+    const R ci = fwd ? R(1) : R(-1);
+    cx<R> u[RPT][2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            u[r][0][a] = mk<R>(0, 0);
+            u[r][1][a] = mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const uint32_t e = fwd ? (uint32_t)(3 * a + b) : (uint32_t)(3 * b + a);
+            cx<R> l = ld<R>(Um, e * V + lsite);
+            l.im *= ci;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                fma_(u[r][0][a], l, h[r][0][b]);
+                fma_(u[r][1][a], l, h[r][1][b]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) reconstruct<R>(mu, sg, acc[r], u[r]);
+}
+
+__device__ __forceinline__ uint32_t nbr(const Geom& g, uint32_t s, const int (&coord)[4], int mu,
+                                        bool fwd) {
+    const uint32_t sd = (uint32_t)g.stride[mu];
+    const int L = g.L[mu];
+    const int cm = coord[mu];
+    if (fwd) return (cm == L - 1) ? s - (uint32_t)(L - 1) * sd : s + sd;
+    return (cm == 0) ? s + (uint32_t)(L - 1) * sd : s - sd;
+}
+
+// acc = sum over the 8 hops.  The hop loop stays rolled so that only HPI hops'
+// loads are live at a time (fully unrolled, the scheduler hoists every
+// neighbour's loads and the kernel spills).  HPI = 2 takes both hops of one
+// direction per iteration: twice the loads in flight for more registers.
+template <typename R, int HPI, int RPT>
+__device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
+                                            const C2<R>* const (&psi)[RPT],
+                                            const C2<R>* __restrict__ U, const Geom& g,
+                                            uint32_t s, const int (&coord)[4]) {
+    const uint32_t V = (uint32_t)g.V;
+    if constexpr (HPI == 1) {
+#pragma unroll 1
+        for (int d = 0; d < 8; ++d) {
+            const int mu = d >> 1;
+            const bool fwd = (d & 1) == 0;
+            const uint32_t nb = nbr(g, s, coord, mu, fwd);
+            hop<R, RPT>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb);
+        }
+    } else {
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
+            hop<R, RPT>(mu, true, acc, psi, U + (size_t)mu * 9 * V, V, fw, s);
+            hop<R, RPT>(mu, false, acc, psi, U + (size_t)mu * 9 * V, V, bw, bw);
+        }
+    }
+}
+
+
+template <typename R, int MODE, int HPI, int RPT, int ORD>
+__global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
+                                                   C2<R>* __restrict__ out,
+                                                   const C2<R>* __restrict__ U, Geom g, R kappa,
+                                                   double zsr, double zsi,
+                                                   const C2<R>* __restrict__ rdot,
+                                                   double2* __restrict__ partial,
+                                                   const SrcState* __restrict__ stt,
+                                                   ShiftDev sh, int k, int nsb, int nrhs) {
+    // ORD 0: rhs groups fastest, so the blocks of one site tile (all rhs) run
+    // back to back on one XCD and share its links through L2 (few rhs).
+    // ORD 1: site tiles fastest within an rhs group, so a tile's z and t
+    // neighbours were fetched moments earlier by the same XCD (many rhs).
+    const int ngrp = (nrhs + RPT - 1) / RPT;
+    const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
+    const int n0 = (int)uniform(ORD == 0 ? tile % (unsigned)ngrp : tile / (unsigned)nsb) * RPT;
+    const int sb = (int)uniform(ORD == 0 ? tile / (unsigned)ngrp : tile % (unsigned)nsb);
+    bool on[RPT];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        on[r] = n0 + r < nrhs;
+        if constexpr (MODE == 1) on[r] = on[r] && src_live(stt[n0 + r], sh, n0 + r, k);
+        any = any || on[r];
+    }
+    if (!any) return;
+    const uint32_t V = (uint32_t)g.V;
+    const uint32_t s = (uint32_t)sb * kBlock + threadIdx.x;
+    const bool valid = s < V;
+    double dre[RPT], dim[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) dre[r] = dim[r] = 0.0;
+    if (valid) {
+        const C2<R>* psi[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) psi[r] = in + (size_t)(n0 + (on[r] ? r : 0)) * 12 * V;
+        uint32_t rem = s;
+        int coord[4];
+        coord[0] = (int)(rem % (uint32_t)g.L[0]); rem /= (uint32_t)g.L[0];
+        coord[1] = (int)(rem % (uint32_t)g.L[1]); rem /= (uint32_t)g.L[1];
+        coord[2] = (int)(rem % (uint32_t)g.L[2]);
+        coord[3] = (int)(rem / (uint32_t)g.L[2]);
+        cx<R> acc[RPT][4][3];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[r][a][c] = mk<R>(0, 0);
+        dslash_site<R, HPI, RPT>(acc, psi, U, g, s, coord);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if (!on[r]) continue;
+            C2<R>* o = out + (size_t)(n0 + r) * 12 * V;
+            const C2<R>* rd = (MODE == 1) ? rdot + (size_t)(n0 + r) * 12 * V : nullptr;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int comp = 3 * a + c;
+                    const cx<R> p = ld<R>(psi[r], (uint32_t)comp * V + s);
+                    // D psi = psi - kappa acc ; H = gamma5 D
+                    cx<R> hv = p - kappa * acc[r][a][c];
+                    if (a >= 2) hv = -hv;
+                    if constexpr (MODE == 0) {
+                        stc<R>(o, (uint32_t)comp * V + s, hv);
+                    } else {
+                        // q = zs p - H p
+                        const R zr = (R)zsr, zi = (R)zsi;
+                        cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
+                        stc<R>(o, (uint32_t)comp * V + s, q);
+                        const cx<R> rv = ld<R>(rd, (uint32_t)comp * V + s);
+                        // <r, q> = sum conj(r) q, accumulated in FP64
+                        dre[r] += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
+                        dim[r] += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (MODE == 1) {
+        __shared__ double shd[kBlock / 64];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const double tr = block_sum<kBlock>(dre[r], shd);
+            const double ti_ = block_sum<kBlock>(dim[r], shd);
+            if (on[r] && threadIdx.x == 0)
+                partial[(int64_t)(n0 + r) * nsb + sb] = make_double2(tr, ti_);
+        }
+    }
+}
+
+int wilson_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
+
+template <typename R, int HPI, int RPT, int ORD>
+void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
+                     double kappa, double2 zs, const C2<R>* r, double2* partial,
+                     const SrcState* stt, const ShiftDev& sh, int k, int nrhs, hipStream_t s) {
+    const int nsb = wilson_blocks(g);
+    const int ngrp = (nrhs + RPT - 1) / RPT;
+    dim3 grid((unsigned)nsb * (unsigned)ngrp);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_wilson<R, 0, HPI, RPT, ORD>), grid, dim3(kBlock), 0, s, in, out, U, g,
+                           (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
+    else
+        hipLaunchKernelGGL((k_wilson<R, 1, HPI, RPT, ORD>), grid, dim3(kBlock), 0, s, in, out, U, g,
+                           (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
+}
+
+template <typename R>
+void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
+                   double kappa, double2 zs, const C2<R>* r, double2* partial,
+                   const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s,
+                   int variant) {
+    ShiftDev none{};
+    const ShiftDev& shv = sh ? *sh : none;
+#define OVL_WV(H, P, O) launch_wilson_v<R, H, P, O>(mode, in, out, U, g, kappa, zs, r, partial, stt, shv, k, nrhs, s)
+    switch (variant) {
+        case 1: OVL_WV(2, 1, 0); break;
+        case 2: OVL_WV(1, 2, 0); break;
+        case 3: OVL_WV(2, 2, 0); break;
+        case 4: OVL_WV(1, 1, 1); break;
+        case 5: OVL_WV(2, 1, 1); break;
+        case 6: OVL_WV(1, 2, 1); break;
+        case 7: OVL_WV(2, 2, 1); break;
+        default: OVL_WV(1, 1, 0); break;
+    }
+#undef OVL_WV
+}
+template void launch_wilson<double>(int, const double2*, double2*, const double2*, const Geom&,
+                                    double, double2, const double2*, double2*, const SrcState*,
+                                    const ShiftDev*, int, int, hipStream_t, int);
+template void launch_wilson<float>(int, const float2*, float2*, const float2*, const Geom&,
+                                   double, double2, const float2*, double2*, const SrcState*,
+                                   const ShiftDev*, int, int, hipStream_t, int);
+
+}  // namespace ovl

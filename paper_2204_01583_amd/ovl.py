@@ -42,7 +42,9 @@ class Stats(ctypes.Structure):
         ("n_active_end", ctypes.c_int32),
         ("max_est_rel_res", ctypes.c_double),
         ("seconds", ctypes.c_double),
-        ("reserved", ctypes.c_double * 4),
+        ("stencil_variant64", ctypes.c_int32),
+        ("stencil_variant32", ctypes.c_int32),
+        ("reserved", ctypes.c_double * 3),
     ]
 
     def as_dict(self):

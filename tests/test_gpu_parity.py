@@ -208,3 +208,28 @@ def test_deterministic():
     s2, _ = ctx.apply_sign(b)
     assert bool((s1 == s2).all())
     ctx.close()
+
+
+@pytest.mark.parametrize("variant", list(range(8)))
+def test_stencil_variants(variant, monkeypatch):
+    """Every stencil variant the autotuner may pick gives the oracle's H_W,
+    including an odd number of right-hand sides (the two-rhs tail), and the
+    same sign function in both precisions."""
+    monkeypatch.setenv("OVL_STENCIL_VARIANT", str(variant))
+    dims = (4, 6, 4, 8)
+    U = gauge(dims, 0.3, 1)
+    ctx = make_ctx(dims, U, nq=16, precision=1, form=2)
+    H = oracle_H(dims, 0.3, 1, 1.4)
+    for nrhs in (1, 3):
+        b = si.gaussian_sources(dims, nrhs, first_seed=7)
+        out = ctx.apply_hw(to_dev(b)).cpu().numpy()
+        for i in range(nrhs):
+            ref = H @ b[i].ravel()
+            err = float(np.abs(out[i].ravel() - ref).max() / np.abs(ref).max())
+            assert err < 1e-14, (nrhs, i, err)
+    b = si.gaussian_sources(dims, 3, first_seed=7)
+    s, st = ctx.apply_sign(to_dev(b))
+    assert st.stencil_variant64 == variant and st.stencil_variant32 == variant
+    ref = oracle_sign(dims, 0.3, 1, 1.4, 16, CIRCLE, 7)
+    assert relerr(s[0].cpu().numpy(), ref) < 1e-10
+    ctx.close()
