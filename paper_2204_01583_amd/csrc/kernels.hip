@@ -468,7 +468,7 @@ void launch_sum_ref(const double2* xj, const double2* c, double2* sacc, int J, i
 // x_j = sum_i u_i^j r_i with u_i^j = P_i^j / pi_i^j,
 // P_i^j = alpha_i^j + beta_i^j P_{i+1}^j (alpha^j recorded as 0 once shift j
 // stopped, which freezes x_j exactly as the sweep does).  One thread per
-// shift runs the backward recursion; W[src][i][j] = c_j u_i^j.
+// shift runs the backward recursion; W[src][i][j] = u_i^j.
 __global__ __launch_bounds__(kBlock) void k_coef(const double2* __restrict__ h_a,
                                                  const double2* __restrict__ h_b,
                                                  const double2* __restrict__ h_pi,
@@ -485,11 +485,12 @@ __global__ __launch_bounds__(kBlock) void k_coef(const double2* __restrict__ h_a
         const double2 a = h_a[hb + (int64_t)i * J + j], b = h_b[hb + (int64_t)i * J + j];
         P = cadd(a, cmul(b, P));
         const double2 pi = (i == 0) ? make_double2(1, 0) : h_pi[hb + (int64_t)i * J + j];
-        W[hb + (int64_t)i * J + j] = cmul(c[j], cdiv(P, pi));
+        W[hb + (int64_t)i * J + j] = cdiv(P, pi);
     }
 }
-// h[src][i] = sum_j W[src][i][j] (fixed order)
+// h[src][i] = sum_j c_j W[src][i][j] (fixed order)
 __global__ __launch_bounds__(kBlock) void k_hsum(const double2* __restrict__ W,
+                                                 const double2* __restrict__ c,
                                                  const SrcState* __restrict__ st,
                                                  double2* __restrict__ h, int J, int maxk) {
     const int n = blockIdx.y;
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_hsum(const double2* __restrict__ W,
     double2 t = make_double2(0, 0);
     if (i < K) {
         const double2* w = W + ((int64_t)n * (maxk + 1) + i) * J;
-        for (int j = 0; j < J; ++j) t = cadd(t, w[j]);
+        for (int j = 0; j < J; ++j) t = cadd(t, cmul(c[j], w[j]));
     }
     h[(int64_t)n * (maxk + 1) + i] = t;
 }
@@ -509,7 +510,7 @@ void launch_basis_coef(const double2* h_a, const double2* h_b, const double2* h_
     hipLaunchKernelGGL(k_coef, dim3((J + kBlock - 1) / kBlock, nsrc), dim3(kBlock), 0, s, h_a,
                        h_b, h_pi, c, st, W, J, maxk);
     hipLaunchKernelGGL(k_hsum, dim3((maxk + 1 + kBlock - 1) / kBlock, nsrc), dim3(kBlock), 0, s,
-                       W, st, h, J, maxk);
+                       W, c, st, h, J, maxk);
 }
 
 // s[src] = (s[src] +) sum_l h[src][g0 + l] * slot_l[src] over local slots
@@ -622,6 +623,281 @@ void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t 
     hipLaunchKernelGGL(k_norm2, dim3(nb, sh.nsrc), dim3(kBlock), 0, s, b, partial, n12);
     hipLaunchKernelGGL(k_init_state, dim3(sh.nslices, sh.nsrc), dim3(kBlock), 0, s, st, partial,
                        nb, sh);
+}
+
+// ============================================================================
+// force (derivative of S = |D_ov phi|^2 with respect to the links)
+// ============================================================================
+// d = a b + bm gamma5 s ;  psi = bm gamma5 d ;  partial[blk] = |d|^2  (one source)
+__global__ __launch_bounds__(kBlock) void k_dov_psi(const double2* __restrict__ b,
+                                                    const double2* __restrict__ sv,
+                                                    double2* __restrict__ psi, double a, double bm,
+                                                    int64_t V, double* __restrict__ partial) {
+    const int64_t n12 = 12 * V;
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
+        const double g5 = (e / V) < 6 ? 1.0 : -1.0;  // component = e / V, spin = comp / 3
+        const double2 bv = b[e], s = sv[e];
+        const double2 d = make_double2(a * bv.x + bm * g5 * s.x, a * bv.y + bm * g5 * s.y);
+        acc += d.x * d.x + d.y * d.y;
+        psi[e] = make_double2(bm * g5 * d.x, bm * g5 * d.y);
+    }
+    __shared__ double sh[kBlock / 64];
+    const double t = block_sum<kBlock>(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+void launch_dov_psi(const double2* b, const double2* s, double2* psi, double a, double bm,
+                    int64_t V, double* partial, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_dov_psi, dim3(nblk), dim3(kBlock), 0, st, b, s, psi, a, bm, V, partial);
+}
+
+// Y[j][e] (+)= sum_{i in one slot chunk} u_i^{j} r_i[e] for shifts j0 .. j0+JG-1
+// of one source; slots below ksw hold FP64, from ksw on FP32 (at the slot base).
+template <int JG>
+__global__ __launch_bounds__(kBlock) void k_materialize(const char* __restrict__ chunk,
+                                                        size_t slot_bytes, int g0, int l1,
+                                                        int ksw, const double2* __restrict__ W,
+                                                        int J, int j0, int jn, int K,
+                                                        double2* __restrict__ Y, int64_t n12,
+                                                        int accumulate) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n12) return;
+    double re[JG], im[JG];
+#pragma unroll
+    for (int q = 0; q < JG; ++q) re[q] = im[q] = 0.0;
+    const int lend = (K - g0) < l1 ? (K - g0) : l1;
+    for (int l = 0; l < lend; ++l) {
+        const int i = g0 + l;
+        const char* slot = chunk + (size_t)l * slot_bytes;
+        double vr, vi;
+        if (i < ksw) {
+            const double2 v = reinterpret_cast<const double2*>(slot)[e];
+            vr = v.x;
+            vi = v.y;
+        } else {
+            const float2 v = reinterpret_cast<const float2*>(slot)[e];
+            vr = v.x;
+            vi = v.y;
+        }
+        const double2* wr = W + (size_t)i * J + j0;
+#pragma unroll
+        for (int q = 0; q < JG; ++q) {
+            if (q < jn) {
+                const double2 u = wr[q];
+                re[q] += u.x * vr - u.y * vi;
+                im[q] += u.x * vi + u.y * vr;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < JG; ++q) {
+        if (q < jn) {
+            double2* y = Y + (size_t)q * n12 + e;
+            double2 o = make_double2(re[q], im[q]);
+            if (accumulate) {
+                const double2 prev = *y;
+                o.x += prev.x;
+                o.y += prev.y;
+            }
+            *y = o;
+        }
+    }
+}
+constexpr int kMatGroup = 8;
+void launch_materialize(const char* chunk, size_t slot_bytes, int g0, int l1, int ksw,
+                        const double2* W, int J, int j0, int jn, int K, double2* Y, int64_t n12,
+                        bool accumulate, hipStream_t s) {
+    dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock));
+    for (int q0 = 0; q0 < jn; q0 += kMatGroup) {
+        const int m = jn - q0 < kMatGroup ? jn - q0 : kMatGroup;
+        hipLaunchKernelGGL(k_materialize<kMatGroup>, grid, dim3(kBlock), 0, s, chunk, slot_bytes,
+                           g0, l1, ksw, W, J, j0 + q0, m, K, Y + (size_t)q0 * n12, n12,
+                           (int)accumulate);
+    }
+}
+
+// (M v) for M = gamma5 (1 -+ gamma_mu) (sg = -1: 1 - gamma, +1: 1 + gamma):
+// (1 -+ gamma) v = [h ; -+ A^dag h], h = v_up -+ A v_dn; gamma5 flips the lower half.
+__device__ __forceinline__ void proj_g5(int mu, double sg, const double2 (&v)[4][3],
+                                        double2 (&o)[4][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double2 p0 = v[0][c], p1 = v[1][c], p2 = v[2][c], p3 = v[3][c];
+        double2 a0, a1;  // A (p2, p3)
+        switch (mu) {
+            case 0: a0 = make_double2(p3.y, -p3.x); a1 = make_double2(p2.y, -p2.x); break;
+            case 1: a0 = make_double2(-p3.x, -p3.y); a1 = p2; break;
+            case 2: a0 = make_double2(p2.y, -p2.x); a1 = make_double2(-p3.y, p3.x); break;
+            default: a0 = p2; a1 = p3; break;
+        }
+        const double2 h0 = make_double2(p0.x + sg * a0.x, p0.y + sg * a0.y);
+        const double2 h1 = make_double2(p1.x + sg * a1.x, p1.y + sg * a1.y);
+        double2 b0, b1;  // A^dag (h0, h1)
+        switch (mu) {
+            case 0: b0 = make_double2(-h1.y, h1.x); b1 = make_double2(-h0.y, h0.x); break;
+            case 1: b0 = h1; b1 = make_double2(-h0.x, -h0.y); break;
+            case 2: b0 = make_double2(-h0.y, h0.x); b1 = make_double2(h1.y, -h1.x); break;
+            default: b0 = h0; b1 = h1; break;
+        }
+        // lower half of (1 -+ gamma) v is sg * A^dag h; gamma5 negates it
+        o[0][c] = h0;
+        o[1][c] = h1;
+        o[2][c] = make_double2(-sg * b0.x, -sg * b0.y);
+        o[3][c] = make_double2(-sg * b1.x, -sg * b1.y);
+    }
+}
+
+// One lane per link (x, mu).  For shifts j of the current chunk:
+//   A_ab += c_j sum_s conj(X_j(x)_{s a}) (M Y_j(x+mu))_{s b},        M  = gamma5 (1 - gamma_mu)
+//   B_cd += c_j sum_s conj(X_j(x+mu)_{s c}) (M' Y_j(x))_{s d},       M' = gamma5 (1 + gamma_mu)
+// acc holds [A | B] (18 complex) per link across chunks.  With last != 0 the
+// result -2 kappa ph (conj(A) + B^T) is written as the complex gradient G, or
+// converted to the traceless hermitian force F = TH[(Z + Z^dag)/2], Z = i U G^dag.
+__global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ X,
+                                                  const double2* __restrict__ Y,
+                                                  const double2* __restrict__ c, int jn,
+                                                  Geom g, const double2* __restrict__ Uint,
+                                                  int bc0, int bc1, int bc2, int bc3,
+                                                  double kappa, double2* __restrict__ acc,
+                                                  int first, int last, int kind,
+                                                  double2* __restrict__ out) {
+    const int64_t V = g.V;
+    const int64_t lk = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (lk >= 4 * V) return;
+    const int mu = (int)(lk / V);
+    const int64_t x = lk - (int64_t)mu * V;
+    const int cm = (int)((x / g.stride[mu]) % g.L[mu]);
+    const int64_t xp = (cm == g.L[mu] - 1) ? x - (int64_t)(g.L[mu] - 1) * g.stride[mu] : x + g.stride[mu];
+    const int64_t n12 = 12 * V;
+    double2 A[3][3], B[3][3];
+    double2* ac = acc + (size_t)lk * 18;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            A[a][b] = first ? make_double2(0, 0) : ac[3 * a + b];
+            B[a][b] = first ? make_double2(0, 0) : ac[9 + 3 * a + b];
+        }
+#pragma unroll 1
+    for (int j = 0; j < jn; ++j) {
+        const double2* Xj = X + (size_t)j * n12;
+        const double2* Yj = Y + (size_t)j * n12;
+        const double2 cj = c[j];
+        double2 v[4][3], m[4][3], xs[4][3];
+        // term 1: X(x), M Y(x+mu)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                v[sp][cc] = Yj[(size_t)(3 * sp + cc) * V + xp];
+                xs[sp][cc] = Xj[(size_t)(3 * sp + cc) * V + x];
+            }
+        proj_g5(mu, -1.0, v, m);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                double2 t = make_double2(0, 0);
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp) {  // conj(X) * (M Y)
+                    const double2 xa = xs[sp][a], mb = m[sp][b];
+                    t.x += xa.x * mb.x + xa.y * mb.y;
+                    t.y += xa.x * mb.y - xa.y * mb.x;
+                }
+                A[a][b] = cadd(A[a][b], cmul(cj, t));
+            }
+        // term 2: X(x+mu), M' Y(x)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                v[sp][cc] = Yj[(size_t)(3 * sp + cc) * V + x];
+                xs[sp][cc] = Xj[(size_t)(3 * sp + cc) * V + xp];
+            }
+        proj_g5(mu, 1.0, v, m);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                double2 t = make_double2(0, 0);
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp) {
+                    const double2 xa = xs[sp][a], mb = m[sp][b];
+                    t.x += xa.x * mb.x + xa.y * mb.y;
+                    t.y += xa.x * mb.y - xa.y * mb.x;
+                }
+                B[a][b] = cadd(B[a][b], cmul(cj, t));
+            }
+    }
+    if (!last) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                ac[3 * a + b] = A[a][b];
+                ac[9 + 3 * a + b] = B[a][b];
+            }
+        return;
+    }
+    const int bcm = mu == 0 ? bc0 : mu == 1 ? bc1 : mu == 2 ? bc2 : bc3;
+    const double f = -2.0 * kappa * ((cm == g.L[mu] - 1) ? (double)bcm : 1.0);
+    double2 G[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)  // G = f (conj(A) + B^T)
+            G[a][b] = make_double2(f * (A[a][b].x + B[b][a].x), f * (-A[a][b].y + B[b][a].y));
+    double2* o = out + ((size_t)mu * V + x) * 9;
+    if (kind == 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) o[3 * a + b] = G[a][b];
+        return;
+    }
+    // Z = i U G^dag ; F = (Z + Z^dag)/2 - tr/3.  The internal links carry the
+    // boundary phase (+-1); multiplying by it again restores the caller's U.
+    const double ph = (cm == g.L[mu] - 1) ? (double)bcm : 1.0;
+    double2 Z[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double2 t = make_double2(0, 0);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {  // U[a][q] conj(G[b][q])
+                double2 u = Uint[((size_t)mu * 9 + 3 * a + q) * V + x];
+                u.x *= ph;
+                u.y *= ph;
+                const double2 gg = G[b][q];
+                t.x += u.x * gg.x + u.y * gg.y;
+                t.y += u.y * gg.x - u.x * gg.y;
+            }
+            Z[a][b] = make_double2(-t.y, t.x);  // i t
+        }
+    double2 F[3][3];
+    double tr = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            F[a][b] = make_double2(0.5 * (Z[a][b].x + Z[b][a].x), 0.5 * (Z[a][b].y - Z[b][a].y));
+            if (a == b) tr += F[a][b].x;
+        }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a][a].x -= tr / 3.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) o[3 * a + b] = F[a][b];
+}
+void launch_force(const double2* X, const double2* Y, const double2* c, int jn, const Geom& g,
+                  const double2* Uint, const int bc[4], double kappa, double2* acc, bool first,
+                  bool last, int kind, double2* out, hipStream_t s) {
+    dim3 grid((unsigned)((4 * g.V + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_force, grid, dim3(kBlock), 0, s, X, Y, c, jn, g, Uint, bc[0], bc[1],
+                       bc[2], bc[3], kappa, acc, (int)first, (int)last, kind, out);
 }
 
 }  // namespace ovl

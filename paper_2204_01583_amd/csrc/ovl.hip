@@ -71,6 +71,7 @@ struct ovl_ctx {
     SrcState* host_state = nullptr;  // pinned mirror
     int host_state_n = 0;
     DBuf bench_a, bench_b;
+    DBuf fY, fX, fpsi, facc, fc, fpart;  // force work space
     // per-kernel-class event timing (ovl_set_profiling)
     static constexpr int kClasses = 8;
     bool prof_on = false;
@@ -121,10 +122,11 @@ int check_dev_ptr(ovl_ctx* ctx, const void* p, const char* name) {
     return OVL_OK;
 }
 
-bool overlaps(const void* a, const void* b, size_t n) {
+// [a, a+na) and [b, b+nb) intersect
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     const char* x = static_cast<const char*>(a);
     const char* y = static_cast<const char*>(b);
-    return x < y + n && y < x + n;
+    return x < y + nb && y < x + na;
 }
 
 double kappa_of(double m0) { return 1.0 / (2.0 * (4.0 - m0)); }
@@ -248,7 +250,8 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
                     &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
                     &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_e,
                     &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
-                    &ctx->h,    &ctx->bench_a, &ctx->bench_b};
+                    &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->fY, &ctx->fX, &ctx->fpsi,
+                    &ctx->facc, &ctx->fc, &ctx->fpart};
     for (DBuf* b : bufs) b->release();
     for (DBuf& b : ctx->slot_chunks) b.release();
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -534,7 +537,7 @@ static int check_apply_args(ovl_ctx* ctx, const void* in, const void* out, int n
     rc = check_dev_ptr(ctx, out, "out");
     if (rc) return rc;
     const size_t bytes = (size_t)nrhs * n12(ctx) * sizeof(double2);
-    if (overlaps(in, out, bytes)) return fail(ctx, OVL_E_ARG, "out aliases in");
+    if (overlaps(in, bytes, out, bytes)) return fail(ctx, OVL_E_ARG, "out aliases in");
     return OVL_OK;
 }
 
@@ -579,6 +582,8 @@ struct Work {
     size_t state_bytes;
     ShiftDev sh;
     int var64, var32;      // stencil variants (autotuned)
+    int k_switch;          // first FP32 iteration (mixed), or -1
+    int K;                 // seed iterations of the last solve (max over sources)
     double2 *dz, *cj;
     double2 *h_a, *h_b, *h_pi, *W, *h;
 };
@@ -855,6 +860,8 @@ static int solve(ovl_ctx* ctx, Work& w) {
             HIPCHK(ctx, hipGetLastError());
         }
     }
+    w.k_switch = k_switch;
+    w.K = iters;
     if (status == OVL_OK && !all_done) status = OVL_NOT_CONVERGED;
     if (status == OVL_OK || status == OVL_NOT_CONVERGED) {
         if (form == OVL_FORM_REFERENCE) {
@@ -945,9 +952,109 @@ extern "C" int ovl_apply_dov(ovl_ctx* ctx, const void* in, void* out, int32_t nr
     return apply_common(ctx, in, out, nrhs, st, true);
 }
 
-extern "C" int ovl_force(ovl_ctx* ctx, const void*, void*, int32_t, int32_t, double*, ovl_stats*) {
+// Y[j] = sum_i u_i^j r_i for shifts [j0, j0+jn) of the last basis solve (one source)
+static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y) {
+    const int K = w.K;
+    const int ksw = w.k_switch < 0 ? K + 1 : w.k_switch;
+    bool acc = false;
+    for (int c0 = 0; c0 < K; c0 += kSlotChunk) {
+        launch_materialize(w.chunks[c0 / kSlotChunk], w.slot_bytes, c0, kSlotChunk, ksw, w.W, w.J,
+                           j0, jn, K, Y, w.N, acc, ctx->stream);
+        acc = true;
+    }
+    if (!acc) HIPCHK(ctx, hipMemsetAsync(Y, 0, (size_t)jn * w.N * sizeof(double2), ctx->stream));
+    HIPCHK(ctx, hipGetLastError());
+    return OVL_OK;
+}
+
+extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind,
+                         int32_t shift_chunk, double* action, ovl_stats* st) {
     if (!ctx) return OVL_E_ARG;
-    return fail(ctx, OVL_E_STATE, "ovl_force is not available in this build");
+    DeviceGuard dg(ctx->device);
+    if (kind != 0 && kind != 1) return fail(ctx, OVL_E_ARG, "kind must be 0 (force) or 1 (gradient)");
+    if (!ctx->gauge_set || !ctx->masses_set || ctx->z.empty())
+        return fail(ctx, OVL_E_STATE, "gauge, masses and nodes must be set before ovl_force");
+    int rc = check_dev_ptr(ctx, phi, "phi");
+    if (rc) return rc;
+    rc = check_dev_ptr(ctx, grad, "grad");
+    if (rc) return rc;
+    if (overlaps(phi, (size_t)12 * ctx->g.V * sizeof(double2), grad,
+                 (size_t)36 * ctx->g.V * sizeof(double2)))
+        return fail(ctx, OVL_E_ARG, "grad aliases phi");
+    const int saved_form = ctx->form;
+    const std::vector<double2> z0 = ctx->z, c0 = ctx->c;
+    const int J = (int)z0.size();
+    const int64_t N = n12(ctx);
+    const int C = (shift_chunk <= 0 || shift_chunk > J) ? J : shift_chunk;
+    hipStream_t s = ctx->stream;
+    auto restore = [&]() {
+        ctx->form = saved_form;
+        ctx->z = z0;
+        ctx->c = c0;
+    };
+    // 1. Y_j = (z_j - H)^-1 phi and s = sum c_j Y_j from one basis-form solve
+    ctx->form = OVL_FORM_BASIS;
+    Work w;
+    rc = prepare(ctx, 1, w);
+    if (rc) { restore(); return rc; }
+    launch_pack_spinor64(static_cast<const double2*>(phi), w.b64, ctx->g.V, 1, s);
+    const int rc1 = solve(ctx, w);
+    if (rc1 < 0) { restore(); return rc1; }
+    const ovl_stats st1 = ctx->last;
+    if (ctx->fY.ensure((size_t)J * N * sizeof(double2)) != hipSuccess ||
+        ctx->fpsi.ensure((size_t)N * sizeof(double2)) != hipSuccess ||
+        ctx->fX.ensure((size_t)C * N * sizeof(double2)) != hipSuccess ||
+        ctx->facc.ensure((size_t)4 * ctx->g.V * 18 * sizeof(double2)) != hipSuccess ||
+        ctx->fc.ensure((size_t)J * sizeof(double2)) != hipSuccess ||
+        ctx->fpart.ensure(512 * sizeof(double)) != hipSuccess) {
+        restore();
+        return fail(ctx, OVL_E_OOM, "force work space allocation failed");
+    }
+    rc = materialize(ctx, w, 0, J, ctx->fY.as<double2>());
+    if (rc) { restore(); return rc; }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->fc.p, w.cj, J * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    // 2. D_ov phi, psi = (1-mq)/2 gamma5 D_ov phi and S = |D_ov phi|^2
+    const int npart = 256;
+    launch_dov_psi(w.b64, w.s64, ctx->fpsi.as<double2>(), 0.5 * (1.0 + ctx->mq),
+                   0.5 * (1.0 - ctx->mq), ctx->g.V, ctx->fpart.as<double>(), npart, s);
+    std::vector<double> part(npart);
+    HIPCHK(ctx, hipMemcpyAsync(part.data(), ctx->fpart.p, npart * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    // 3. X_j = (conj(z_j) - H)^-1 psi from a second basis-form solve at the conjugate nodes
+    for (int j = 0; j < J; ++j) ctx->z[j].y = -z0[j].y;
+    Work w2;
+    rc = prepare(ctx, 1, w2);  // synchronises the stream (so part[] is ready)
+    if (rc) { restore(); return rc; }
+    double S = 0.0;
+    for (double v : part) S += v;
+    HIPCHK(ctx, hipMemcpyAsync(w2.b64, ctx->fpsi.p, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    const int rc2 = solve(ctx, w2);
+    if (rc2 < 0) { restore(); return rc2; }
+    const ovl_stats st2 = ctx->last;
+    // 4. per link: sum_j c_j X_j^dag dH Y_j, C shifts at a time
+    for (int j0 = 0; j0 < J; j0 += C) {
+        const int jn = std::min(C, J - j0);
+        rc = materialize(ctx, w2, j0, jn, ctx->fX.as<double2>());
+        if (rc) { restore(); return rc; }
+        launch_force(ctx->fX.as<double2>(), ctx->fY.as<double2>() + (size_t)j0 * N,
+                     ctx->fc.as<double2>() + j0, jn, ctx->g, ctx->U64.as<double2>(), ctx->bc,
+                     kappa_of(ctx->m0), ctx->facc.as<double2>(), j0 == 0, j0 + jn >= J, kind,
+                     static_cast<double2*>(grad), s);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    restore();
+    ovl_stats& L = ctx->last;
+    L = st1;
+    L.iterations = std::max(st1.iterations, st2.iterations);
+    L.fp32_iterations = std::max(st1.fp32_iterations, st2.fp32_iterations);
+    L.n_active_end = st1.n_active_end + st2.n_active_end;
+    L.max_est_rel_res = std::max(st1.max_est_rel_res, st2.max_est_rel_res);
+    L.seconds = st1.seconds + st2.seconds;
+    L.reserved[0] = st2.iterations;
+    if (action) *action = S;
+    if (st) *st = L;
+    return (rc1 == OVL_NOT_CONVERGED || rc2 == OVL_NOT_CONVERGED) ? OVL_NOT_CONVERGED : OVL_OK;
 }
 
 extern "C" int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const void* const*,

@@ -227,6 +227,29 @@ class Context:
         """(D_ov(m_q) x, Stats)."""
         return self._apply(self.lib.ovl_apply_dov, x, allow_not_converged)
 
+    def force(self, phi, kind=0, shift_chunk=0, allow_not_converged=False):
+        """Derivative of S = |D_ov phi|^2 with respect to the links.
+
+        kind 0: traceless hermitian force F (dS/dh = sum tr(Omega F) for
+        U -> exp(i h Omega) U); kind 1: complex gradient G with
+        dS = Re sum conj(G) dU.  Returns (tensor [4, Lt, Lz, Ly, Lx, 3, 3], S, Stats).
+        """
+        phi = self._spinor_in(phi)
+        if phi.shape[0] != 1:
+            raise ValueError("force takes one phi")
+        out = torch.empty((4,) + self.site_shape + (3, 3), dtype=torch.complex128,
+                          device=phi.device)
+        S = ctypes.c_double()
+        st = Stats()
+        self._sync_stream()
+        rc = self.lib.ovl_force(self._h, ctypes.c_void_p(phi.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), int(kind), int(shift_chunk),
+                                ctypes.byref(S), ctypes.byref(st))
+        self._rc(rc, "ovl_force")
+        if rc == NOT_CONVERGED and not allow_not_converged:
+            raise OvlError(rc, self.lib.ovl_last_error(self._h).decode())
+        return out, S.value, st
+
     def bench_kernel(self, which, nrhs, reps):
         ms, nb = ctypes.c_double(), ctypes.c_double()
         self._sync_stream()
@@ -251,3 +274,22 @@ class Context:
         st = Stats()
         self._rc(self.lib.ovl_get_stats(self._h, ctypes.byref(st)), "ovl_get_stats")
         return st
+
+
+class OverlapAction(torch.autograd.Function):
+    """S(U) = |D_ov(m_q) phi|^2 with the gradient from the library's adjoint
+    kernel (ovl_force, kind 1).  PyTorch's convention for a real function of a
+    complex tensor: U.grad = G with dS = Re sum conj(G) dU.  The solver and
+    contour settings are those of `context`; `U` is loaded with set_gauge."""
+
+    @staticmethod
+    def forward(fctx, U, phi, context):
+        context.set_gauge(U.detach().contiguous())
+        G, S, _ = context.force(phi.detach().contiguous(), kind=1)
+        fctx.save_for_backward(G)
+        return torch.tensor(S, dtype=torch.float64, device=U.device)
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        (G,) = fctx.saved_tensors
+        return grad_out * G, None, None

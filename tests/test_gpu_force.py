@@ -1,0 +1,119 @@
+"""GPU parity of the adjoint force kernel (ovl_force) against the oracle and
+against finite differences of the library's own action."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle.contour import nodes
+from oracle.force import force as oracle_force
+from tests.gpu_util import CIRCLE, gauge, make_ctx, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(module):
+    from paper_2204_01583_amd import ovl
+    ovl.load()
+
+
+@pytest.mark.parametrize("dims,chunk", [((2, 2, 4, 4), 0), ((4, 2, 2, 4), 5)])
+def test_force_matches_oracle(dims, chunk):
+    m0, mq, nq = 1.4, 0.1, 16
+    U = gauge(dims, 0.3, 2)
+    phi = si.gaussian_sources(dims, 1, first_seed=11)[0]
+    z, c = nodes(nq, *CIRCLE)
+    G_ref, F_ref, S_ref = oracle_force(U, phi, m0, mq, z, c, method="dense")
+    ctx = make_ctx(dims, U, m0, mq, nq, form=2, tol=1e-13)
+    G, S, st = ctx.force(to_dev(phi), kind=1, shift_chunk=chunk)
+    F, S2, _ = ctx.force(to_dev(phi), kind=0, shift_chunk=chunk)
+    eG = relerr(G.cpu().numpy(), G_ref)
+    eF = relerr(F.cpu().numpy(), F_ref)
+    print(f"{dims}: S {S:.12e} vs {S_ref:.12e}, G err {eG:.2e}, F err {eF:.2e}, iters {st.iterations}")
+    assert abs(S - S_ref) / S_ref < 1e-11 and abs(S2 - S) / S < 1e-13
+    assert eG < 1e-10 and eF < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 16)])
+def test_force_finite_differences(dims):
+    """Central differences (h = 1e-6) of S(U) = |D_ov phi|^2 through the
+    library's apply_dov at U +- h E along 32 random complex link directions
+    (checks G) and 4 random su(3) directions U -> exp(+-i h Omega) U (checks F),
+    2 x 64 nodes.  The iteration count is fixed so both sides apply the same
+    rational function of H_W.  Central differences of an FP64 S carry a
+    rounding floor of about eps * S / h (S ~ 1e6 here, so ~3e-4 absolute
+    against derivatives ~1e2); the bound is 10 eps S / h + 1e-8 |dS|."""
+    import torch
+    m0, mq, nq = 1.4, 0.1, 64
+    U = gauge(dims, 0.3, 0)
+    phi = to_dev(si.gaussian_sources(dims, 1, first_seed=5))
+    ctx = make_ctx(dims, U, m0, mq, nq, form=2, tol=1e-13)
+    _, _, st = ctx.force(phi, kind=1)
+    K = st.iterations
+    ctx.set_solver(0, 2, tol=1e-300, maxiter=K)
+    G, S0, _ = ctx.force(phi, kind=1, allow_not_converged=True)
+    F, _, _ = ctx.force(phi, kind=0, allow_not_converged=True)
+    Ud = to_dev(U)
+    rng = np.random.default_rng(3)
+    h = 1e-6
+
+    def action(Up):
+        ctx.set_gauge(Up.contiguous())
+        d, _ = ctx.apply_dov(phi, allow_not_converged=True)
+        return float((d.abs() ** 2).sum())
+
+    eps = np.finfo(np.float64).eps
+    floor = 10 * eps * S0 / h
+    worst = 0.0
+    for trial in range(32):
+        E = to_dev(rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape))
+        fd = (action(Ud + h * E) - action(Ud - h * E)) / (2 * h)
+        an = float((G.conj() * E).real.sum())
+        worst = max(worst, abs(fd - an) / (floor + 1e-8 * abs(an)))
+        assert abs(fd - an) <= floor + 1e-8 * abs(an), (trial, fd, an)
+    print(f"{dims}: S {S0:.6e}, 32 complex directions, worst |fd-an| / bound {worst:.2f}, "
+          f"iterations {K}")
+    lam = si.gell_mann()
+    for trial in range(4):
+        om = si.random_su3_direction(dims, 100 + trial)
+        om = om * np.sqrt(om.size / 8)        # O(1) per link, so dS/dh clears the FD floor
+        Om = np.einsum("...k,kij->...ij", om, lam) / 2
+        e, W = np.linalg.eigh(Om)
+        expo = lambda t: to_dev(np.einsum("...ij,...j,...kj->...ik", W, np.exp(1j * t * e), W.conj()))
+        up = torch.einsum("...ij,...jk->...ik", expo(h), Ud)
+        um = torch.einsum("...ij,...jk->...ik", expo(-h), Ud)
+        fd = (action(up) - action(um)) / (2 * h)
+        an = float(torch.einsum("...ij,...ji->...", to_dev(Om), F).real.sum())
+        print(f"  su(3) direction {trial}: fd {fd:.8e} analytic {an:.8e} bound {floor + 1e-8 * abs(an):.1e}")
+        assert abs(fd - an) <= floor + 1e-8 * abs(an)
+    ctx.close()
+
+
+def test_force_mixed_matches_fp64():
+    dims, m0, mq, nq = (8, 8, 8, 8), 1.4, 0.1, 32
+    U = gauge(dims, 0.3, 0)
+    phi = to_dev(si.gaussian_sources(dims, 1, first_seed=5))
+    ctx = make_ctx(dims, U, m0, mq, nq, form=2, tol=1e-12)
+    F64, S64, _ = ctx.force(phi, kind=0)
+    ctx.set_solver(1, 2, tol=1e-12, maxiter=3000)
+    F32, S32, st = ctx.force(phi, kind=0)
+    err = float((F32 - F64).norm() / F64.norm())
+    print(f"mixed force err {err:.2e}, fp32 iterations {st.fp32_iterations}")
+    assert st.fp32_iterations > 0
+    assert err < 1e-9 and abs(S32 - S64) / S64 < 1e-10
+    ctx.close()
+
+
+def test_autograd_gradcheck():
+    import torch
+    from paper_2204_01583_amd import ovl
+    dims = (2, 2, 2, 4)
+    U = to_dev(gauge(dims, 0.3, 4)).requires_grad_(True)
+    phi = to_dev(si.gaussian_sources(dims, 1, first_seed=9))
+    ctx = make_ctx(dims, gauge(dims, 0.3, 4), 1.4, 0.1, 8, form=2, tol=1e-14)
+    f = lambda u: ovl.OverlapAction.apply(u, phi, ctx)
+    assert torch.autograd.gradcheck(f, (U,), eps=1e-6, atol=1e-7, rtol=1e-6, fast_mode=True)
+    S = f(U)
+    S.backward()
+    assert U.grad is not None and U.grad.shape == U.shape
+    ctx.close()
