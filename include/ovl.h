@@ -65,7 +65,8 @@ extern "C" {
 #define OVL_FORM_REFERENCE 0 /* per-shift solutions x_j kept in HBM, s = sum c_j x_j at the end */
 #define OVL_FORM_FUSED     1 /* per-shift directions p_j only; s accumulated in the same sweep  */
 #define OVL_FORM_BASIS     2 /* seed residuals r_k stored; s = sum_k h_k r_k from the scalars    */
-#define OVL_FORM_TWOPASS   3 /* as BASIS, but the r_k are regenerated in a second pass          */
+#define OVL_FORM_TWOPASS   3 /* as BASIS without storing the r_k: a second pass regenerates them
+                                bit for bit (deterministic reductions) and accumulates s       */
 
 typedef struct ovl_ctx ovl_ctx;
 
@@ -144,10 +145,15 @@ int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind, int32_t s
               double* action, ovl_stats* st);
 
 /* ovl_apply_sign for several contexts (different lattices allowed) at once:
- * out[i] = sgn(H_W[ctx i]) in[i] with nrhs[i] spinors.  All contexts must be
- * on one device and share the node set and solver settings of ctxs[0]; the
- * work is enqueued on ctxs[0]'s stream as one captured graph per chunk of
- * iterations.  st (may be NULL) receives the aggregate. */
+ * out[i] = sum_j c_j (z_j - H_W[ctx i])^-1 in[i] with nrhs[i] spinors; every
+ * context must have its gauge field and masses set.  The node set and solver
+ * settings of ctxs[0] are used for every context during the call (each
+ * context's own settings are restored afterwards).  All contexts must be on
+ * one device, 1 <= nctx <= 64.  Each seed-iteration stage is ONE kernel launch
+ * over a job table of all contexts; chunks of 16 iterations are captured once
+ * as a HIP graph and replayed (OVL_GRAPHS=0 launches eagerly instead).  The
+ * work follows ctxs[0]'s stream.  st (may be NULL) receives the aggregate:
+ * max iterations, summed active shifts, max residual estimate. */
 int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const void* const* in,
                            void* const* out, const int32_t* nrhs, ovl_stats* st);
 

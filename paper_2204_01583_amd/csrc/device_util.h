@@ -72,10 +72,11 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
     return (b < per * 8u) ? (b % 8u) * per + b / 8u : b;
 }
 
-// A source is live at iteration k while it has no error and some shift is
-// still active (per-slice counts written by the previous iteration).
+// A source is live at iteration k while it has no error, k is below the
+// iteration limit and some shift is still active (per-slice counts written by
+// the previous iteration).
 __device__ __forceinline__ bool src_live(const SrcState& S, const ShiftDev& sh, int n, int k) {
-    if (S.status != 0) return false;
+    if (S.status != 0 || k >= sh.maxk) return false;
     const int* c = sh.cnt + ((size_t)(k & 1) * sh.nsrc + n) * kMaxSlices;
     int t = 0;
     for (int i = 0; i < sh.nslices; ++i) t += c[i];

@@ -33,23 +33,21 @@ void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const 
                    int variant = 0);
 int wilson_blocks(const Geom& g);
 
-// ---- seed iteration k, kernels K2 and K3 (vector grids of nbe blocks/source) --
+// ---- seed iteration over a job table (device-side iteration counter kdev) --
 int vec_blocks(int64_t n12, int nslices);
-// alpha_k, pi_{k+1}^j, alpha^j; r_out = r_in - alpha q; part_e = ||r_out||^2 partials
+int wilson_grid_blocks(const Geom& g, int nrhs, int variant);
+// K1 for every job: q = z_s p - H p, <r_k, q> partials
 template <typename R>
-void launch_update_r(const C2<R>* rin, C2<R>* rout, const C2<R>* q, SrcState* st,
-                     const double2* part_w, int nsb, double* part_e, int nbe, int64_t n12,
-                     const ShiftDev& sh, int k, hipStream_t s);
-// beta_k, beta^j, residuals, deactivation (+ history); p = r + beta p
+void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
+                        int variant, hipStream_t s);
+// K2 (alpha, pi^j, r update) and K3 (beta, shift bookkeeping, p update or sweep)
 template <typename R>
-void launch_update_p(const C2<R>* r, C2<R>* p, SrcState* st, const double* part_e, int nbe,
-                     int64_t n12, const ShiftDev& sh, int k, hipStream_t s);
-// the same scalars, then the fused (s += c_j alpha^j p_j) or reference
-// (x_j += alpha^j p_j) shift sweep with p_j and p updates
-template <typename R>
-void launch_sweep(bool ref, const C2<R>* r, C2<R>* p, C2<R>* pj, double2* acc,
-                  const double2* b0, SrcState* st, const double* part_e, int nbe, int64_t n12,
-                  const ShiftDev& sh, int k, hipStream_t s);
+void launch_iteration_k23(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
+                          int form, int maxJ, hipStream_t s);
+void launch_advance(int* kdev, hipStream_t s);
+// two-pass form, second pass: s = h_0 b
+void launch_s_init(const double2* b, const double2* h, int maxk, double2* s, int64_t n12, int nsrc,
+                   hipStream_t st);
 void launch_sum_ref(const double2* xj, const double2* c, double2* sacc, int J, int64_t n12,
                     int nsrc, hipStream_t s);
 // ||b||^2 and the iteration-0 state

@@ -166,32 +166,42 @@ int vec_blocks(int64_t n12, int nslices) {
     return nb;
 }
 
-// K2: alpha, shifted pi / alpha^j, r update and ||r_{k+1}||^2 partials
+// Decode a vector-grid block: job, source n and block bx of nbx for it.
+struct VecBlock {
+    int j, n, bx;
+};
+__device__ __forceinline__ VecBlock vec_block(const JobDesc* jobs, int njobs) {
+    const int gb = (int)blockIdx.x;
+    int j = 0;
+    while (j + 1 < njobs && gb >= jobs[j + 1].vec_b0) ++j;
+    const int local = gb - jobs[j].vec_b0;
+    return VecBlock{j, local / jobs[j].nbe, local % jobs[j].nbe};
+}
+
+// K2 body: alpha, shifted pi / alpha^j, r update and ||r_{k+1}||^2 partials.
+// Two-pass form, second pass (J.h != null): s += h_{k+1} r_{k+1} as well.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_update_r(const C2<R>* __restrict__ rin,
-                                                     C2<R>* __restrict__ rout,
-                                                     const C2<R>* __restrict__ q,
-                                                     SrcState* __restrict__ st,
-                                                     const double2* __restrict__ part_w, int nsb,
-                                                     double* __restrict__ part_e, int64_t n12,
-                                                     ShiftDev sh, int k) {
-    const int n = blockIdx.y;
-    SrcState& S = st[n];
+__device__ __forceinline__ void update_r_block(const JobDesc& J, int n, int bx, int k) {
+    const int f = sizeof(R) == 4 ? 1 : 0;
+    const ShiftDev& sh = J.sh;
+    SrcState& S = J.st[n];
     if (!src_live(S, sh, n, k)) return;
+    const int nbx = J.nbe, nsb = J.nsb;
+    const int64_t n12 = 12 * J.g.V;
     __shared__ double shm[kBlock / 64];
-    const double2 rq = sum_partials_c(part_w + (size_t)n * nsb, nsb, shm);
+    const double2 rq = sum_partials_c(J.part_w + (size_t)n * nsb, nsb, shm);
     const double rr = S.rr[k & 1];
     const bool bad = !finite2(rq);
     const bool brk = !bad && cabs2(rq) <= 1e-300 * rr;
     if (bad || brk) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) S.status = bad ? OVL_E_NONFINITE : OVL_E_BREAKDOWN;
+        if (bx == 0 && threadIdx.x == 0) S.status = bad ? OVL_E_NONFINITE : OVL_E_BREAKDOWN;
         return;
     }
     const double2 alpha = cdiv(make_double2(rr, 0.0), rq);
-    if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[k & 1] = alpha;
-    if ((int)blockIdx.x < sh.nslices) {
+    if (bx == 0 && threadIdx.x == 0) S.alpha[k & 1] = alpha;
+    if (bx < sh.nslices) {
         // pi_{k+1} = (1 + alpha Dz) pi_k + (alpha beta_{k-1} / alpha_{k-1}) (pi_k - pi_{k-1})
-        const int j = blockIdx.x * kBlock + threadIdx.x;
+        const int j = bx * kBlock + threadIdx.x;
         const size_t o = (size_t)n * sh.J + j;
         const size_t stride3 = (size_t)sh.nsrc * sh.J;
         if (j < sh.J && sh.active[(size_t)(k & 1) * stride3 + o]) {
@@ -207,45 +217,57 @@ __global__ __launch_bounds__(kBlock) void k_update_r(const C2<R>* __restrict__ r
         }
     }
     const R ar = (R)alpha.x, ai = (R)alpha.y;
-    const C2<R>* ri = rin + (size_t)n * n12;
-    C2<R>* ro = rout + (size_t)n * n12;
-    const C2<R>* qq = q + (size_t)n * n12;
+    const C2<R>* ri = job_rk<const C2<R>>(J, k, f) + (size_t)n * n12;
+    C2<R>* ro = job_rk<C2<R>>(J, k + 1, f) + (size_t)n * n12;
+    const C2<R>* qq = static_cast<const C2<R>*>(J.q[f]) + (size_t)n * n12;
+    const bool acc2 = J.h != nullptr;
+    const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
+    double2* sacc = J.s64 + (size_t)n * n12;
     double acc = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
-         e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)nbx * kBlock) {
         const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e);
         const cx<R> rn = mk<R>(r.re - (ar * qv.re - ai * qv.im), r.im - (ar * qv.im + ai * qv.re));
         stc<R>(ro, e, rn);
         acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
+        if (acc2) {
+            double2 sv = sacc[e];
+            sv.x += hk.x * (double)rn.re - hk.y * (double)rn.im;
+            sv.y += hk.x * (double)rn.im + hk.y * (double)rn.re;
+            sacc[e] = sv;
+        }
     }
     const double t = block_sum<kBlock>(acc, shm);
-    if (threadIdx.x == 0) part_e[(size_t)n * gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0) J.part_e[(size_t)n * nbx + bx] = t;
 }
 
 // K3 scalar part, shared by the p update and the sweeps.  Returns false if
 // the source is not live (then the shift slices publish zero counts).
 // On return beta = beta_k.
-__device__ __forceinline__ bool k3_scalars(SrcState& S, const ShiftDev& sh, const double* part_e,
-                                           int nbe, int n, int k, double2& beta, double* shm) {
+__device__ __forceinline__ bool k3_scalars(const JobDesc& J, int n, int bx, int k, double2& beta,
+                                           double* shm) {
+    const ShiftDev& sh = J.sh;
+    SrcState& S = J.st[n];
     const size_t stride3 = (size_t)sh.nsrc * sh.J;
     int* cnt_next = sh.cnt + ((size_t)((k + 1) & 1) * sh.nsrc + n) * kMaxSlices;
     if (!src_live(S, sh, n, k)) {
-        if ((int)blockIdx.x < sh.nslices && threadIdx.x == 0) cnt_next[blockIdx.x] = 0;
+        // a finished source stays finished; at the iteration limit the counts
+        // of the last iteration are kept, so the host sees what is still active
+        if (k < sh.maxk && bx < sh.nslices && threadIdx.x == 0) cnt_next[bx] = 0;
         return false;
     }
-    const double rrn = sum_partials_re<double>(part_e + (size_t)n * nbe, nbe, shm);
+    const double rrn = sum_partials_re<double>(J.part_e + (size_t)n * J.nbe, J.nbe, shm);
     const double2 al = S.alpha[k & 1];
     const double2 ph = cdiv(al, make_double2(al.x, -al.y));  // alpha / conj(alpha)
     const double ratio = rrn / S.rr[k & 1];
     beta = make_double2(ph.x * ratio, ph.y * ratio);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bx == 0 && threadIdx.x == 0) {
         S.beta[k & 1] = beta;
         S.rr[(k + 1) & 1] = rrn;
         S.iter = k + 1;
         if (!isfinite(rrn)) S.status = OVL_E_NONFINITE;
     }
-    if ((int)blockIdx.x < sh.nslices) {
-        const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (bx < sh.nslices) {
+        const int j = bx * kBlock + threadIdx.x;
         const size_t o = (size_t)n * sh.J + j;
         int stay = 0;
         double res = 0.0;
@@ -273,47 +295,40 @@ __device__ __forceinline__ bool k3_scalars(SrcState& S, const ShiftDev& sh, cons
         const double tot = block_sum<kBlock>((double)stay, shm);
         const double mx = block_max<kBlock>(res, shm);
         if (threadIdx.x == 0) {
-            cnt_next[blockIdx.x] = (int)(tot + 0.5);
-            sh.mres[(size_t)n * kMaxSlices + blockIdx.x] = mx;
+            cnt_next[bx] = (int)(tot + 0.5);
+            sh.mres[(size_t)n * kMaxSlices + bx] = mx;
         }
     }
     return true;
 }
 
-// K3, basis forms: p <- r_{k+1} + beta p
+// K3 body, basis forms: p <- r_{k+1} + beta p
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_update_p(const C2<R>* __restrict__ r,
-                                                     C2<R>* __restrict__ p, SrcState* st,
-                                                     const double* __restrict__ part_e, int nbe,
-                                                     int64_t n12, ShiftDev sh, int k) {
-    const int n = blockIdx.y;
+__device__ __forceinline__ void update_p_block(const JobDesc& J, int n, int bx, int k) {
+    const int f = sizeof(R) == 4 ? 1 : 0;
     __shared__ double shm[kBlock / 64];
     double2 beta;
-    if (!k3_scalars(st[n], sh, part_e, nbe, n, k, beta, shm)) return;
+    if (!k3_scalars(J, n, bx, k, beta, shm)) return;
+    const int64_t n12 = 12 * J.g.V;
     const R br = (R)beta.x, bi = (R)beta.y;
-    const C2<R>* rr = r + (size_t)n * n12;
-    C2<R>* pp = p + (size_t)n * n12;
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
-         e += (int64_t)gridDim.x * kBlock) {
+    const C2<R>* rr = job_rk<const C2<R>>(J, k + 1, f) + (size_t)n * n12;
+    C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
+    for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
         const cx<R> rv = ld<R>(rr, e), po = ld<R>(pp, e);
         stc<R>(pp, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
     }
 }
 
-// K3, sweep forms.  Every block rebuilds the list of shifts active at the
-// start of iteration k in LDS: coefficient (c_j alpha^j, or alpha^j for the
-// reference form), 1/pi_{k+1}^j and beta^j.  Then, per component:
+// K3 body, sweep forms.  Every block rebuilds the list of shifts active at
+// the start of iteration k in LDS: coefficient (c_j alpha^j, or alpha^j for
+// the reference form), 1/pi_{k+1}^j and beta^j.  Then, per component:
 //   s += sum_l coef_l p_{j_l}   (fused)  or  x_j += alpha^j p_j (reference)
 //   p_{j_l} <- r / pi_{k+1} + beta^j p_{j_l};   p <- r + beta p
-// In the first iteration p_j = b for every j, read from b0 instead.
+// In the first iteration p_j = b for every j, read from b instead.
 template <typename R, bool REF>
-__global__ __launch_bounds__(kBlock) void k_sweep(const C2<R>* __restrict__ r,
-                                                  C2<R>* __restrict__ p, C2<R>* __restrict__ pj,
-                                                  double2* __restrict__ acc_out,
-                                                  const double2* __restrict__ b0, SrcState* st,
-                                                  const double* __restrict__ part_e, int nbe,
-                                                  int64_t n12, ShiftDev sh, int k) {
-    const int n = blockIdx.y;
+__device__ __forceinline__ void sweep_block(const JobDesc& J, int n, int bx, int k) {
+    const int f = sizeof(R) == 4 ? 1 : 0;
+    const ShiftDev& sh = J.sh;
     __shared__ double shm[kBlock / 64];
     extern __shared__ unsigned char lds_raw[];
     double2* l_coef = reinterpret_cast<double2*>(lds_raw);
@@ -323,8 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const C2<R>* __restrict__ r,
     __shared__ int wcount[kBlock / 64];
     __shared__ int base;
     double2 beta;
-    SrcState& S = st[n];
-    if (!k3_scalars(S, sh, part_e, nbe, n, k, beta, shm)) return;
+    if (!k3_scalars(J, n, bx, k, beta, shm)) return;
     const size_t stride3 = (size_t)sh.nsrc * sh.J;
     if (threadIdx.x == 0) base = 0;
     __syncthreads();
@@ -363,11 +377,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const C2<R>* __restrict__ r,
         __syncthreads();
     }
     const int nl = base;
+    const int64_t n12 = 12 * J.g.V;
     const R br = (R)beta.x, bi = (R)beta.y;
-    const C2<R>* rr = r + (size_t)n * n12;
-    C2<R>* pp = p + (size_t)n * n12;
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
-         e += (int64_t)gridDim.x * kBlock) {
+    const C2<R>* rr = static_cast<const C2<R>*>(J.r[f]) + (size_t)n * n12;
+    C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
+    C2<R>* pj = static_cast<C2<R>*>(J.pj[f]);
+    double2* acc_out = REF ? J.xj : J.s64;
+    const double2* b0 = J.b64;
+    for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
         const cx<R> rv = ld<R>(rr, e);
         const cx<R> bfirst = (k == 0) ? mk<R>((R)b0[(size_t)n * n12 + e].x, (R)b0[(size_t)n * n12 + e].y)
                                       : mk<R>(0, 0);
@@ -402,42 +419,71 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const C2<R>* __restrict__ r,
     }
 }
 
+// Job-table wrappers: one launch covers every (job, source, block) of a batch.
 template <typename R>
-void launch_update_r(const C2<R>* rin, C2<R>* rout, const C2<R>* q, SrcState* st,
-                     const double2* part_w, int nsb, double* part_e, int nbe, int64_t n12,
-                     const ShiftDev& sh, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_r<R>, dim3(nbe, sh.nsrc), dim3(kBlock), 0, s, rin, rout, q, st,
-                       part_w, nsb, part_e, n12, sh, k);
+__global__ __launch_bounds__(kBlock) void k_update_r_jobs(const JobDesc* __restrict__ jobs,
+                                                          int njobs, const int* __restrict__ kdev) {
+    const int k = (int)uniform((uint32_t)*kdev);
+    const VecBlock v = vec_block(jobs, njobs);
+    update_r_block<R>(jobs[v.j], v.n, v.bx, k);
 }
 template <typename R>
-void launch_update_p(const C2<R>* r, C2<R>* p, SrcState* st, const double* part_e, int nbe,
-                     int64_t n12, const ShiftDev& sh, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_p<R>, dim3(nbe, sh.nsrc), dim3(kBlock), 0, s, r, p, st, part_e,
-                       nbe, n12, sh, k);
+__global__ __launch_bounds__(kBlock) void k_update_p_jobs(const JobDesc* __restrict__ jobs,
+                                                          int njobs, const int* __restrict__ kdev) {
+    const int k = (int)uniform((uint32_t)*kdev);
+    const VecBlock v = vec_block(jobs, njobs);
+    update_p_block<R>(jobs[v.j], v.n, v.bx, k);
 }
+template <typename R, bool REF>
+__global__ __launch_bounds__(kBlock) void k_sweep_jobs(const JobDesc* __restrict__ jobs, int njobs,
+                                                       const int* __restrict__ kdev) {
+    const int k = (int)uniform((uint32_t)*kdev);
+    const VecBlock v = vec_block(jobs, njobs);
+    sweep_block<R, REF>(jobs[v.j], v.n, v.bx, k);
+}
+// the iteration counter of a batch, advanced once per seed iteration
+__global__ void k_advance(int* kdev) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *kdev += 1;
+}
+
 template <typename R>
-void launch_sweep(bool ref, const C2<R>* r, C2<R>* p, C2<R>* pj, double2* acc,
-                  const double2* b0, SrcState* st, const double* part_e, int nbe, int64_t n12,
-                  const ShiftDev& sh, int k, hipStream_t s) {
-    const size_t lds = (size_t)sh.J * (3 * sizeof(double2) + sizeof(int));
-    if (ref)
-        hipLaunchKernelGGL((k_sweep<R, true>), dim3(nbe, sh.nsrc), dim3(kBlock), lds, s, r, p, pj,
-                           acc, b0, st, part_e, nbe, n12, sh, k);
-    else
-        hipLaunchKernelGGL((k_sweep<R, false>), dim3(nbe, sh.nsrc), dim3(kBlock), lds, s, r, p, pj,
-                           acc, b0, st, part_e, nbe, n12, sh, k);
+void launch_iteration_k23(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
+                          int form, int maxJ, hipStream_t s) {
+    const dim3 grid(vec_blocks_total), blk(kBlock);
+    hipLaunchKernelGGL(k_update_r_jobs<R>, grid, blk, 0, s, jobs, njobs, kdev);
+    if (form == OVL_FORM_BASIS || form == OVL_FORM_TWOPASS) {
+        hipLaunchKernelGGL(k_update_p_jobs<R>, grid, blk, 0, s, jobs, njobs, kdev);
+    } else {
+        const size_t lds = (size_t)maxJ * (3 * sizeof(double2) + sizeof(int));
+        if (form == OVL_FORM_REFERENCE)
+            hipLaunchKernelGGL((k_sweep_jobs<R, true>), grid, blk, lds, s, jobs, njobs, kdev);
+        else
+            hipLaunchKernelGGL((k_sweep_jobs<R, false>), grid, blk, lds, s, jobs, njobs, kdev);
+    }
 }
-#define OVL_INST_K23(R)                                                                         \
-    template void launch_update_r<R>(const C2<R>*, C2<R>*, const C2<R>*, SrcState*,            \
-                                     const double2*, int, double*, int, int64_t,                \
-                                     const ShiftDev&, int, hipStream_t);                        \
-    template void launch_update_p<R>(const C2<R>*, C2<R>*, SrcState*, const double*, int,      \
-                                     int64_t, const ShiftDev&, int, hipStream_t);               \
-    template void launch_sweep<R>(bool, const C2<R>*, C2<R>*, C2<R>*, double2*, const double2*, \
-                                  SrcState*, const double*, int, int64_t, const ShiftDev&, int, \
-                                  hipStream_t);
-OVL_INST_K23(double)
-OVL_INST_K23(float)
+template void launch_iteration_k23<double>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
+template void launch_iteration_k23<float>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
+void launch_advance(int* kdev, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, kdev);
+}
+
+// two-pass form, second pass: s = h_0 b (r_0 = b)
+__global__ __launch_bounds__(kBlock) void k_s_init(const double2* __restrict__ b,
+                                                   const double2* __restrict__ h, int maxk,
+                                                   double2* __restrict__ sv, int64_t n12) {
+    const int n = blockIdx.y;
+    const double2 h0 = h[(size_t)n * (maxk + 1)];
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
+        const double2 v = b[(size_t)n * n12 + e];
+        sv[(size_t)n * n12 + e] = make_double2(h0.x * v.x - h0.y * v.y, h0.x * v.y + h0.y * v.x);
+    }
+}
+void launch_s_init(const double2* b, const double2* h, int maxk, double2* s, int64_t n12, int nsrc,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_s_init, dim3(vec_blocks(n12, 1), nsrc), dim3(kBlock), 0, st, b, h, maxk,
+                       s, n12);
+}
 
 // s = sum_j c_j x_j (reference form, once at the end; fixed order in j)
 __global__ __launch_bounds__(kBlock) void k_sum_ref(const double2* __restrict__ xj,

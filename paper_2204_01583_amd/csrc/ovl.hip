@@ -72,6 +72,12 @@ struct ovl_ctx {
     int host_state_n = 0;
     DBuf bench_a, bench_b;
     DBuf fY, fX, fpsi, facc, fc, fpart;  // force work space
+    DBuf slot_table;                       // basis form: device table of slot-chunk bases
+    // solve stream (graphs cannot be captured on the legacy null stream) and handoff events
+    hipStream_t ws = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    DBuf jobs_dev;                         // batch lead: JobDesc table + iteration counter
+    struct GraphCache { std::string key; hipGraphExec_t exec = nullptr; } graphs[2];
     // per-kernel-class event timing (ovl_set_profiling)
     static constexpr int kClasses = 8;
     bool prof_on = false;
@@ -149,8 +155,9 @@ struct DeviceGuard {
 // Brackets one launch of class `cls` with two events (profiling only).
 struct ProfScope {
     ovl_ctx* ctx;
+    hipStream_t st;
     int idx = -1;
-    ProfScope(ovl_ctx* c, int cls, double bytes) : ctx(c) {
+    ProfScope(ovl_ctx* c, hipStream_t s, int cls, double bytes) : ctx(c), st(s) {
         if (!ctx->prof_on) return;
         const size_t need = 2 * (ctx->prof_pending.size() + 1);
         while (ctx->ev_pool.size() < need) {
@@ -160,10 +167,10 @@ struct ProfScope {
         }
         idx = (int)ctx->prof_pending.size();
         ctx->prof_pending.push_back({cls, 2 * idx, bytes});
-        (void)hipEventRecord(ctx->ev_pool[2 * idx], ctx->stream);
+        (void)hipEventRecord(ctx->ev_pool[2 * idx], st);
     }
     ~ProfScope() {
-        if (idx >= 0) (void)hipEventRecord(ctx->ev_pool[2 * idx + 1], ctx->stream);
+        if (idx >= 0) (void)hipEventRecord(ctx->ev_pool[2 * idx + 1], st);
     }
 };
 
@@ -251,10 +258,15 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
                     &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_e,
                     &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
                     &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->fY, &ctx->fX, &ctx->fpsi,
-                    &ctx->facc, &ctx->fc, &ctx->fpart};
+                    &ctx->facc, &ctx->fc, &ctx->fpart, &ctx->slot_table, &ctx->jobs_dev};
     for (DBuf* b : bufs) b->release();
     for (DBuf& b : ctx->slot_chunks) b.release();
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto& gc : ctx->graphs)
+        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->ws) (void)hipStreamDestroy(ctx->ws);
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
     delete ctx;
     return OVL_OK;
@@ -339,7 +351,7 @@ extern "C" int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, dou
     if (!ctx) return OVL_E_ARG;
     if (precision != OVL_PREC_FP64 && precision != OVL_PREC_MIXED)
         return fail(ctx, OVL_E_ARG, "unknown precision %d", precision);
-    if (form < OVL_FORM_REFERENCE || form > OVL_FORM_BASIS)
+    if (form < OVL_FORM_REFERENCE || form > OVL_FORM_TWOPASS)
         return fail(ctx, OVL_E_ARG, "unknown or unsupported form %d", form);
     if (!(tol > 0.0 && tol < 1.0)) return fail(ctx, OVL_E_ARG, "need 0 < tol < 1");
     if (maxiter < 1 || maxiter > 1000000) return fail(ctx, OVL_E_ARG, "bad maxiter %d", maxiter);
@@ -566,7 +578,6 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
 // ============================================================================
 namespace {
 
-constexpr int kSlotChunk = 32;  // residual slots per basis allocation
 
 struct Work {
     int nsrc, J, maxk;
@@ -584,6 +595,9 @@ struct Work {
     int var64, var32;      // stencil variants (autotuned)
     int k_switch;          // first FP32 iteration (mixed), or -1
     int K;                 // seed iterations of the last solve (max over sources)
+    size_t rpp;            // two-pass: elements between the two r buffers
+    char** slot_tab;       // basis: device table of slot-chunk bases
+    int n_tab;             // chunks published in slot_tab
     double2 *dz, *cj;
     double2 *h_a, *h_b, *h_pi, *W, *h;
 };
@@ -606,8 +620,9 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     w.maxk = ctx->maxiter;
     const size_t vec64 = (size_t)nsrc * N * sizeof(double2);
     const size_t vec32 = (size_t)nsrc * N * sizeof(float2);
+    const bool twopass = form == OVL_FORM_TWOPASS;
     HIPCHK(ctx, ctx->b64.ensure(vec64));
-    HIPCHK(ctx, ctx->r64.ensure(vec64));
+    HIPCHK(ctx, ctx->r64.ensure(twopass ? 2 * vec64 : vec64));
     HIPCHK(ctx, ctx->p64.ensure(vec64));
     HIPCHK(ctx, ctx->q64.ensure(vec64));
     HIPCHK(ctx, ctx->s64.ensure(vec64));
@@ -620,8 +635,11 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     w.pj64 = w.xj = nullptr;
     w.chunks.clear();
     w.slot_bytes = vec64;
+    w.rpp = (size_t)nsrc * N;
+    w.slot_tab = nullptr;
+    w.n_tab = 0;
     if (mixed) {
-        HIPCHK(ctx, ctx->r32.ensure(vec32));
+        HIPCHK(ctx, ctx->r32.ensure(twopass ? 2 * vec32 : vec32));
         HIPCHK(ctx, ctx->p32.ensure(vec32));
         HIPCHK(ctx, ctx->q32.ensure(vec32));
         w.r32 = ctx->r32.as<float2>();
@@ -641,6 +659,11 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
         }
     }
     const bool basis = form == OVL_FORM_BASIS;
+    const bool hist = basis || twopass;
+    if (basis) {
+        HIPCHK(ctx, ctx->slot_table.ensure(((size_t)w.maxk / kSlotChunk + 2) * sizeof(char*)));
+        w.slot_tab = ctx->slot_table.as<char*>();
+    }
     if (basis && ctx->slot_chunk_bytes != vec64 * kSlotChunk) {
         // slot geometry changed: drop the old chunks
         for (DBuf& b : ctx->slot_chunks) b.release();
@@ -685,7 +708,7 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // tab is pageable and goes out of scope
     w.h_a = w.h_b = w.h_pi = w.W = w.h = nullptr;
-    if (basis) {
+    if (hist) {
         const size_t hs = (size_t)nsrc * (w.maxk + 1) * J;
         HIPCHK(ctx, ctx->hist.ensure(3 * hs * sizeof(double2)));
         HIPCHK(ctx, ctx->W.ensure(hs * sizeof(double2)));
@@ -713,208 +736,430 @@ template <typename R> R* slot_ptr(const Work& w, int i) {
     return reinterpret_cast<R*>(w.chunks[i / kSlotChunk] + (size_t)(i % kSlotChunk) * w.slot_bytes);
 }
 
-// make sure residual slots 0 .. upto exist
-int ensure_slots(ovl_ctx* ctx, Work& w, int upto) {
-    const int need = upto / kSlotChunk + 1;
+// make sure residual slots 0 .. upto exist and are published in the device table
+int ensure_slots(ovl_ctx* ctx, Work& w, int upto, hipStream_t s) {
+    const int need = std::min(upto, w.maxk) / kSlotChunk + 1;
     while ((int)ctx->slot_chunks.size() < need) {
         ctx->slot_chunks.emplace_back();
         HIPCHK(ctx, ctx->slot_chunks.back().ensure(ctx->slot_chunk_bytes));
     }
     w.chunks.clear();
     for (DBuf& b : ctx->slot_chunks) w.chunks.push_back(b.as<char>());
+    if ((int)w.chunks.size() > w.n_tab) {
+        // pageable source: the copy is staged at the call, before the next replay reads it
+        HIPCHK(ctx, hipMemcpyAsync(w.slot_tab, w.chunks.data(), w.chunks.size() * sizeof(char*),
+                                   hipMemcpyHostToDevice, s));
+        w.n_tab = (int)w.chunks.size();
+    }
     return OVL_OK;
 }
 
-// One seed iteration k in precision R (double before the switch, float after):
-// K1 stencil + <r,q>, K2 r update, K3 p update or shift sweep.
+// Work stream of a context (created on first use; default priority).
+int solve_stream(ovl_ctx* ctx, hipStream_t* out) {
+    if (!ctx->ws) {
+        HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->ws, hipStreamNonBlocking));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    }
+    *out = ctx->ws;
+    return OVL_OK;
+}
+
+bool graphs_enabled(const ovl_ctx* ctx) {
+    if (ctx->prof_on) return false;  // per-launch events need eager launches
+    const char* e = getenv("OVL_GRAPHS");
+    return !(e && e[0] == '0');
+}
+
+constexpr int kChunk = 16;  // seed iterations per captured graph / per convergence poll
+
+struct Batch {
+    std::vector<ovl_ctx*> ctx;
+    std::vector<Work*> w;
+    std::vector<JobDesc> desc;
+    int sten_total = 0, vec_total = 0, variant64 = 0, variant32 = 0, form = 0, maxJ = 0;
+    JobDesc* desc_dev = nullptr;
+    int* kdev = nullptr;
+};
+
+void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, int variant, int& sten_b0, int& vec_b0) {
+    d.g = c->g;
+    d.kappa = kappa_of(c->m0);
+    d.zs = c->zseed;
+    d.U[0] = c->U64.p;
+    d.U[1] = c->U32.p;
+    d.nsrc = w.nsrc;
+    d.nsb = wilson_blocks(c->g);
+    d.sten_b0 = sten_b0;
+    d.sten_nb = wilson_grid_blocks(c->g, w.nsrc, variant);
+    sten_b0 += d.sten_nb;
+    d.vec_b0 = vec_b0;
+    d.nbe = w.nbe;
+    vec_b0 += w.nbe * w.nsrc;
+    d.st = w.st;
+    d.sh = w.sh;
+    d.part_w = w.part_w;
+    d.part_e = w.part_e;
+    d.p[0] = w.p64; d.p[1] = w.p32;
+    d.q[0] = w.q64; d.q[1] = w.q32;
+    d.r[0] = w.r64; d.r[1] = w.r32;
+    d.rpp = w.rpp;
+    d.b64 = w.b64;
+    d.s64 = w.s64;
+    d.pj[0] = w.pj64; d.pj[1] = w.pj32;
+    d.xj = w.xj;
+    d.slots = w.slot_tab;
+    d.slot_bytes = w.slot_bytes;
+    d.h = nullptr;
+    d.ksw = 1 << 30;
+    d.form = c->form;
+}
+
+// Enqueue `count` seed iterations of every job in precision R.
 template <typename R>
-void enqueue_iteration(ovl_ctx* ctx, const Work& w, int k, int form, hipStream_t s, C2<R>* r,
-                       C2<R>* p, C2<R>* q, C2<R>* pj, const C2<R>* U, int nact_total) {
-    const int64_t N = w.N;
-    const bool basis = form == OVL_FORM_BASIS;
-    const double es = sizeof(C2<R>);
+void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool prof,
+                   int nact_total) {
+    ovl_ctx* lead = B.ctx[0];
     const int c32 = sizeof(R) == 4 ? 1 : 0;
-    const double V = (double)ctx->g.V;
-    // r_k: working vector, or basis slot k (FP32 slots are packed at the slot base)
-    C2<R>* rk = basis ? slot_ptr<C2<R>>(w, k) : r;
-    C2<R>* rk1 = basis ? slot_ptr<C2<R>>(w, k + 1) : r;
-    {   // links once, p read, q written, r read for <r,q>
-        ProfScope ps(ctx, 0 + c32, V * es * (36.0 + 36.0 * w.nsrc));
-        launch_wilson<R>(1, p, q, U, ctx->g, kappa_of(ctx->m0), ctx->zseed, rk, w.part_w, w.st,
-                         &w.sh, k, w.nsrc, s, c32 ? w.var32 : w.var64);
+    const double es = sizeof(C2<R>);
+    double sten_b = 0, vec_b = 0, sweep_b = 0;
+    if (prof) {
+        for (size_t i = 0; i < B.w.size(); ++i) {
+            const double V = (double)B.ctx[i]->g.V, n = B.w[i]->nsrc, N = 12 * V;
+            sten_b += V * es * (36.0 + 36.0 * n);
+            vec_b += 3.0 * es * N * n;
+            const bool ref = B.form == OVL_FORM_REFERENCE;
+            sweep_b += N * (n * (3.0 * es + (ref ? 0.0 : 32.0)));
+        }
+        const double N0 = 12.0 * B.ctx[0]->g.V;
+        sweep_b += N0 * nact_total * (2.0 * es + (B.form == OVL_FORM_REFERENCE ? 32.0 : 0.0));
     }
-    {
-        ProfScope ps(ctx, 2 + c32, 3.0 * es * N * w.nsrc);
-        launch_update_r<R>(rk, rk1, q, w.st, w.part_w, w.nbw, w.part_e, w.nbe, N, w.sh, k, s);
+    const int var = c32 ? B.variant32 : B.variant64;
+    const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
+    for (int i = 0; i < count; ++i) {
+        (void)k_host;
+        {
+            ProfScope ps(lead, s, prof ? 0 + c32 : -1, sten_b);
+            launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.sten_total, var, s);
+        }
+        {
+            // K2 and K3 together: r update (3 vectors) plus p update (3) or the sweep
+            ProfScope ps(lead, s, prof ? (sweep ? 4 + c32 : 2 + c32) : -1,
+                         sweep ? vec_b + sweep_b : 2.0 * vec_b);
+            launch_iteration_k23<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.vec_total, B.form,
+                                    B.maxJ, s);
+        }
+        launch_advance(B.kdev, s);
     }
-    if (basis) {
-        ProfScope ps(ctx, 2 + c32, 3.0 * es * N * w.nsrc);
-        launch_update_p<R>(rk1, p, w.st, w.part_e, w.nbe, N, w.sh, k, s);
+}
+
+// Capture (once per key) and replay a graph of kChunk iterations in precision R.
+template <typename R>
+int replay_chunk(Batch& B, hipStream_t s) {
+    ovl_ctx* lead = B.ctx[0];
+    const int ph = sizeof(R) == 4 ? 1 : 0;
+    char kb[256];
+    snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d", (void*)B.desc_dev, (void*)B.kdev,
+             B.desc.size(), B.sten_total, B.vec_total, ph ? B.variant32 : B.variant64, B.form, B.maxJ);
+    auto& gc = lead->graphs[ph];
+    if (!gc.exec || gc.key != kb) {
+        if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+        gc.exec = nullptr;
+        hipGraph_t graph;
+        HIPCHK(lead, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        enqueue_chunk<R>(B, kChunk, 0, s, false, 0);
+        HIPCHK(lead, hipStreamEndCapture(s, &graph));
+        const hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(lead, e);
+        gc.key = kb;
+    }
+    HIPCHK(lead, hipGraphLaunch(gc.exec, s));
+    return OVL_OK;
+}
+
+int run_chunk(Batch& B, bool low, bool graphs, hipStream_t s, int k_host, int nact_total) {
+    if (graphs) return low ? replay_chunk<float>(B, s) : replay_chunk<double>(B, s);
+    const bool prof = B.ctx[0]->prof_on;
+    if (low) enqueue_chunk<float>(B, kChunk, k_host, s, prof, nact_total);
+    else enqueue_chunk<double>(B, kChunk, k_host, s, prof, nact_total);
+    HIPCHK(B.ctx[0], hipGetLastError());
+    return OVL_OK;
+}
+
+// Initial vectors and state of one job (r = p = b; s = 0; x_j = 0; slot 0 = b).
+int init_job(ovl_ctx* c, Work& w, hipStream_t s) {
+    const size_t vec64 = (size_t)w.nsrc * w.N * sizeof(double2);
+    const int form = c->form;
+    if (form == OVL_FORM_BASIS) {
+        int rc = ensure_slots(c, w, kChunk + 1, s);
+        if (rc) return rc;
+        HIPCHK(c, hipMemcpyAsync(slot_ptr<double2>(w, 0), w.b64, vec64, hipMemcpyDeviceToDevice, s));
     } else {
-        // r read, p read+write, s read+write (FP64) per source; p_j read+write
-        // (and x_j read+write in FP64 for the reference form) per active shift
-        const bool ref = form == OVL_FORM_REFERENCE;
-        const double b = (double)N * (w.nsrc * (3.0 * es + (ref ? 0.0 : 32.0)) +
-                                      nact_total * (2.0 * es + (ref ? 32.0 : 0.0)));
-        ProfScope ps(ctx, 4 + c32, b);
-        launch_sweep<R>(ref, r, p, pj, ref ? w.xj : w.s64, w.b64, w.st, w.part_e, w.nbe, N, w.sh,
-                        k, s);
+        HIPCHK(c, hipMemcpyAsync(w.r64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
     }
+    HIPCHK(c, hipMemcpyAsync(w.p64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
+    if (form == OVL_FORM_FUSED) HIPCHK(c, hipMemsetAsync(w.s64, 0, vec64, s));
+    if (form == OVL_FORM_REFERENCE) HIPCHK(c, hipMemsetAsync(w.xj, 0, vec64 * w.J, s));
+    launch_init_state(w.st, w.b64, w.part_e, w.N, w.sh, s);
+    HIPCHK(c, hipGetLastError());
+    return OVL_OK;
+}
+
+// FP64 -> FP32 switch of one job at iteration k
+void convert_job(ovl_ctx* c, Work& w, int k, hipStream_t s) {
+    const int64_t n = (int64_t)w.nsrc * w.N;
+    launch_convert_64_to_32(w.p64, w.p32, n, s);
+    if (c->form == OVL_FORM_BASIS) {
+        launch_convert_64_to_32(slot_ptr<double2>(w, k), w.r32, n, s);
+        (void)hipMemcpyAsync(slot_ptr<float2>(w, k), w.r32, (size_t)n * sizeof(float2),
+                             hipMemcpyDeviceToDevice, s);
+    } else if (c->form == OVL_FORM_TWOPASS) {
+        launch_convert_64_to_32(w.r64 + (size_t)(k & 1) * w.rpp, w.r32 + (size_t)(k & 1) * w.rpp, n, s);
+    } else {
+        launch_convert_64_to_32(w.r64, w.r32, n, s);
+        launch_convert_64_to_32(w.pj64, w.pj32, n * w.J, s);
+    }
+}
+
+struct PollResult {
+    int status = OVL_OK;
+    bool all_done = true;
+    double maxres = 0.0;
+    int iters = 0, nact = 0;
+};
+
+PollResult poll(Batch& B, int k_host, hipStream_t s, int* rc_out) {
+    PollResult P;
+    *rc_out = OVL_OK;
+    for (size_t i = 0; i < B.w.size(); ++i) {
+        ovl_ctx* c = B.ctx[i];
+        Work& w = *B.w[i];
+        if (hipMemcpyAsync(c->host_state, w.st, w.state_bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
+            *rc_out = fail(B.ctx[0], OVL_E_HIP, "state copy failed");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) *rc_out = fail(B.ctx[0], OVL_E_HIP, "stream sync failed");
+    prof_collect(B.ctx[0]);
+    for (size_t i = 0; i < B.w.size(); ++i) {
+        ovl_ctx* c = B.ctx[i];
+        Work& w = *B.w[i];
+        const char* hb = reinterpret_cast<const char*>(c->host_state);
+        const int* hcnt = reinterpret_cast<const int*>(hb + state_cnt_off(w.nsrc)) +
+                          (size_t)(std::min(k_host, w.maxk) & 1) * w.nsrc * kMaxSlices;
+        const double* hmres = reinterpret_cast<const double*>(hb + state_mres_off(w.nsrc));
+        for (int n = 0; n < w.nsrc; ++n) {
+            const SrcState& S = c->host_state[n];
+            if (S.status != OVL_OK && P.status == OVL_OK) P.status = S.status;
+            int na = 0;
+            for (int q = 0; q < w.sh.nslices; ++q) {
+                na += hcnt[n * kMaxSlices + q];
+                P.maxres = std::max(P.maxres, hmres[n * kMaxSlices + q]);
+            }
+            P.all_done = P.all_done && (na == 0 || S.status != OVL_OK);
+            P.iters = std::max(P.iters, S.iter);
+            P.nact += na;
+        }
+    }
+    return P;
 }
 
 }  // namespace
 
-// Runs the shifted solver on nsrc sources packed in w.b64 and leaves
-// s = sum_j c_j y_j in w.s64.  Returns a status; fills ctx->last.
-static int solve(ovl_ctx* ctx, Work& w) {
-    hipStream_t s = ctx->stream;
-    const int form = ctx->form;
-    const bool mixed = ctx->precision == OVL_PREC_MIXED;
-    const int64_t N = w.N;
-    const size_t vec64 = (size_t)w.nsrc * N * sizeof(double2);
-    w.var64 = stencil_variant(ctx, w.nsrc, 0);
-    w.var32 = mixed ? stencil_variant(ctx, w.nsrc, 1) : 0;
+// Runs the shifted solver for every job of a batch (their sources packed in
+// w->b64) and leaves s = sum_j c_j y_j in each w->s64.  Work is enqueued on
+// the lead context's solve stream after its caller stream.  Returns a status
+// and fills ctx->last of every context.
+static int solve_batch(Batch& B) {
+    ovl_ctx* lead = B.ctx[0];
+    hipStream_t s;
+    int rc = solve_stream(lead, &s);
+    if (rc) return rc;
+    HIPCHK(lead, hipEventRecord(lead->ev_in, lead->stream));
+    HIPCHK(lead, hipStreamWaitEvent(s, lead->ev_in, 0));
+    const bool mixed = lead->precision == OVL_PREC_MIXED;
+    const int form = lead->form;
+    const bool graphs = graphs_enabled(lead);
+    const int maxk = lead->maxiter;
     hipEvent_t e0, e1;
-    HIPCHK(ctx, hipEventCreate(&e0));
-    HIPCHK(ctx, hipEventCreate(&e1));
-    HIPCHK(ctx, hipEventRecord(e0, s));
-    // r = p = b, s = 0 (fused), x_j = 0 (reference), slot 0 = b (basis)
-    if (form == OVL_FORM_BASIS) {
-        int rc = ensure_slots(ctx, w, std::min(w.maxk, ctx->poll) + 1);
+    HIPCHK(lead, hipEventCreate(&e0));
+    HIPCHK(lead, hipEventCreate(&e1));
+    HIPCHK(lead, hipEventRecord(e0, s));
+    // stencil variants: those tuned for the largest job
+    size_t big = 0;
+    for (size_t i = 1; i < B.w.size(); ++i)
+        if (B.ctx[i]->g.V * B.w[i]->nsrc > B.ctx[big]->g.V * B.w[big]->nsrc) big = i;
+    B.variant64 = stencil_variant(B.ctx[big], B.w[big]->nsrc, 0);
+    B.variant32 = mixed ? stencil_variant(B.ctx[big], B.w[big]->nsrc, 1) : 0;
+    // both phases share one stencil grid layout, which depends on the rhs per
+    // lane: the FP32 variant takes the FP64 variant's choice of it
+    if (mixed) B.variant32 = (B.variant32 & ~2) | (B.variant64 & 2);
+    B.form = form;
+    B.maxJ = 0;
+    B.desc.resize(B.w.size());
+    int sb = 0, vb = 0;
+    for (size_t i = 0; i < B.w.size(); ++i) {
+        fill_desc(B.ctx[i], *B.w[i], B.desc[i], B.variant64, sb, vb);
+        B.maxJ = std::max(B.maxJ, B.w[i]->J);
+    }
+    B.sten_total = sb;
+    B.vec_total = vb;
+    const size_t dbytes = (B.desc.size() * sizeof(JobDesc) + 255) & ~(size_t)255;
+    HIPCHK(lead, lead->jobs_dev.ensure(dbytes + 256));
+    B.desc_dev = lead->jobs_dev.as<JobDesc>();
+    B.kdev = reinterpret_cast<int*>(lead->jobs_dev.as<char>() + dbytes);
+    for (size_t i = 0; i < B.w.size(); ++i) {
+        rc = init_job(B.ctx[i], *B.w[i], s);
         if (rc) return rc;
     }
-    if (form == OVL_FORM_BASIS)
-        HIPCHK(ctx, hipMemcpyAsync(slot_ptr<double2>(w, 0), w.b64, vec64,
-                                   hipMemcpyDeviceToDevice, s));
-    else
-        HIPCHK(ctx, hipMemcpyAsync(w.r64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
-    HIPCHK(ctx, hipMemcpyAsync(w.p64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
-    if (form == OVL_FORM_FUSED) HIPCHK(ctx, hipMemsetAsync(w.s64, 0, vec64, s));
-    if (form == OVL_FORM_REFERENCE) HIPCHK(ctx, hipMemsetAsync(w.xj, 0, vec64 * w.J, s));
-    launch_init_state(w.st, w.b64, w.part_e, N, w.sh, s);
-    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(), B.desc.size() * sizeof(JobDesc),
+                                hipMemcpyHostToDevice, s));
+    HIPCHK(lead, hipMemsetAsync(B.kdev, 0, sizeof(int), s));  // outside any captured graph
 
-    bool low = false;  // FP32 phase active
-    int k_switch = -1;
-    int k = 0;
-    bool all_done = false;
-    int status = OVL_OK;
-    double maxres = 1.0;
-    int iters = 0, nact = 0;
-    int nact_known = w.J * w.nsrc;  // active shifts at the last poll (profiling bytes)
-    while (k < w.maxk) {
-        const int chunk = std::min(ctx->poll, w.maxk - k);
-        if (form == OVL_FORM_BASIS) {
-            int rc = ensure_slots(ctx, w, k + chunk + 1);
-            if (rc) return rc;
-        }
-        for (int i = 0; i < chunk; ++i, ++k) {
-            if (!low)
-                enqueue_iteration<double>(ctx, w, k, form, s, w.r64, w.p64, w.q64, w.pj64,
-                                          ctx->U64.as<double2>(), nact_known);
-            else
-                enqueue_iteration<float>(ctx, w, k, form, s, w.r32, w.p32, w.q32, w.pj32,
-                                         ctx->U32.as<float2>(), nact_known);
-        }
-        HIPCHK(ctx, hipGetLastError());
-        HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, w.st, w.state_bytes, hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        prof_collect(ctx);
-        all_done = true;
-        maxres = 0.0;
-        iters = 0;
-        nact = 0;
-        const char* hb = reinterpret_cast<const char*>(ctx->host_state);
-        const int* hcnt = reinterpret_cast<const int*>(hb + state_cnt_off(w.nsrc)) +
-                          (size_t)(k & 1) * w.nsrc * kMaxSlices;
-        const double* hmres = reinterpret_cast<const double*>(hb + state_mres_off(w.nsrc));
-        for (int n = 0; n < w.nsrc; ++n) {
-            const SrcState& S = ctx->host_state[n];
-            if (S.status != OVL_OK && status == OVL_OK) status = S.status;
-            int na = 0;
-            for (int i = 0; i < w.sh.nslices; ++i) {
-                na += hcnt[n * kMaxSlices + i];
-                maxres = std::max(maxres, hmres[n * kMaxSlices + i]);
+    bool low = false;
+    int k_switch = -1, k_host = 0, status = OVL_OK;
+    PollResult P;
+    P.maxres = 1.0;
+    int nact_known = 0;
+    for (size_t i = 0; i < B.w.size(); ++i) nact_known += B.w[i]->J * B.w[i]->nsrc;
+    while (k_host < maxk) {
+        if (form == OVL_FORM_BASIS)
+            for (size_t i = 0; i < B.w.size(); ++i) {
+                rc = ensure_slots(B.ctx[i], *B.w[i], k_host + kChunk + 1, s);
+                if (rc) return rc;
             }
-            all_done = all_done && (na == 0 || S.status != OVL_OK);
-            iters = std::max(iters, S.iter);
-            nact += na;
-        }
-        nact_known = nact;
-        if (status != OVL_OK || all_done) break;
-        if (mixed && !low && maxres < ctx->switch_res && k < w.maxk) {
+        rc = run_chunk(B, low, graphs, s, k_host, nact_known);
+        if (rc) return rc;
+        k_host += kChunk;
+        int prc;
+        P = poll(B, k_host, s, &prc);
+        if (prc) return prc;
+        nact_known = P.nact;
+        if (P.status != OVL_OK) { status = P.status; break; }
+        if (P.all_done) break;
+        if (mixed && !low && P.maxres < lead->switch_res && k_host < maxk) {
             // relaxed precision: from here the remaining corrections are small
             // enough that FP32 vectors perturb the result by ~eps32 * switch_res
             low = true;
-            k_switch = k;
-            launch_convert_64_to_32(w.p64, w.p32, (int64_t)w.nsrc * N, s);
-            if (form == OVL_FORM_BASIS) {
-                launch_convert_64_to_32(slot_ptr<double2>(w, k), w.r32, (int64_t)w.nsrc * N, s);
-                HIPCHK(ctx, hipMemcpyAsync(slot_ptr<float2>(w, k), w.r32,
-                                           (size_t)w.nsrc * N * sizeof(float2),
-                                           hipMemcpyDeviceToDevice, s));
-            } else {
-                launch_convert_64_to_32(w.r64, w.r32, (int64_t)w.nsrc * N, s);
-                launch_convert_64_to_32(w.pj64, w.pj32, (int64_t)w.nsrc * N * w.J, s);
-            }
-            HIPCHK(ctx, hipGetLastError());
+            k_switch = k_host;
+            for (size_t i = 0; i < B.w.size(); ++i) convert_job(B.ctx[i], *B.w[i], k_host, s);
+            HIPCHK(lead, hipGetLastError());
         }
     }
-    w.k_switch = k_switch;
-    w.K = iters;
-    if (status == OVL_OK && !all_done) status = OVL_NOT_CONVERGED;
+    const int k_run = k_host;
+    if (status == OVL_OK && !P.all_done) status = OVL_NOT_CONVERGED;
+    for (size_t i = 0; i < B.w.size(); ++i) {
+        B.w[i]->k_switch = k_switch;
+        B.w[i]->K = 0;
+        for (int n = 0; n < B.w[i]->nsrc; ++n) B.w[i]->K = std::max(B.w[i]->K, B.ctx[i]->host_state[n].iter);
+    }
     if (status == OVL_OK || status == OVL_NOT_CONVERGED) {
-        if (form == OVL_FORM_REFERENCE) {
-            launch_sum_ref(w.xj, w.cj, w.s64, w.J, N, w.nsrc, s);
-        } else if (form == OVL_FORM_BASIS) {
-            launch_basis_coef(w.h_a, w.h_b, w.h_pi, w.cj, w.st, w.W, w.h, w.J, w.maxk, w.nsrc, s);
-            // s = sum_i h_i r_i, chunk by chunk; FP64 slots below k_switch, FP32 from it
-            const int kend = iters + 1;
-            const int ksw = k_switch < 0 ? kend : k_switch;
-            bool acc = false;
-            for (int c0 = 0; c0 < kend; c0 += kSlotChunk) {
-                const int c1 = std::min(kend, c0 + kSlotChunk);
-                char* base = w.chunks[c0 / kSlotChunk];
-                const int a0 = c0, a1 = std::min(c1, ksw);
-                if (a1 > a0) {
-                    ProfScope ps(ctx, 6, (double)N * w.nsrc * (16.0 * (a1 - a0) + 32.0));
-                    launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.maxk, w.st, c0,
-                                              a0 - c0, a1 - c0, w.s64, acc, N, w.nsrc, s);
-                    acc = true;
-                }
-                const int f0 = std::max(c0, ksw), f1 = c1;
-                if (f1 > f0) {
-                    ProfScope ps(ctx, 6, (double)N * w.nsrc * (8.0 * (f1 - f0) + 32.0));
-                    launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.maxk, w.st,
-                                             c0, f0 - c0, f1 - c0, w.s64, acc, N, w.nsrc, s);
-                    acc = true;
+        for (size_t i = 0; i < B.w.size(); ++i) {
+            ovl_ctx* c = B.ctx[i];
+            Work& w = *B.w[i];
+            const int64_t N = w.N;
+            if (form == OVL_FORM_REFERENCE) {
+                launch_sum_ref(w.xj, w.cj, w.s64, w.J, N, w.nsrc, s);
+            } else if (form == OVL_FORM_BASIS || form == OVL_FORM_TWOPASS) {
+                launch_basis_coef(w.h_a, w.h_b, w.h_pi, w.cj, w.st, w.W, w.h, w.J, w.maxk, w.nsrc, s);
+            }
+            if (form == OVL_FORM_BASIS) {
+                // s = sum_i h_i r_i, chunk by chunk; FP64 slots below k_switch, FP32 from it
+                const int kend = w.K + 1;
+                const int ksw = k_switch < 0 ? kend : k_switch;
+                bool acc = false;
+                for (int c0 = 0; c0 < kend; c0 += kSlotChunk) {
+                    const int c1 = std::min(kend, c0 + kSlotChunk);
+                    char* base = w.chunks[c0 / kSlotChunk];
+                    const int a0 = c0, a1 = std::min(c1, ksw);
+                    if (a1 > a0) {
+                        ProfScope ps(lead, s, 6, (double)N * w.nsrc * (16.0 * (a1 - a0) + 32.0));
+                        launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.maxk, w.st, c0,
+                                                  a0 - c0, a1 - c0, w.s64, acc, N, w.nsrc, s);
+                        acc = true;
+                    }
+                    const int f0 = std::max(c0, ksw), f1 = c1;
+                    if (f1 > f0) {
+                        ProfScope ps(lead, s, 6, (double)N * w.nsrc * (8.0 * (f1 - f0) + 32.0));
+                        launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.maxk, w.st,
+                                                 c0, f0 - c0, f1 - c0, w.s64, acc, N, w.nsrc, s);
+                        acc = true;
+                    }
                 }
             }
+            HIPCHK(c, hipGetLastError());
         }
-        HIPCHK(ctx, hipGetLastError());
+        if (form == OVL_FORM_TWOPASS) {
+            // second pass: the same iterations again (bitwise identical, the
+            // reductions being deterministic), now adding h_{k+1} r_{k+1} to s
+            for (size_t i = 0; i < B.w.size(); ++i) {
+                Work& w = *B.w[i];
+                rc = init_job(B.ctx[i], w, s);
+                if (rc) return rc;
+                launch_s_init(w.b64, w.h, w.maxk, w.s64, w.N, w.nsrc, s);
+                B.desc[i].h = w.h;
+            }
+            HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(), B.desc.size() * sizeof(JobDesc),
+                                        hipMemcpyHostToDevice, s));
+            HIPCHK(lead, hipMemsetAsync(B.kdev, 0, sizeof(int), s));
+            bool low2 = false;
+            for (int k2 = 0; k2 < k_run; k2 += kChunk) {
+                if (mixed && !low2 && k2 == k_switch) {
+                    low2 = true;
+                    for (size_t i = 0; i < B.w.size(); ++i) convert_job(B.ctx[i], *B.w[i], k2, s);
+                }
+                rc = run_chunk(B, low2, graphs, s, k2, nact_known);
+                if (rc) return rc;
+            }
+            HIPCHK(lead, hipGetLastError());
+        }
     }
-    HIPCHK(ctx, hipEventRecord(e1, s));
-    HIPCHK(ctx, hipEventSynchronize(e1));
-    prof_collect(ctx);
+    HIPCHK(lead, hipEventRecord(e1, s));
+    HIPCHK(lead, hipEventSynchronize(e1));
+    prof_collect(lead);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    ovl_stats& L = ctx->last;
-    std::memset(&L, 0, sizeof(L));
-    L.iterations = iters;
-    L.fp32_iterations = k_switch < 0 ? 0 : std::max(0, iters - k_switch);
-    L.n_shifts = w.J;
-    L.n_active_end = nact;
-    L.max_est_rel_res = maxres;
-    L.seconds = ms * 1e-3;
-    L.stencil_variant64 = w.var64;
-    L.stencil_variant32 = mixed ? w.var32 : -1;
-    if (status < 0) fail(ctx, status, "solver stopped: %s", ovl_status_string(status));
-    if (status == OVL_NOT_CONVERGED)
-        fail(ctx, status, "maxiter=%d reached with %d shifts above tol (max est. res %.3e)",
-             w.maxk, nact, maxres);
+    // hand the results back to the caller's stream
+    HIPCHK(lead, hipEventRecord(lead->ev_out, s));
+    HIPCHK(lead, hipStreamWaitEvent(lead->stream, lead->ev_out, 0));
+    for (size_t i = 0; i < B.w.size(); ++i) {
+        ovl_ctx* c = B.ctx[i];
+        Work& w = *B.w[i];
+        int na = 0;
+        double mr = 0.0;
+        const char* hb = reinterpret_cast<const char*>(c->host_state);
+        const int* hcnt = reinterpret_cast<const int*>(hb + state_cnt_off(w.nsrc)) +
+                          (size_t)(std::min(k_run, w.maxk) & 1) * w.nsrc * kMaxSlices;
+        const double* hmres = reinterpret_cast<const double*>(hb + state_mres_off(w.nsrc));
+        for (int n = 0; n < w.nsrc; ++n)
+            for (int q = 0; q < w.sh.nslices; ++q) {
+                na += hcnt[n * kMaxSlices + q];
+                mr = std::max(mr, hmres[n * kMaxSlices + q]);
+            }
+        ovl_stats& L = c->last;
+        std::memset(&L, 0, sizeof(L));
+        L.iterations = w.K;
+        L.fp32_iterations = k_switch < 0 ? 0 : std::max(0, w.K - k_switch);
+        L.n_shifts = w.J;
+        L.n_active_end = na;
+        L.max_est_rel_res = mr;
+        L.seconds = ms * 1e-3;
+        L.stencil_variant64 = B.variant64;
+        L.stencil_variant32 = mixed ? B.variant32 : -1;
+        if (status < 0) fail(c, status, "solver stopped: %s", ovl_status_string(status));
+        if (status == OVL_NOT_CONVERGED)
+            fail(c, status, "maxiter=%d reached with %d shifts above tol (max est. res %.3e)",
+                 w.maxk, na, mr);
+    }
     return status;
+}
+
+static int solve(ovl_ctx* ctx, Work& w) {
+    Batch B;
+    B.ctx.push_back(ctx);
+    B.w.push_back(&w);
+    return solve_batch(B);
 }
 
 static int apply_common(ovl_ctx* ctx, const void* in, void* out, int nrhs, ovl_stats* st,
@@ -959,7 +1204,7 @@ static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y) 
     bool acc = false;
     for (int c0 = 0; c0 < K; c0 += kSlotChunk) {
         launch_materialize(w.chunks[c0 / kSlotChunk], w.slot_bytes, c0, kSlotChunk, ksw, w.W, w.J,
-                           j0, jn, K, Y, w.N, acc, ctx->stream);
+                           j0, jn, K, Y, w.N, acc, ctx->stream);  // after solve's handoff
         acc = true;
     }
     if (!acc) HIPCHK(ctx, hipMemsetAsync(Y, 0, (size_t)jn * w.N * sizeof(double2), ctx->stream));
@@ -1057,10 +1302,95 @@ extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind
     return (rc1 == OVL_NOT_CONVERGED || rc2 == OVL_NOT_CONVERGED) ? OVL_NOT_CONVERGED : OVL_OK;
 }
 
-extern "C" int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const void* const*,
-                                      void* const*, const int32_t*, ovl_stats*) {
-    if (!ctxs || nctx < 1 || !ctxs[0]) return OVL_E_ARG;
-    return fail(ctxs[0], OVL_E_STATE, "ovl_apply_sign_batched is not available in this build");
+extern "C" int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const void* const* in,
+                                      void* const* out, const int32_t* nrhs, ovl_stats* st) {
+    if (!ctxs || nctx < 1 || nctx > kMaxJobs || !ctxs[0] || !in || !out || !nrhs) return OVL_E_ARG;
+    ovl_ctx* lead = ctxs[0];
+    DeviceGuard dg(lead->device);
+    for (int i = 0; i < nctx; ++i) {
+        if (!ctxs[i]) return fail(lead, OVL_E_ARG, "context %d is NULL", i);
+        if (ctxs[i]->device != lead->device)
+            return fail(lead, OVL_E_ARG, "context %d is on device %d, not %d", i, ctxs[i]->device,
+                        lead->device);
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == ctxs[i]) return fail(lead, OVL_E_ARG, "context %d appears twice", i);
+    }
+    if (lead->z.empty()) return fail(lead, OVL_E_STATE, "ovl_set_contour / ovl_set_nodes was not called");
+    // every job takes the lead's nodes and solver settings for this call
+    struct Saved {
+        std::vector<double2> z, c;
+        int precision, form, maxiter;
+        double tol, switch_res;
+        double2 zseed;
+    };
+    std::vector<Saved> saved(nctx);
+    for (int i = 0; i < nctx; ++i) {
+        ovl_ctx* c = ctxs[i];
+        saved[i] = {c->z, c->c, c->precision, c->form, c->maxiter, c->tol, c->switch_res, c->zseed};
+        c->z = lead->z;
+        c->c = lead->c;
+        c->precision = lead->precision;
+        c->form = lead->form;
+        c->maxiter = lead->maxiter;
+        c->tol = lead->tol;
+        c->switch_res = lead->switch_res;
+        c->zseed = lead->zseed;
+    }
+    auto restore = [&]() {
+        for (int i = 0; i < nctx; ++i) {
+            ovl_ctx* c = ctxs[i];
+            c->z = saved[i].z;
+            c->c = saved[i].c;
+            c->precision = saved[i].precision;
+            c->form = saved[i].form;
+            c->maxiter = saved[i].maxiter;
+            c->tol = saved[i].tol;
+            c->switch_res = saved[i].switch_res;
+            c->zseed = saved[i].zseed;
+        }
+    };
+    std::vector<Work> works(nctx);
+    Batch B;
+    int rc = OVL_OK;
+    for (int i = 0; i < nctx && rc == OVL_OK; ++i) {
+        rc = check_apply_args(ctxs[i], in[i], out[i], nrhs[i], true);
+        if (rc == OVL_OK) rc = prepare(ctxs[i], nrhs[i], works[i]);
+        if (rc != OVL_OK && ctxs[i] != lead) {
+            fail(lead, rc, "context %d: %s", i, ctxs[i]->err);
+        }
+        B.ctx.push_back(ctxs[i]);
+        B.w.push_back(&works[i]);
+    }
+    if (rc != OVL_OK) { restore(); return rc; }
+    for (int i = 0; i < nctx; ++i)
+        launch_pack_spinor64(static_cast<const double2*>(in[i]), works[i].b64, ctxs[i]->g.V, nrhs[i],
+                             lead->stream);
+    if (hipGetLastError() != hipSuccess) { restore(); return fail(lead, OVL_E_HIP, "pack failed"); }
+    rc = solve_batch(B);
+    if (rc >= 0) {
+        for (int i = 0; i < nctx; ++i)
+            launch_unpack_spinor64(works[i].s64, static_cast<double2*>(out[i]), ctxs[i]->g.V, nrhs[i],
+                                   lead->stream);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(lead->stream) != hipSuccess)
+            rc = fail(lead, OVL_E_HIP, "unpack failed");
+    }
+    restore();
+    if (st) {
+        ovl_stats a{};
+        a.stencil_variant64 = lead->last.stencil_variant64;
+        a.stencil_variant32 = lead->last.stencil_variant32;
+        a.seconds = lead->last.seconds;
+        for (int i = 0; i < nctx; ++i) {
+            const ovl_stats& L = ctxs[i]->last;
+            a.iterations = std::max(a.iterations, L.iterations);
+            a.fp32_iterations = std::max(a.fp32_iterations, L.fp32_iterations);
+            a.n_shifts = L.n_shifts;
+            a.n_active_end += L.n_active_end;
+            a.max_est_rel_res = std::max(a.max_est_rel_res, L.max_est_rel_res);
+        }
+        *st = a;
+    }
+    return rc;
 }
 
 // ============================================================================

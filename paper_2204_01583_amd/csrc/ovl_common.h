@@ -108,4 +108,49 @@ struct ShiftDev {
     int maxk;
 };
 
+// One job of a (possibly batched) shifted solve: one lattice with its links,
+// nsrc right-hand sides and its own solver buffers.  The iteration kernels
+// take a device array of these and find their job from the block index, so
+// one launch advances every job of a batch by one stage.
+constexpr int kMaxJobs = 64;
+constexpr int kSlotChunk = 32;  // basis form: residual slots per allocation
+struct JobDesc {
+    Geom g;
+    double kappa;
+    double2 zs;                 // seed shift
+    const void* U[2];           // links, [0] FP64 [1] FP32 (internal layout)
+    int nsrc;
+    int nsb;                    // site blocks of the stencil
+    int sten_b0, sten_nb;       // this job's blocks in the stencil grid
+    int vec_b0, nbe;            // this job's first block in the vector grid; blocks per source
+    SrcState* st;
+    ShiftDev sh;
+    double2* part_w;            // [nsrc][nsb]
+    double* part_e;             // [nsrc][nbe]
+    // working vectors [nsrc][12V], index [0] FP64, [1] FP32
+    void* p[2];
+    void* q[2];
+    void* r[2];                 // fused/reference: r in place; two-pass: r_k at r[..] + (k&1) * rpp
+    size_t rpp;                 // two-pass: element offset of the second r buffer
+    double2* b64;               // packed source
+    double2* s64;               // quadrature sum
+    void* pj[2];                // sweep forms: [nsrc][J][12V]
+    double2* xj;                // reference form
+    char* const* slots;         // basis form: device table of slot-chunk bases
+    size_t slot_bytes;          // bytes of one slot (nsrc * 12V FP64 complex)
+    const double2* h;           // two-pass, second pass: h[src][i] weights of r_i
+    int ksw;                    // first FP32 iteration (slots from it hold FP32), or large
+    int form;                   // OVL_FORM_* of this solve
+};
+
+// r_k and r_{k+1} of a job (element pointers of source 0; sources are 12V apart)
+template <typename T>
+__device__ __forceinline__ T* job_rk(const JobDesc& J, int k, int fp32) {
+    if (J.form == 2) {  // basis: slot k (FP32 slots packed at the slot base)
+        return reinterpret_cast<T*>(J.slots[k / kSlotChunk] + (size_t)(k % kSlotChunk) * J.slot_bytes);
+    }
+    T* r = static_cast<T*>(J.r[fp32]);
+    return J.form == 3 ? r + (size_t)(k & 1) * J.rpp : r;
+}
+
 }  // namespace ovl

@@ -140,21 +140,22 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 }
 
 
+// Body of the stencil for one block, `tile` being the block's position in
+// the (site tile, rhs group) space after the XCD-aware remap.
 template <typename R, int MODE, int HPI, int RPT, int ORD>
-__global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
-                                                   C2<R>* __restrict__ out,
-                                                   const C2<R>* __restrict__ U, Geom g, R kappa,
-                                                   double zsr, double zsi,
-                                                   const C2<R>* __restrict__ rdot,
-                                                   double2* __restrict__ partial,
-                                                   const SrcState* __restrict__ stt,
-                                                   ShiftDev sh, int k, int nsb, int nrhs) {
+__device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>* __restrict__ out,
+                                             const C2<R>* __restrict__ U, const Geom& g, R kappa,
+                                             double zsr, double zsi,
+                                             const C2<R>* __restrict__ rdot,
+                                             double2* __restrict__ partial,
+                                             const SrcState* __restrict__ stt,
+                                             const ShiftDev& sh, int k, int nsb, int nrhs,
+                                             unsigned tile) {
     // ORD 0: rhs groups fastest, so the blocks of one site tile (all rhs) run
     // back to back on one XCD and share its links through L2 (few rhs).
     // ORD 1: site tiles fastest within an rhs group, so a tile's z and t
     // neighbours were fetched moments earlier by the same XCD (many rhs).
     const int ngrp = (nrhs + RPT - 1) / RPT;
-    const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
     const int n0 = (int)uniform(ORD == 0 ? tile % (unsigned)ngrp : tile / (unsigned)nsb) * RPT;
     const int sb = (int)uniform(ORD == 0 ? tile / (unsigned)ngrp : tile % (unsigned)nsb);
     bool on[RPT];
@@ -232,7 +233,62 @@ __global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
     }
 }
 
+template <typename R, int MODE, int HPI, int RPT, int ORD>
+__global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
+                                                   C2<R>* __restrict__ out,
+                                                   const C2<R>* __restrict__ U, Geom g, R kappa,
+                                                   double zsr, double zsi,
+                                                   const C2<R>* __restrict__ rdot,
+                                                   double2* __restrict__ partial,
+                                                   const SrcState* __restrict__ stt,
+                                                   ShiftDev sh, int k, int nsb, int nrhs) {
+    const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
+    wilson_block<R, MODE, HPI, RPT, ORD>(in, out, U, g, kappa, zsr, zsi, rdot, partial, stt, sh,
+                                         k, nsb, nrhs, tile);
+}
+
+// K1 over a job table: q = z_s p - H p and <r_k, q> partials for every job of
+// a batch in one launch; the iteration index k is read from device memory so
+// a captured graph can be replayed for any k.
+template <typename R, int HPI, int RPT, int ORD>
+__global__ __launch_bounds__(kBlock) void k_wilson_jobs(const JobDesc* __restrict__ jobs, int njobs,
+                                                        const int* __restrict__ kdev) {
+    const int k = (int)uniform((uint32_t)*kdev);
+    const unsigned gb = uniform(xcd_remap(blockIdx.x, gridDim.x));
+    int j = 0;
+    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0) ++j;
+    const JobDesc& J = jobs[j];
+    const int f = sizeof(R) == 4 ? 1 : 0;
+    wilson_block<R, 1, HPI, RPT, ORD>(static_cast<const C2<R>*>(J.p[f]), static_cast<C2<R>*>(J.q[f]),
+                                      static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
+                                      J.zs.y, job_rk<const C2<R>>(J, k, f), J.part_w, J.st, J.sh,
+                                      k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0);
+}
+
 int wilson_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
+int wilson_grid_blocks(const Geom& g, int nrhs, int variant) {
+    const int rpt = (variant & 2) ? 2 : 1;
+    return wilson_blocks(g) * ((nrhs + rpt - 1) / rpt);
+}
+
+template <typename R>
+void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
+                        int variant, hipStream_t s) {
+#define OVL_WJ(H, P, O) hipLaunchKernelGGL((k_wilson_jobs<R, H, P, O>), dim3(total_blocks), dim3(kBlock), 0, s, jobs, njobs, kdev)
+    switch (variant) {
+        case 1: OVL_WJ(2, 1, 0); break;
+        case 2: OVL_WJ(1, 2, 0); break;
+        case 3: OVL_WJ(2, 2, 0); break;
+        case 4: OVL_WJ(1, 1, 1); break;
+        case 5: OVL_WJ(2, 1, 1); break;
+        case 6: OVL_WJ(1, 2, 1); break;
+        case 7: OVL_WJ(2, 2, 1); break;
+        default: OVL_WJ(1, 1, 0); break;
+    }
+#undef OVL_WJ
+}
+template void launch_wilson_jobs<double>(const JobDesc*, int, const int*, int, int, hipStream_t);
+template void launch_wilson_jobs<float>(const JobDesc*, int, const int*, int, int, hipStream_t);
 
 template <typename R, int HPI, int RPT, int ORD>
 void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,

@@ -20,6 +20,8 @@ OK, NOT_CONVERGED = 0, 1
 E_ARG, E_STATE, E_HIP, E_OOM, E_NONFINITE, E_BREAKDOWN = -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_MIXED = 0, 1
 FORM_REFERENCE, FORM_FUSED, FORM_BASIS, FORM_TWOPASS = 0, 1, 2, 3
+FORMS = {"reference": FORM_REFERENCE, "fused": FORM_FUSED, "basis": FORM_BASIS,
+         "twopass": FORM_TWOPASS}
 BENCH_STENCIL64, BENCH_STENCIL32 = 0, 1
 
 # every function declared in include/ovl.h
@@ -274,6 +276,29 @@ class Context:
         st = Stats()
         self._rc(self.lib.ovl_get_stats(self._h, ctypes.byref(st)), "ovl_get_stats")
         return st
+
+
+def apply_sign_batched(contexts, inputs, allow_not_converged=False):
+    """One batched solve over several contexts (lattices may differ):
+    outputs[i] = sum_j c_j (z_j - H_W[context i])^-1 inputs[i].  The nodes and
+    solver settings of contexts[0] are used for all.  Returns (outputs, Stats)."""
+    lib = load()
+    n = len(contexts)
+    ins = [c._spinor_in(x) for c, x in zip(contexts, inputs)]
+    outs = [torch.empty_like(x) for x in ins]
+    for c in contexts:
+        c._sync_stream()
+    P = ctypes.c_void_p
+    h = (P * n)(*[c._h for c in contexts])
+    pin = (P * n)(*[P(x.data_ptr()) for x in ins])
+    pout = (P * n)(*[P(x.data_ptr()) for x in outs])
+    nr = (ctypes.c_int32 * n)(*[x.shape[0] for x in ins])
+    st = Stats()
+    rc = lib.ovl_apply_sign_batched(h, n, pin, pout, nr, ctypes.byref(st))
+    if rc < 0 or (rc == NOT_CONVERGED and not allow_not_converged):
+        raise OvlError(rc, f"ovl_apply_sign_batched: {status_string(rc)}: "
+                           f"{lib.ovl_last_error(contexts[0]._h).decode()}")
+    return outs, st
 
 
 class OverlapAction(torch.autograd.Function):

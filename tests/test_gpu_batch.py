@@ -1,0 +1,99 @@
+"""Batched solves over uneven lattices (one job-table launch per stage,
+graph-captured chunks), the two-pass form, and graph replay against eager
+launches."""
+import os
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from tests.gpu_util import CIRCLE, gauge, make_ctx, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+REF8 = os.path.join(os.path.dirname(__file__), "golden",
+                    "sign_8x8x8x8_r0.3_m1.4_nq64_circle_src1000.npy")
+
+
+def setup_module(module):
+    from paper_2204_01583_amd import ovl
+    ovl.load()
+
+
+@pytest.mark.parametrize("precision,form", [(0, 1), (0, 0), (1, 2), (1, 3)])
+def test_graph_replay_equals_eager(precision, form, monkeypatch):
+    """Every solve replays its captured 16-iteration graph many times; the
+    result must equal the eagerly launched solve bit for bit (same kernels,
+    deterministic reductions), on two applies in a row."""
+    dims = (4, 4, 4, 6)
+    U = gauge(dims, 0.3, 3)
+    b = to_dev(si.gaussian_sources(dims, 2, first_seed=21))
+    ctx = make_ctx(dims, U, nq=16, precision=precision, form=form)
+    g1, st = ctx.apply_sign(b)
+    g2, _ = ctx.apply_sign(b)
+    monkeypatch.setenv("OVL_GRAPHS", "0")
+    e1, _ = ctx.apply_sign(b)
+    print(f"prec {precision} form {form}: iterations {st.iterations}")
+    assert st.iterations > 32            # several chunk replays
+    assert bool((g1 == e1).all()) and bool((g2 == e1).all())
+    ctx.close()
+
+
+def test_twopass_equals_basis():
+    dims = (8, 8, 8, 8)
+    U = gauge(dims, 0.3, 0)
+    b = to_dev(si.gaussian_sources(dims, 2, first_seed=1000))
+    ctx = make_ctx(dims, U, 1.4, 0.05, 64, precision=1, form=2)
+    s_basis, st1 = ctx.apply_sign(b)
+    ctx.set_solver(1, 3, tol=1e-12, maxiter=3000)
+    s_two, st2 = ctx.apply_sign(b)
+    err = relerr(s_two.cpu().numpy(), s_basis.cpu().numpy())
+    print(f"two-pass vs basis (mixed): {err:.2e}, iterations {st1.iterations} {st2.iterations}")
+    assert st1.iterations == st2.iterations
+    assert err < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,form", [(1, 3), (0, 2)])
+def test_batched_uneven_lattices(precision, form):
+    """A batch of fields of different sizes and roughness, several sources
+    each, in one solve: every job equals its own unbatched solve, and the
+    job carrying the stored 8^4 workload matches the oracle."""
+    from paper_2204_01583_amd import ovl
+    specs = [((8, 8, 8, 8), 0.3, 0), ((4, 4, 6, 6), 0.2, 1), ((6, 6, 6, 8), 0.4, 2),
+             ((4, 4, 4, 4), 0.3, 3)]
+    nq = 64
+    ctxs, ins = [], []
+    for dims, r, seed in specs:
+        c = make_ctx(dims, gauge(dims, r, seed), 1.4, 0.05, nq, precision=precision, form=form)
+        ctxs.append(c)
+        ins.append(to_dev(si.gaussian_sources(dims, 3, first_seed=1000)))
+    outs, st = ovl.apply_sign_batched(ctxs, ins)
+    print(f"batched: iterations {st.iterations}, fp32 {st.fp32_iterations}")
+    tol = 1e-10 if precision else 1e-11
+    ref8 = np.load(REF8)
+    assert relerr(outs[0][0].cpu().numpy(), ref8) < tol
+    # FP64: the same kernels and reductions, so the jobs agree to rounding;
+    # mixed: the FP32 switch point is common to the batch (set by its slowest
+    # job), so a job may switch later than alone: both are within 1e-10.
+    same = 1e-12 if precision == 0 else 1e-10
+    for c, x, o in zip(ctxs, ins, outs):
+        single, _ = c.apply_sign(x)
+        err = relerr(o.cpu().numpy(), single.cpu().numpy())
+        print(f"  {c.dims}: batched vs single {err:.2e}")
+        assert err < same
+    for c in ctxs:
+        c.close()
+
+
+def test_batched_rejects_bad_arguments():
+    from paper_2204_01583_amd import ovl
+    dims = (4, 4, 4, 4)
+    c = make_ctx(dims, gauge(dims, 0.3, 0), nq=8)
+    x = to_dev(si.gaussian_sources(dims, 1))
+    with pytest.raises(ovl.OvlError):
+        ovl.apply_sign_batched([c, c], [x, x])          # the same context twice
+    d = ovl.Context(dims)                                # no gauge field
+    with pytest.raises(ovl.OvlError):
+        ovl.apply_sign_batched([c, d], [x, x])
+    c.close()
+    d.close()

@@ -69,7 +69,7 @@ def test_hw_free_plane_wave_16():
 CFG0 = dict(dims=(4, 4, 4, 4), r=0.3, seed=0, m0=1.4, mq=0.1, nq=32)
 
 
-@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
 def test_sign_4x4_fp64_all_forms(form):
     c = CFG0
     U = gauge(c["dims"], c["r"], c["seed"])
@@ -84,7 +84,7 @@ def test_sign_4x4_fp64_all_forms(form):
     ctx.close()
 
 
-@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("form", [1, 2, 3])
 def test_sign_4x4_mixed(form):
     c = CFG0
     U = gauge(c["dims"], c["r"], c["seed"])
@@ -117,7 +117,8 @@ REF8 = os.path.join(os.path.dirname(__file__), "golden",
                     "sign_8x8x8x8_r0.3_m1.4_nq64_circle_src1000.npy")
 
 
-@pytest.mark.parametrize("precision,form,tol", [(0, 1, 1e-11), (0, 2, 1e-11), (1, 2, 1e-10)])
+@pytest.mark.parametrize("precision,form,tol", [(0, 1, 1e-11), (0, 2, 1e-11), (1, 2, 1e-10),
+                                                (0, 3, 1e-11), (1, 3, 1e-10)])
 def test_sign_8x8(precision, form, tol):
     """8^4, 2 x 64 nodes, against the stored oracle result (make_oracle_refs.py)."""
     dims, nq = (8, 8, 8, 8), 64
