@@ -181,9 +181,10 @@ int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
  * the context's stream; ovl_get_profile returns the summed duration, the
  * number of launches and the summed algorithmic bytes since the last
  * ovl_set_profiling(ctx, 1).  kclass:
- *   0 stencil FP64 (q = z_s p - H p with <r,q>)   1 the same in FP32
- *   2 vector updates FP64 (r and p updates)        3 the same in FP32
- *   4 shift sweep FP64                             5 shift sweep FP32
+ *   0 stencil FP64 (q = z_s p - H p with <r,q>,   1 the same in FP32
+ *     ||q||^2 and ||r||^2)
+ *   2 r and p update FP64 (one kernel)             3 the same in FP32
+ *   4 r update with the shift sweep FP64           5 the same in FP32
  *   6 basis sum s = sum h_k r_k                    7 scalar kernels
  * Algorithmic bytes count every array element the kernel must read or write
  * once (links once per launch, neighbour spinors once). */

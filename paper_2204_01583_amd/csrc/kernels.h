@@ -20,7 +20,7 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 
 // ---- Wilson stencil --------------------------------------------------------
 // out = H_W in                                               (mode 0)
-// out = zs*in - H_W in, partial[src][blk] = <r,out> (mode 1); sources that are
+// out = zs*in - H_W in, partial[src][blk] = (<r,out>, ||out||^2, ||r||^2) (mode 1); sources that are
 // not live at iteration k (see kernels.hip) are skipped.
 // variant v = 4*order + 2*(rhs per lane - 1) + (hops per loop step - 1):
 // hops per step 1 or 2 (both directions of one mu), 1 or 2 rhs per lane
@@ -28,7 +28,7 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 constexpr int kStencilVariants = 8;
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
-                   double kappa, double2 zs, const C2<R>* r, double2* partial,
+                   double kappa, double2 zs, const C2<R>* r, double4* partial,
                    const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s,
                    int variant = 0);
 int wilson_blocks(const Geom& g);
@@ -40,10 +40,10 @@ int wilson_grid_blocks(const Geom& g, int nrhs, int variant);
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
                         int variant, hipStream_t s);
-// K2 (alpha, pi^j, r update) and K3 (beta, shift bookkeeping, p update or sweep)
+// K2: seed and shift scalars, shift bookkeeping, r update and p update or sweep
 template <typename R>
-void launch_iteration_k23(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
-                          int form, int maxJ, hipStream_t s);
+void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
+                             int form, int maxJ, hipStream_t s);
 void launch_advance(int* kdev, hipStream_t s);
 // two-pass form, second pass: s = h_0 b
 void launch_s_init(const double2* b, const double2* h, int maxk, double2* s, int64_t n12, int nsrc,

@@ -123,13 +123,13 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 }
 
 // ============================================================================
-// The seed iteration k is three kernels:
-//   K1  q = z_s p - H p and per-block <r, q>                (k_wilson, mode 1)
-//   K2  alpha_k (every block, from K1's partials), shifted pi_{k+1}, alpha^j
-//       (blocks 0..nslices-1, one lane per shift), r <- r - alpha q, ||r||^2
-//   K3  beta_k (every block, from K2's partials), shifted beta^j, residual
-//       estimates and deactivation (blocks 0..nslices-1), then p <- r + beta p
-//       or the shift sweep.
+// The seed iteration k is two kernels:
+//   K1  q = z_s p - H p with per-block <r_k, q>, ||q||^2, ||r_k||^2
+//       (k_wilson, mode 1)
+//   K2  alpha_k, beta_k (every block, from K1's partials), shifted pi_{k+1},
+//       alpha^j, beta^j, residual estimates and deactivation (blocks
+//       0..nslices-1 own one 256-shift slice each, one lane per shift), then
+//       r <- r - alpha q together with p <- r + beta p or the shift sweep.
 // Quantities written in iteration k live in parity (k&1) or mod-3 buffers, so
 // no block reads what another block of the same kernel writes:
 //   SrcState.rr[k&1] = ||r_k||^2, alpha[k&1], beta[k&1];
@@ -147,18 +147,6 @@ __device__ __forceinline__ double sum_partials_re<double>(const double* p, int n
     for (int b = threadIdx.x; b < nb; b += kBlock) v += p[b];
     return block_sum<kBlock>(v, sh);
 }
-__device__ __forceinline__ double2 sum_partials_c(const double2* p, int nb, double* sh) {
-    double re = 0.0, im = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) {
-        const double2 v = p[b];
-        re += v.x;
-        im += v.y;
-    }
-    re = block_sum<kBlock>(re, sh);
-    im = block_sum<kBlock>(im, sh);
-    return make_double2(re, im);
-}
-
 int vec_blocks(int64_t n12, int nslices) {
     int nb = (int)((n12 + 4 * kBlock - 1) / (4 * kBlock));
     if (nb > 512) nb = 512;
@@ -166,7 +154,7 @@ int vec_blocks(int64_t n12, int nslices) {
     return nb;
 }
 
-// Decode a vector-grid block: job, source n and block bx of nbx for it.
+// Decode a vector-grid block: job, source n and block bx of nbe for it.
 struct VecBlock {
     int j, n, bx;
 };
@@ -178,158 +166,113 @@ __device__ __forceinline__ VecBlock vec_block(const JobDesc* jobs, int njobs) {
     return VecBlock{j, local / jobs[j].nbe, local % jobs[j].nbe};
 }
 
-// K2 body: alpha, shifted pi / alpha^j, r update and ||r_{k+1}||^2 partials.
-// Two-pass form, second pass (J.h != null): s += h_{k+1} r_{k+1} as well.
-template <typename R>
-__device__ __forceinline__ void update_r_block(const JobDesc& J, int n, int bx, int k) {
+// Seed scalars of iteration k from the stencil's per-block partials:
+//   alpha_k = ||r_k||^2 / <r_k, q_k>,   q_k = A_s p_k,
+//   ||r_{k+1}||^2 = ||r_k - alpha q||^2 = |alpha|^2 ||q||^2 - ||r_k||^2
+//     (alpha <r,q> = ||r||^2 is real), clamped at 0,
+//   beta_k = (alpha / conj(alpha)) ||r_{k+1}||^2 / ||r_k||^2.
+// The next stencil pass measures ||r_{k+1}||^2 from the vector itself, so
+// alpha_{k+1} is always taken from the true residual.
+struct SeedScalars {
+    double2 alpha, beta;
+    double rr, rrn;
+    int status;
+};
+__device__ __forceinline__ SeedScalars seed_scalars(const JobDesc& J, int n, double* shm) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    const double4* pw = J.part_w + (size_t)n * J.nsb;
+    for (int b = threadIdx.x; b < J.nsb; b += kBlock) {
+        const double4 v = pw[b];
+        a0 += v.x;
+        a1 += v.y;
+        a2 += v.z;
+        a3 += v.w;
+    }
+    a0 = block_sum<kBlock>(a0, shm);
+    a1 = block_sum<kBlock>(a1, shm);
+    a2 = block_sum<kBlock>(a2, shm);
+    a3 = block_sum<kBlock>(a3, shm);
+    SeedScalars r;
+    const double2 rq = make_double2(a0, a1);
+    r.rr = a3;
+    r.status = 0;
+    if (!finite2(rq) || !isfinite(a2) || !isfinite(a3)) r.status = OVL_E_NONFINITE;
+    else if (cabs2(rq) <= 1e-300 * a3) r.status = OVL_E_BREAKDOWN;
+    if (r.status) {
+        r.alpha = r.beta = make_double2(0, 0);
+        r.rrn = 0;
+        return r;
+    }
+    r.alpha = cdiv(make_double2(a3, 0.0), rq);
+    r.rrn = fmax(cabs2(r.alpha) * a2 - a3, 0.0);
+    const double2 ph = cdiv(r.alpha, make_double2(r.alpha.x, -r.alpha.y));
+    const double ratio = r.rrn / a3;
+    r.beta = make_double2(ph.x * ratio, ph.y * ratio);
+    return r;
+}
+
+// Per-shift scalars of iteration k for shift j (active at the start of k):
+//   pi_{k+1} = (1 + alpha Dz_j) pi_k + (alpha beta_{k-1}/alpha_{k-1}) (pi_k - pi_{k-1})
+//   alpha^j = alpha pi_k / pi_{k+1},  beta^j = (pi_k / pi_{k+1})^2 beta,
+//   shifted residual estimate ||r_{k+1}|| / |pi_{k+1}| / ||b||.
+struct ShiftScalars {
+    double2 pn, aj, bj, ipi;
+    double res;
+};
+__device__ __forceinline__ ShiftScalars shift_scalars(const ShiftDev& sh, size_t o, int j, int k,
+                                                      const SeedScalars& sc, double2 c1, double bb) {
+    const size_t stride3 = (size_t)sh.nsrc * sh.J;
+    const double2 p = sh.pi[(size_t)(k % 3) * stride3 + o];
+    const double2 pp = sh.pi[(size_t)((k + 2) % 3) * stride3 + o];
+    const double2 dz = sh.dz[j];
+    const double2 al = sc.alpha;
+    const double2 one_ad = make_double2(1.0 + (al.x * dz.x - al.y * dz.y), al.x * dz.y + al.y * dz.x);
+    ShiftScalars t;
+    t.pn = cadd(cmul(one_ad, p), cmul(c1, csub(p, pp)));
+    const double2 rt = cdiv(p, t.pn);
+    t.aj = cmul(al, rt);
+    t.bj = cmul(cmul(rt, rt), sc.beta);
+    t.ipi = cdiv(make_double2(1.0, 0.0), t.pn);
+    t.res = sqrt(sc.rrn / cabs2(t.pn) / bb);
+    return t;
+}
+
+// The seed iteration's second kernel (after the stencil), for every form:
+// scalars, shift bookkeeping (the 256-shift slice of block bx), then one pass
+// over the components: r_{k+1} = r_k - alpha q and either p = r_{k+1} + beta p
+// (basis forms; two-pass second pass also s += h_{k+1} r_{k+1}) or the shift
+// sweep (fused: s += c_j alpha^j p_j; reference: x_j += alpha^j p_j; then
+// p_j = r_{k+1}/pi_{k+1} + beta^j p_j and p = r_{k+1} + beta p).  In the
+// first iteration p_j = b for every j, read from b instead.
+template <typename R, int KIND>  // KIND 0 basis / two-pass, 1 fused sweep, 2 reference sweep
+__device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, int k) {
+    constexpr bool SWEEP = KIND != 0;
     const int f = sizeof(R) == 4 ? 1 : 0;
     const ShiftDev& sh = J.sh;
     SrcState& S = J.st[n];
-    if (!src_live(S, sh, n, k)) return;
-    const int nbx = J.nbe, nsb = J.nsb;
-    const int64_t n12 = 12 * J.g.V;
     __shared__ double shm[kBlock / 64];
-    const double2 rq = sum_partials_c(J.part_w + (size_t)n * nsb, nsb, shm);
-    const double rr = S.rr[k & 1];
-    const bool bad = !finite2(rq);
-    const bool brk = !bad && cabs2(rq) <= 1e-300 * rr;
-    if (bad || brk) {
-        if (bx == 0 && threadIdx.x == 0) S.status = bad ? OVL_E_NONFINITE : OVL_E_BREAKDOWN;
-        return;
-    }
-    const double2 alpha = cdiv(make_double2(rr, 0.0), rq);
-    if (bx == 0 && threadIdx.x == 0) S.alpha[k & 1] = alpha;
-    if (bx < sh.nslices) {
-        // pi_{k+1} = (1 + alpha Dz) pi_k + (alpha beta_{k-1} / alpha_{k-1}) (pi_k - pi_{k-1})
-        const int j = bx * kBlock + threadIdx.x;
-        const size_t o = (size_t)n * sh.J + j;
-        const size_t stride3 = (size_t)sh.nsrc * sh.J;
-        if (j < sh.J && sh.active[(size_t)(k & 1) * stride3 + o]) {
-            const double2 c1 = cdiv(cmul(alpha, S.beta[(k + 1) & 1]), S.alpha[(k + 1) & 1]);
-            const double2 p = sh.pi[(size_t)(k % 3) * stride3 + o];
-            const double2 pp = sh.pi[(size_t)((k + 2) % 3) * stride3 + o];
-            const double2 dz = sh.dz[j];
-            const double2 one_ad = make_double2(1.0 + (alpha.x * dz.x - alpha.y * dz.y),
-                                                alpha.x * dz.y + alpha.y * dz.x);
-            const double2 pn = cadd(cmul(one_ad, p), cmul(c1, csub(p, pp)));
-            sh.pi[(size_t)((k + 1) % 3) * stride3 + o] = pn;
-            sh.aj[o] = cdiv(cmul(alpha, p), pn);
-        }
-    }
-    const R ar = (R)alpha.x, ai = (R)alpha.y;
-    const C2<R>* ri = job_rk<const C2<R>>(J, k, f) + (size_t)n * n12;
-    C2<R>* ro = job_rk<C2<R>>(J, k + 1, f) + (size_t)n * n12;
-    const C2<R>* qq = static_cast<const C2<R>*>(J.q[f]) + (size_t)n * n12;
-    const bool acc2 = J.h != nullptr;
-    const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
-    double2* sacc = J.s64 + (size_t)n * n12;
-    double acc = 0.0;
-    for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)nbx * kBlock) {
-        const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e);
-        const cx<R> rn = mk<R>(r.re - (ar * qv.re - ai * qv.im), r.im - (ar * qv.im + ai * qv.re));
-        stc<R>(ro, e, rn);
-        acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
-        if (acc2) {
-            double2 sv = sacc[e];
-            sv.x += hk.x * (double)rn.re - hk.y * (double)rn.im;
-            sv.y += hk.x * (double)rn.im + hk.y * (double)rn.re;
-            sacc[e] = sv;
-        }
-    }
-    const double t = block_sum<kBlock>(acc, shm);
-    if (threadIdx.x == 0) J.part_e[(size_t)n * nbx + bx] = t;
-}
-
-// K3 scalar part, shared by the p update and the sweeps.  Returns false if
-// the source is not live (then the shift slices publish zero counts).
-// On return beta = beta_k.
-__device__ __forceinline__ bool k3_scalars(const JobDesc& J, int n, int bx, int k, double2& beta,
-                                           double* shm) {
-    const ShiftDev& sh = J.sh;
-    SrcState& S = J.st[n];
-    const size_t stride3 = (size_t)sh.nsrc * sh.J;
     int* cnt_next = sh.cnt + ((size_t)((k + 1) & 1) * sh.nsrc + n) * kMaxSlices;
     if (!src_live(S, sh, n, k)) {
         // a finished source stays finished; at the iteration limit the counts
         // of the last iteration are kept, so the host sees what is still active
         if (k < sh.maxk && bx < sh.nslices && threadIdx.x == 0) cnt_next[bx] = 0;
-        return false;
+        return;
     }
-    const double rrn = sum_partials_re<double>(J.part_e + (size_t)n * J.nbe, J.nbe, shm);
-    const double2 al = S.alpha[k & 1];
-    const double2 ph = cdiv(al, make_double2(al.x, -al.y));  // alpha / conj(alpha)
-    const double ratio = rrn / S.rr[k & 1];
-    beta = make_double2(ph.x * ratio, ph.y * ratio);
+    const SeedScalars sc = seed_scalars(J, n, shm);
+    if (sc.status) {
+        if (bx == 0 && threadIdx.x == 0) S.status = sc.status;
+        if (bx < sh.nslices && threadIdx.x == 0) cnt_next[bx] = 0;
+        return;
+    }
     if (bx == 0 && threadIdx.x == 0) {
-        S.beta[k & 1] = beta;
-        S.rr[(k + 1) & 1] = rrn;
+        S.alpha[k & 1] = sc.alpha;
+        S.beta[k & 1] = sc.beta;
+        S.rr[k & 1] = sc.rr;
         S.iter = k + 1;
-        if (!isfinite(rrn)) S.status = OVL_E_NONFINITE;
     }
-    if (bx < sh.nslices) {
-        const int j = bx * kBlock + threadIdx.x;
-        const size_t o = (size_t)n * sh.J + j;
-        int stay = 0;
-        double res = 0.0;
-        if (j < sh.J) {
-            const bool act = sh.active[(size_t)(k & 1) * stride3 + o] != 0;
-            double2 bj = make_double2(0, 0);
-            if (act) {
-                const double2 pn = sh.pi[(size_t)((k + 1) % 3) * stride3 + o];
-                const double2 p = sh.pi[(size_t)(k % 3) * stride3 + o];
-                const double2 rt = cdiv(p, pn);
-                bj = cmul(cmul(rt, rt), beta);
-                res = sqrt(rrn / cabs2(pn) / S.bb);
-                stay = (res > sh.tol && isfinite(res)) ? 1 : 0;
-                sh.res[o] = res;
-            }
-            sh.active[(size_t)((k + 1) & 1) * stride3 + o] = stay;
-            if (sh.h_a != nullptr) {
-                const size_t ho = ((size_t)n * (sh.maxk + 1) + k) * sh.J + j;
-                sh.h_a[ho] = act ? sh.aj[o] : make_double2(0, 0);
-                sh.h_b[ho] = bj;
-                sh.h_pi[ho + sh.J] = act ? sh.pi[(size_t)((k + 1) % 3) * stride3 + o]
-                                         : make_double2(1, 0);
-            }
-        }
-        const double tot = block_sum<kBlock>((double)stay, shm);
-        const double mx = block_max<kBlock>(res, shm);
-        if (threadIdx.x == 0) {
-            cnt_next[bx] = (int)(tot + 0.5);
-            sh.mres[(size_t)n * kMaxSlices + bx] = mx;
-        }
-    }
-    return true;
-}
-
-// K3 body, basis forms: p <- r_{k+1} + beta p
-template <typename R>
-__device__ __forceinline__ void update_p_block(const JobDesc& J, int n, int bx, int k) {
-    const int f = sizeof(R) == 4 ? 1 : 0;
-    __shared__ double shm[kBlock / 64];
-    double2 beta;
-    if (!k3_scalars(J, n, bx, k, beta, shm)) return;
-    const int64_t n12 = 12 * J.g.V;
-    const R br = (R)beta.x, bi = (R)beta.y;
-    const C2<R>* rr = job_rk<const C2<R>>(J, k + 1, f) + (size_t)n * n12;
-    C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
-    for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
-        const cx<R> rv = ld<R>(rr, e), po = ld<R>(pp, e);
-        stc<R>(pp, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
-    }
-}
-
-// K3 body, sweep forms.  Every block rebuilds the list of shifts active at
-// the start of iteration k in LDS: coefficient (c_j alpha^j, or alpha^j for
-// the reference form), 1/pi_{k+1}^j and beta^j.  Then, per component:
-//   s += sum_l coef_l p_{j_l}   (fused)  or  x_j += alpha^j p_j (reference)
-//   p_{j_l} <- r / pi_{k+1} + beta^j p_{j_l};   p <- r + beta p
-// In the first iteration p_j = b for every j, read from b instead.
-template <typename R, bool REF>
-__device__ __forceinline__ void sweep_block(const JobDesc& J, int n, int bx, int k) {
-    const int f = sizeof(R) == 4 ? 1 : 0;
-    const ShiftDev& sh = J.sh;
-    __shared__ double shm[kBlock / 64];
+    const double2 c1 = cdiv(cmul(sc.alpha, S.beta[(k + 1) & 1]), S.alpha[(k + 1) & 1]);
+    const size_t stride3 = (size_t)sh.nsrc * sh.J;
+    // LDS list of the active shifts (sweep forms)
     extern __shared__ unsigned char lds_raw[];
     double2* l_coef = reinterpret_cast<double2*>(lds_raw);
     double2* l_ipi = l_coef + sh.J;
@@ -337,109 +280,138 @@ __device__ __forceinline__ void sweep_block(const JobDesc& J, int n, int bx, int
     int* l_j = reinterpret_cast<int*>(l_b + sh.J);
     __shared__ int wcount[kBlock / 64];
     __shared__ int base;
-    double2 beta;
-    if (!k3_scalars(J, n, bx, k, beta, shm)) return;
-    const size_t stride3 = (size_t)sh.nsrc * sh.J;
-    if (threadIdx.x == 0) base = 0;
-    __syncthreads();
+    if (SWEEP) {
+        if (threadIdx.x == 0) base = 0;
+        __syncthreads();
+    }
     for (int j0 = 0; j0 < sh.J; j0 += kBlock) {
+        const bool mine = (j0 / kBlock) == bx;  // this block keeps the state of slice j0
+        if (!SWEEP && !mine) continue;
         const int j = j0 + threadIdx.x;
         const size_t o = (size_t)n * sh.J + j;
         const bool act = j < sh.J && sh.active[(size_t)(k & 1) * stride3 + o] != 0;
-        double2 coef = make_double2(0, 0), ipi = coef, bj = coef;
-        if (act) {
-            const double2 pn = sh.pi[(size_t)((k + 1) % 3) * stride3 + o];
-            const double2 pk = sh.pi[(size_t)(k % 3) * stride3 + o];
-            const double2 rt = cdiv(pk, pn);
-            bj = cmul(cmul(rt, rt), beta);
-            ipi = cdiv(make_double2(1.0, 0.0), pn);
-            coef = REF ? sh.aj[o] : cmul(sh.c[j], sh.aj[o]);
-        }
-        const unsigned long long m = __ballot(act);
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int before = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wcount[w] = __popcll(m);
-        __syncthreads();
-        int off = base;
-        for (int i = 0; i < w; ++i) off += wcount[i];
-        if (act) {
-            l_j[off + before] = j;
-            l_coef[off + before] = coef;
-            l_ipi[off + before] = ipi;
-            l_b[off + before] = bj;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int i = 0; i < kBlock / 64; ++i) tot += wcount[i];
-            base += tot;
-        }
-        __syncthreads();
-    }
-    const int nl = base;
-    const int64_t n12 = 12 * J.g.V;
-    const R br = (R)beta.x, bi = (R)beta.y;
-    const C2<R>* rr = static_cast<const C2<R>*>(J.r[f]) + (size_t)n * n12;
-    C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
-    C2<R>* pj = static_cast<C2<R>*>(J.pj[f]);
-    double2* acc_out = REF ? J.xj : J.s64;
-    const double2* b0 = J.b64;
-    for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
-        const cx<R> rv = ld<R>(rr, e);
-        const cx<R> bfirst = (k == 0) ? mk<R>((R)b0[(size_t)n * n12 + e].x, (R)b0[(size_t)n * n12 + e].y)
-                                      : mk<R>(0, 0);
-        double sre = 0.0, sim = 0.0;
-        for (int l = 0; l < nl; ++l) {
-            const int j = l_j[l];
-            const double2 ca = l_coef[l], ip = l_ipi[l], bj = l_b[l];
-            C2<R>* pjp = pj + ((size_t)n * sh.J + j) * n12;
-            const cx<R> pv = (k == 0) ? bfirst : ld<R>(pjp, e);
-            if constexpr (REF) {
-                double2* xp = acc_out + ((size_t)n * sh.J + j) * n12;
-                double2 x = xp[e];
-                x.x += ca.x * (double)pv.re - ca.y * (double)pv.im;
-                x.y += ca.x * (double)pv.im + ca.y * (double)pv.re;
-                xp[e] = x;
-            } else {
-                sre += ca.x * (double)pv.re - ca.y * (double)pv.im;
-                sim += ca.x * (double)pv.im + ca.y * (double)pv.re;
+        ShiftScalars t{};
+        if (act) t = shift_scalars(sh, o, j, k, sc, c1, S.bb);
+        if (mine) {
+            int stay = 0;
+            if (j < sh.J) {
+                if (act) {
+                    sh.pi[(size_t)((k + 1) % 3) * stride3 + o] = t.pn;
+                    sh.aj[o] = t.aj;
+                    sh.res[o] = t.res;
+                    stay = (t.res > sh.tol && isfinite(t.res)) ? 1 : 0;
+                }
+                sh.active[(size_t)((k + 1) & 1) * stride3 + o] = stay;
+                if (sh.h_a != nullptr) {
+                    const size_t ho = ((size_t)n * (sh.maxk + 1) + k) * sh.J + j;
+                    sh.h_a[ho] = act ? t.aj : make_double2(0, 0);
+                    sh.h_b[ho] = act ? t.bj : make_double2(0, 0);
+                    sh.h_pi[ho + sh.J] = act ? t.pn : make_double2(1, 0);
+                }
             }
-            const R ipr = (R)ip.x, ipi_ = (R)ip.y, bjr = (R)bj.x, bji = (R)bj.y;
-            stc<R>(pjp, e, mk<R>(rv.re * ipr - rv.im * ipi_ + bjr * pv.re - bji * pv.im,
-                                 rv.re * ipi_ + rv.im * ipr + bjr * pv.im + bji * pv.re));
+            const double tot = block_sum<kBlock>((double)stay, shm);
+            const double mx = block_max<kBlock>(act ? t.res : 0.0, shm);
+            if (threadIdx.x == 0) {
+                cnt_next[bx] = (int)(tot + 0.5);
+                sh.mres[(size_t)n * kMaxSlices + bx] = mx;
+            }
         }
-        if constexpr (!REF) {
-            double2 sv = acc_out[(size_t)n * n12 + e];
-            sv.x += sre;
-            sv.y += sim;
-            acc_out[(size_t)n * n12 + e] = sv;
+        if (SWEEP) {
+            const double2 coef = act ? (KIND == 2 ? t.aj : cmul(sh.c[j], t.aj)) : make_double2(0, 0);
+            const unsigned long long m = __ballot(act);
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            const int before = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wcount[w] = __popcll(m);
+            __syncthreads();
+            int off = base;
+            for (int i = 0; i < w; ++i) off += wcount[i];
+            if (act) {
+                l_j[off + before] = j;
+                l_coef[off + before] = coef;
+                l_ipi[off + before] = t.ipi;
+                l_b[off + before] = t.bj;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int tot = 0;
+                for (int i = 0; i < kBlock / 64; ++i) tot += wcount[i];
+                base += tot;
+            }
+            __syncthreads();
         }
-        const cx<R> po = ld<R>(pp, e);
-        stc<R>(pp, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
+    }
+    const int64_t n12 = 12 * J.g.V;
+    const R ar = (R)sc.alpha.x, ai = (R)sc.alpha.y;
+    const R br = (R)sc.beta.x, bi = (R)sc.beta.y;
+    const C2<R>* ri = job_rk<const C2<R>>(J, k, f) + (size_t)n * n12;
+    C2<R>* ro = job_rk<C2<R>>(J, k + 1, f) + (size_t)n * n12;
+    const C2<R>* qq = static_cast<const C2<R>*>(J.q[f]) + (size_t)n * n12;
+    C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
+    if constexpr (!SWEEP) {
+        const bool acc2 = J.h != nullptr;
+        const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
+        double2* sacc = J.s64 + (size_t)n * n12;
+        for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
+            const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e), po = ld<R>(pp, e);
+            const cx<R> rn = mk<R>(r.re - (ar * qv.re - ai * qv.im), r.im - (ar * qv.im + ai * qv.re));
+            stc<R>(ro, e, rn);
+            stc<R>(pp, e, mk<R>(rn.re + br * po.re - bi * po.im, rn.im + br * po.im + bi * po.re));
+            if (acc2) {
+                double2 sv = sacc[e];
+                sv.x += hk.x * (double)rn.re - hk.y * (double)rn.im;
+                sv.y += hk.x * (double)rn.im + hk.y * (double)rn.re;
+                sacc[e] = sv;
+            }
+        }
+    } else {
+        const int nl = base;
+        C2<R>* pj = static_cast<C2<R>*>(J.pj[f]);
+        double2* acc_out = KIND == 2 ? J.xj : J.s64;
+        const double2* b0 = J.b64;
+        for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
+            const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e);
+            const cx<R> rv = mk<R>(r.re - (ar * qv.re - ai * qv.im), r.im - (ar * qv.im + ai * qv.re));
+            stc<R>(ro, e, rv);
+            const cx<R> bfirst = (k == 0) ? mk<R>((R)b0[(size_t)n * n12 + e].x, (R)b0[(size_t)n * n12 + e].y)
+                                          : mk<R>(0, 0);
+            double sre = 0.0, sim = 0.0;
+            for (int l = 0; l < nl; ++l) {
+                const int j = l_j[l];
+                const double2 ca = l_coef[l], ip = l_ipi[l], bj = l_b[l];
+                C2<R>* pjp = pj + ((size_t)n * sh.J + j) * n12;
+                const cx<R> pv = (k == 0) ? bfirst : ld<R>(pjp, e);
+                if constexpr (KIND == 2) {
+                    double2* xp = acc_out + ((size_t)n * sh.J + j) * n12;
+                    double2 x = xp[e];
+                    x.x += ca.x * (double)pv.re - ca.y * (double)pv.im;
+                    x.y += ca.x * (double)pv.im + ca.y * (double)pv.re;
+                    xp[e] = x;
+                } else {
+                    sre += ca.x * (double)pv.re - ca.y * (double)pv.im;
+                    sim += ca.x * (double)pv.im + ca.y * (double)pv.re;
+                }
+                const R ipr = (R)ip.x, ipi_ = (R)ip.y, bjr = (R)bj.x, bji = (R)bj.y;
+                stc<R>(pjp, e, mk<R>(rv.re * ipr - rv.im * ipi_ + bjr * pv.re - bji * pv.im,
+                                     rv.re * ipi_ + rv.im * ipr + bjr * pv.im + bji * pv.re));
+            }
+            if constexpr (KIND == 1) {
+                double2 sv = acc_out[(size_t)n * n12 + e];
+                sv.x += sre;
+                sv.y += sim;
+                acc_out[(size_t)n * n12 + e] = sv;
+            }
+            const cx<R> po = ld<R>(pp, e);
+            stc<R>(pp, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
+        }
     }
 }
 
-// Job-table wrappers: one launch covers every (job, source, block) of a batch.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_update_r_jobs(const JobDesc* __restrict__ jobs,
-                                                          int njobs, const int* __restrict__ kdev) {
+template <typename R, int KIND>
+__global__ __launch_bounds__(kBlock) void k_update_jobs(const JobDesc* __restrict__ jobs, int njobs,
+                                                        const int* __restrict__ kdev) {
     const int k = (int)uniform((uint32_t)*kdev);
     const VecBlock v = vec_block(jobs, njobs);
-    update_r_block<R>(jobs[v.j], v.n, v.bx, k);
-}
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_update_p_jobs(const JobDesc* __restrict__ jobs,
-                                                          int njobs, const int* __restrict__ kdev) {
-    const int k = (int)uniform((uint32_t)*kdev);
-    const VecBlock v = vec_block(jobs, njobs);
-    update_p_block<R>(jobs[v.j], v.n, v.bx, k);
-}
-template <typename R, bool REF>
-__global__ __launch_bounds__(kBlock) void k_sweep_jobs(const JobDesc* __restrict__ jobs, int njobs,
-                                                       const int* __restrict__ kdev) {
-    const int k = (int)uniform((uint32_t)*kdev);
-    const VecBlock v = vec_block(jobs, njobs);
-    sweep_block<R, REF>(jobs[v.j], v.n, v.bx, k);
+    update_block<R, KIND>(jobs[v.j], v.n, v.bx, k);
 }
 // the iteration counter of a batch, advanced once per seed iteration
 __global__ void k_advance(int* kdev) {
@@ -447,22 +419,19 @@ __global__ void k_advance(int* kdev) {
 }
 
 template <typename R>
-void launch_iteration_k23(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
-                          int form, int maxJ, hipStream_t s) {
+void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
+                             int form, int maxJ, hipStream_t s) {
     const dim3 grid(vec_blocks_total), blk(kBlock);
-    hipLaunchKernelGGL(k_update_r_jobs<R>, grid, blk, 0, s, jobs, njobs, kdev);
-    if (form == OVL_FORM_BASIS || form == OVL_FORM_TWOPASS) {
-        hipLaunchKernelGGL(k_update_p_jobs<R>, grid, blk, 0, s, jobs, njobs, kdev);
-    } else {
-        const size_t lds = (size_t)maxJ * (3 * sizeof(double2) + sizeof(int));
-        if (form == OVL_FORM_REFERENCE)
-            hipLaunchKernelGGL((k_sweep_jobs<R, true>), grid, blk, lds, s, jobs, njobs, kdev);
-        else
-            hipLaunchKernelGGL((k_sweep_jobs<R, false>), grid, blk, lds, s, jobs, njobs, kdev);
-    }
+    const size_t lds = (size_t)maxJ * (3 * sizeof(double2) + sizeof(int));
+    if (form == OVL_FORM_BASIS || form == OVL_FORM_TWOPASS)
+        hipLaunchKernelGGL((k_update_jobs<R, 0>), grid, blk, 0, s, jobs, njobs, kdev);
+    else if (form == OVL_FORM_FUSED)
+        hipLaunchKernelGGL((k_update_jobs<R, 1>), grid, blk, lds, s, jobs, njobs, kdev);
+    else
+        hipLaunchKernelGGL((k_update_jobs<R, 2>), grid, blk, lds, s, jobs, njobs, kdev);
 }
-template void launch_iteration_k23<double>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
-template void launch_iteration_k23<float>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
+template void launch_iteration_update<double>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
+template void launch_iteration_update<float>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
 void launch_advance(int* kdev, hipStream_t s) {
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, kdev);
 }

@@ -67,7 +67,7 @@ struct ovl_ctx {
     DBuf b64, r64, p64, q64, r32, p32, q32, s64, pj64, pj32, xj;
     std::vector<DBuf> slot_chunks;   // basis forms: kSlotChunk residual slots each
     size_t slot_chunk_bytes = 0;
-    DBuf part_w, part_e, state, shifts, lists, nodes_dev, hist, W, h;
+    DBuf part_w, part_b, state, shifts, lists, nodes_dev, hist, W, h;
     SrcState* host_state = nullptr;  // pinned mirror
     int host_state_n = 0;
     DBuf bench_a, bench_b;
@@ -255,7 +255,7 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     DBuf* bufs[] = {&ctx->U64,  &ctx->U32,   &ctx->hw_in,  &ctx->hw_out, &ctx->b64,   &ctx->r64,
                     &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
-                    &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_e,
+                    &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_b,
                     &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
                     &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->fY, &ctx->fX, &ctx->fpsi,
                     &ctx->facc, &ctx->fc, &ctx->fpart, &ctx->slot_table, &ctx->jobs_dev};
@@ -586,9 +586,9 @@ struct Work {
     float2 *r32, *p32, *q32, *pj32;
     std::vector<char*> chunks;  // basis: slot i at chunks[i / kSlotChunk] + (i % kSlotChunk) * slot_bytes
     size_t slot_bytes;          // nsrc * N * sizeof(double2)
-    double2* part_w;
-    double* part_e;
-    int nbw, nbe;          // partials per source of K1 and of the vector kernels
+    double4* part_w;       // K1 partials per source and stencil block
+    double* part_b;        // ||b||^2 partials at initialisation
+    int nbw, nbe;          // stencil blocks and vector-kernel blocks per source
     SrcState* st;          // device state block: st | cnt | mres (one copy to the host)
     size_t state_bytes;
     ShiftDev sh;
@@ -673,12 +673,12 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     const int nslices = (J + 255) / 256;
     w.nbw = wilson_blocks(ctx->g);
     w.nbe = vec_blocks(N, nslices);
-    HIPCHK(ctx, ctx->part_w.ensure((size_t)nsrc * w.nbw * sizeof(double2)));
-    HIPCHK(ctx, ctx->part_e.ensure((size_t)nsrc * w.nbe * sizeof(double)));
+    HIPCHK(ctx, ctx->part_w.ensure((size_t)nsrc * w.nbw * sizeof(double4)));
+    HIPCHK(ctx, ctx->part_b.ensure((size_t)nsrc * w.nbe * sizeof(double)));
     w.state_bytes = state_bytes_for(nsrc);
     HIPCHK(ctx, ctx->state.ensure(w.state_bytes));
-    w.part_w = ctx->part_w.as<double2>();
-    w.part_e = ctx->part_e.as<double>();
+    w.part_w = ctx->part_w.as<double4>();
+    w.part_b = ctx->part_b.as<double>();
     w.st = ctx->state.as<SrcState>();
     const size_t sj = (size_t)nsrc * J;
     HIPCHK(ctx, ctx->shifts.ensure(sj * (4 * sizeof(double2) + sizeof(double) + 2 * sizeof(int))));
@@ -799,7 +799,6 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, int variant, int& sten_b0, int& 
     d.st = w.st;
     d.sh = w.sh;
     d.part_w = w.part_w;
-    d.part_e = w.part_e;
     d.p[0] = w.p64; d.p[1] = w.p32;
     d.q[0] = w.q64; d.q[1] = w.q32;
     d.r[0] = w.r64; d.r[1] = w.r32;
@@ -829,7 +828,7 @@ void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool pr
             sten_b += V * es * (36.0 + 36.0 * n);
             vec_b += 3.0 * es * N * n;
             const bool ref = B.form == OVL_FORM_REFERENCE;
-            sweep_b += N * (n * (3.0 * es + (ref ? 0.0 : 32.0)));
+            sweep_b += N * (n * (2.0 * es + (ref ? 0.0 : 32.0)));
         }
         const double N0 = 12.0 * B.ctx[0]->g.V;
         sweep_b += N0 * nact_total * (2.0 * es + (B.form == OVL_FORM_REFERENCE ? 32.0 : 0.0));
@@ -843,11 +842,12 @@ void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool pr
             launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.sten_total, var, s);
         }
         {
-            // K2 and K3 together: r update (3 vectors) plus p update (3) or the sweep
+            // K2: r update (r, q read, r written) plus p update (p read and
+            // written) or the sweep
             ProfScope ps(lead, s, prof ? (sweep ? 4 + c32 : 2 + c32) : -1,
-                         sweep ? vec_b + sweep_b : 2.0 * vec_b);
-            launch_iteration_k23<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.vec_total, B.form,
-                                    B.maxJ, s);
+                         sweep ? vec_b + sweep_b : 5.0 / 3.0 * vec_b);
+            launch_iteration_update<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.vec_total,
+                                       B.form, B.maxJ, s);
         }
         launch_advance(B.kdev, s);
     }
@@ -901,7 +901,7 @@ int init_job(ovl_ctx* c, Work& w, hipStream_t s) {
     HIPCHK(c, hipMemcpyAsync(w.p64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
     if (form == OVL_FORM_FUSED) HIPCHK(c, hipMemsetAsync(w.s64, 0, vec64, s));
     if (form == OVL_FORM_REFERENCE) HIPCHK(c, hipMemsetAsync(w.xj, 0, vec64 * w.J, s));
-    launch_init_state(w.st, w.b64, w.part_e, w.N, w.sh, s);
+    launch_init_state(w.st, w.b64, w.part_b, w.N, w.sh, s);
     HIPCHK(c, hipGetLastError());
     return OVL_OK;
 }

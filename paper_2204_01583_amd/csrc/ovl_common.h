@@ -125,8 +125,7 @@ struct JobDesc {
     int vec_b0, nbe;            // this job's first block in the vector grid; blocks per source
     SrcState* st;
     ShiftDev sh;
-    double2* part_w;            // [nsrc][nsb]
-    double* part_e;             // [nsrc][nbe]
+    double4* part_w;            // [nsrc][nsb]: <r_k, q> (re, im), ||q||^2, ||r_k||^2 per block
     // working vectors [nsrc][12V], index [0] FP64, [1] FP32
     void* p[2];
     void* q[2];

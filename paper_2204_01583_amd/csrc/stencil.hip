@@ -147,7 +147,7 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
                                              const C2<R>* __restrict__ U, const Geom& g, R kappa,
                                              double zsr, double zsi,
                                              const C2<R>* __restrict__ rdot,
-                                             double2* __restrict__ partial,
+                                             double4* __restrict__ partial,
                                              const SrcState* __restrict__ stt,
                                              const ShiftDev& sh, int k, int nsb, int nrhs,
                                              unsigned tile) {
@@ -170,9 +170,10 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
     const uint32_t V = (uint32_t)g.V;
     const uint32_t s = (uint32_t)sb * kBlock + threadIdx.x;
     const bool valid = s < V;
-    double dre[RPT], dim[RPT];
+    // per rhs: <r, q> (re, im), ||q||^2 and ||r||^2 of this block's sites
+    double dre[RPT], dim[RPT], dqq[RPT], drr[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) dre[r] = dim[r] = 0.0;
+    for (int r = 0; r < RPT; ++r) dre[r] = dim[r] = dqq[r] = drr[r] = 0.0;
     if (valid) {
         const C2<R>* psi[RPT];
 #pragma unroll
@@ -216,6 +217,8 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
                         // <r, q> = sum conj(r) q, accumulated in FP64
                         dre[r] += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
                         dim[r] += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
+                        dqq[r] += (double)q.re * (double)q.re + (double)q.im * (double)q.im;
+                        drr[r] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
                     }
                 }
             }
@@ -227,8 +230,10 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
         for (int r = 0; r < RPT; ++r) {
             const double tr = block_sum<kBlock>(dre[r], shd);
             const double ti_ = block_sum<kBlock>(dim[r], shd);
+            const double tq = block_sum<kBlock>(dqq[r], shd);
+            const double tn = block_sum<kBlock>(drr[r], shd);
             if (on[r] && threadIdx.x == 0)
-                partial[(int64_t)(n0 + r) * nsb + sb] = make_double2(tr, ti_);
+                partial[(int64_t)(n0 + r) * nsb + sb] = make_double4(tr, ti_, tq, tn);
         }
     }
 }
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
                                                    const C2<R>* __restrict__ U, Geom g, R kappa,
                                                    double zsr, double zsi,
                                                    const C2<R>* __restrict__ rdot,
-                                                   double2* __restrict__ partial,
+                                                   double4* __restrict__ partial,
                                                    const SrcState* __restrict__ stt,
                                                    ShiftDev sh, int k, int nsb, int nrhs) {
     const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
@@ -292,7 +297,7 @@ template void launch_wilson_jobs<float>(const JobDesc*, int, const int*, int, in
 
 template <typename R, int HPI, int RPT, int ORD>
 void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
-                     double kappa, double2 zs, const C2<R>* r, double2* partial,
+                     double kappa, double2 zs, const C2<R>* r, double4* partial,
                      const SrcState* stt, const ShiftDev& sh, int k, int nrhs, hipStream_t s) {
     const int nsb = wilson_blocks(g);
     const int ngrp = (nrhs + RPT - 1) / RPT;
@@ -307,7 +312,7 @@ void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, cons
 
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
-                   double kappa, double2 zs, const C2<R>* r, double2* partial,
+                   double kappa, double2 zs, const C2<R>* r, double4* partial,
                    const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s,
                    int variant) {
     ShiftDev none{};
@@ -326,10 +331,10 @@ void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const 
 #undef OVL_WV
 }
 template void launch_wilson<double>(int, const double2*, double2*, const double2*, const Geom&,
-                                    double, double2, const double2*, double2*, const SrcState*,
+                                    double, double2, const double2*, double4*, const SrcState*,
                                     const ShiftDev*, int, int, hipStream_t, int);
 template void launch_wilson<float>(int, const float2*, float2*, const float2*, const Geom&,
-                                   double, double2, const float2*, double2*, const SrcState*,
+                                   double, double2, const float2*, double4*, const SrcState*,
                                    const ShiftDev*, int, int, hipStream_t, int);
 
 }  // namespace ovl
