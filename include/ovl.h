@@ -165,7 +165,7 @@ int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
  * and the algorithmic bytes of one launch in *bytes.  which:
  *   0: FP64 stencil (out = H_W in) on nrhs internal spinors, autotuned variant
  *   1: the same in FP32
- *   100+v, 200+v: FP64 / FP32 stencil variant v (0..7),
+ *   100+v, 200+v: FP64 / FP32 stencil variant v (0..23),
  *      v = 4*order + 2*(rhs per lane - 1) + (hops per loop step - 1): one or
  *      both hops of a direction per step, one or two rhs per lane sharing each
  *      link load, blocks ordered rhs-fastest (0) or site-fastest (1).

@@ -22,10 +22,13 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 // out = H_W in                                               (mode 0)
 // out = zs*in - H_W in, partial[src][blk] = (<r,out>, ||out||^2, ||r||^2) (mode 1); sources that are
 // not live at iteration k (see kernels.hip) are skipped.
-// variant v = 4*order + 2*(rhs per lane - 1) + (hops per loop step - 1):
-// hops per step 1 or 2 (both directions of one mu), 1 or 2 rhs per lane
-// sharing each link load, block order 0 (rhs fastest) or 1 (sites fastest).
-constexpr int kStencilVariants = 8;
+// variant v = 16*tile + 8*(lanes per site - 1) + 4*order +
+// 2*(rhs per lane - 1) + (hops per loop step - 1): hops per step 1 or 2, 1 or
+// 2 rhs per lane sharing each link load, block order 0 (rhs fastest) or 1
+// (sites fastest), 1 lane per site (all 8 hops) or 2 (forward and backward
+// hops on neighbouring lanes, 512-thread blocks), and (v >= 16, one lane per
+// site) the block's 256 sites staged in LDS for the neighbours inside it.
+constexpr int kStencilVariants = 24;
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                    double kappa, double2 zs, const C2<R>* r, double4* partial,

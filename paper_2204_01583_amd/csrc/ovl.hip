@@ -70,7 +70,7 @@ struct ovl_ctx {
     DBuf part_w, part_b, state, shifts, lists, nodes_dev, hist, W, h;
     SrcState* host_state = nullptr;  // pinned mirror
     int host_state_n = 0;
-    DBuf bench_a, bench_b;
+    DBuf bench_a, bench_b, bench_c, tune_state;
     DBuf fY, fX, fpsi, facc, fc, fpart;  // force work space
     DBuf slot_table;                       // basis form: device table of slot-chunk bases
     // solve stream (graphs cannot be captured on the legacy null stream) and handoff events
@@ -87,7 +87,7 @@ struct ovl_ctx {
     double prof_ms[kClasses] = {0};
     int64_t prof_n[kClasses] = {0};
     double prof_bytes[kClasses] = {0};
-    // stencil variant chosen per (nrhs, precision) by the autotuner
+    // stencil variant chosen per (nrhs, precision + 2 mode) by the autotuner
     std::map<std::pair<int, int>, int> stencil_variant;
     ovl_stats last{};
     char err[512] = {0};
@@ -257,7 +257,7 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
                     &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
                     &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_b,
                     &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
-                    &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->fY, &ctx->fX, &ctx->fpsi,
+                    &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->bench_c, &ctx->tune_state, &ctx->fY, &ctx->fX, &ctx->fpsi,
                     &ctx->facc, &ctx->fc, &ctx->fpart, &ctx->slot_table, &ctx->jobs_dev};
     for (DBuf* b : bufs) b->release();
     for (DBuf& b : ctx->slot_chunks) b.release();
@@ -402,15 +402,15 @@ namespace {
 
 std::mutex g_tune_mu;
 
-std::string tune_key(const ovl_ctx* ctx, int nrhs, int prec) {
+std::string tune_key(const ovl_ctx* ctx, int nrhs, int prec, int mode) {
     hipDeviceProp_t prop;
     const char* arch = "gpu";
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
     int rt = 0;
     (void)hipRuntimeGetVersion(&rt);
     char buf[256];
-    snprintf(buf, sizeof(buf), "%s|hip%d|%dx%dx%dx%d|n%d|%s", arch, rt, ctx->g.L[0], ctx->g.L[1],
-             ctx->g.L[2], ctx->g.L[3], nrhs, prec ? "fp32" : "fp64");
+    snprintf(buf, sizeof(buf), "%s|hip%d|%dx%dx%dx%d|n%d|%s|m%d", arch, rt, ctx->g.L[0],
+             ctx->g.L[1], ctx->g.L[2], ctx->g.L[3], nrhs, prec ? "fp32" : "fp64", mode);
     std::string k(buf);
     for (char& c : k)
         if (c == '"' || c == '\\') c = '_';
@@ -454,8 +454,17 @@ void write_cache(const char* path, const std::map<std::string, int>& m) {
     (void)rename(tmp.c_str(), path);
 }
 
+// Inputs of a mode-1 timing launch: every source live at iteration 0.
+struct TuneInputs {
+    const void* r = nullptr;
+    double4* partial = nullptr;
+    const SrcState* st = nullptr;
+    ShiftDev sh{};
+};
+
 template <typename R>
-double time_variant(ovl_ctx* ctx, int v, int nrhs, C2<R>* a, C2<R>* b, const C2<R>* U) {
+double time_variant(ovl_ctx* ctx, int v, int nrhs, int mode, C2<R>* a, C2<R>* b, const C2<R>* U,
+                    const TuneInputs& ti) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 1e30;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -463,8 +472,13 @@ double time_variant(ovl_ctx* ctx, int v, int nrhs, C2<R>* a, C2<R>* b, const C2<
         return 1e30;
     }
     auto run = [&]() {
-        launch_wilson<R>(0, a, b, U, ctx->g, kappa_of(ctx->m0), make_double2(0, 0), nullptr, nullptr,
-                         nullptr, nullptr, 0, nrhs, ctx->stream, v);
+        if (mode == 1)
+            launch_wilson<R>(1, a, b, U, ctx->g, kappa_of(ctx->m0), ctx->zseed,
+                             static_cast<const C2<R>*>(ti.r), ti.partial, ti.st, &ti.sh, 0, nrhs,
+                             ctx->stream, v);
+        else
+            launch_wilson<R>(0, a, b, U, ctx->g, kappa_of(ctx->m0), make_double2(0, 0), nullptr,
+                             nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, v);
     };
     run();
     const int reps = 4;
@@ -485,20 +499,22 @@ double time_variant(ovl_ctx* ctx, int v, int nrhs, C2<R>* a, C2<R>* b, const C2<
 
 }  // namespace
 
-// Variant of the stencil for nrhs right-hand sides in precision prec (0 FP64, 1 FP32).
-static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec) {
+// Variant of the stencil for nrhs right-hand sides in precision prec (0 FP64,
+// 1 FP32) and mode (0: H_W alone; 1: the solver's q = z_s p - H p with its
+// dot products, timed with every source live).
+static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec, int mode = 0) {
     const char* force = getenv("OVL_STENCIL_VARIANT");
     if (force && *force) {
         const int v = atoi(force);
         if (v >= 0 && v < kStencilVariants) return v;
     }
-    const auto key = std::make_pair(nrhs, prec);
+    const auto key = std::make_pair(nrhs, prec + 2 * mode);
     auto it = ctx->stencil_variant.find(key);
     if (it != ctx->stencil_variant.end()) return it->second;
     const char* at = getenv("OVL_AUTOTUNE");
     if (at && at[0] == '0') return ctx->stencil_variant[key] = 0;
     const char* path = getenv("OVL_AUTOTUNE_CACHE");
-    const std::string k = tune_key(ctx, nrhs, prec);
+    const std::string k = tune_key(ctx, nrhs, prec, mode);
     if (path && *path) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto m = read_cache(path);
@@ -509,14 +525,43 @@ static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec) {
     const size_t es = prec ? sizeof(float2) : sizeof(double2);
     const size_t nb = (size_t)nrhs * n12(ctx) * es;
     int best = 0;
-    if (ctx->bench_a.ensure(nb) == hipSuccess && ctx->bench_b.ensure(nb) == hipSuccess &&
-        hipMemsetAsync(ctx->bench_a.p, 0, nb, ctx->stream) == hipSuccess) {
+    bool ok = ctx->bench_a.ensure(nb) == hipSuccess && ctx->bench_b.ensure(nb) == hipSuccess &&
+              hipMemsetAsync(ctx->bench_a.p, 0, nb, ctx->stream) == hipSuccess;
+    TuneInputs ti;
+    if (ok && mode == 1) {
+        // r (a vector of its own, so its loads cost what they do in the
+        // solver), per-block partials and a state block with every source
+        // live at iteration 0: status 0 and one active shift in slice 0
+        const size_t st_bytes = ((size_t)nrhs * sizeof(SrcState) + 255) & ~(size_t)255;
+        const size_t cnt_bytes = ((size_t)2 * nrhs * kMaxSlices * sizeof(int) + 255) & ~(size_t)255;
+        const size_t part_bytes = (size_t)nrhs * wilson_blocks(ctx->g) * sizeof(double4);
+        ok = ctx->bench_c.ensure(nb) == hipSuccess &&
+             hipMemsetAsync(ctx->bench_c.p, 0, nb, ctx->stream) == hipSuccess &&
+             ctx->tune_state.ensure(st_bytes + cnt_bytes + part_bytes) == hipSuccess &&
+             hipMemsetAsync(ctx->tune_state.p, 0, st_bytes + cnt_bytes, ctx->stream) == hipSuccess;
+        if (ok) {
+            std::vector<int> cnt((size_t)nrhs * kMaxSlices, 0);
+            for (int n = 0; n < nrhs; ++n) cnt[(size_t)n * kMaxSlices] = 1;
+            char* base = ctx->tune_state.as<char>();
+            ok = hipMemcpyAsync(base + st_bytes, cnt.data(), cnt.size() * sizeof(int),
+                                hipMemcpyHostToDevice, ctx->stream) == hipSuccess &&
+                 hipStreamSynchronize(ctx->stream) == hipSuccess;
+            ti.r = ctx->bench_c.p;
+            ti.st = reinterpret_cast<const SrcState*>(base);
+            ti.partial = reinterpret_cast<double4*>(base + st_bytes + cnt_bytes);
+            ti.sh.cnt = reinterpret_cast<int*>(base + st_bytes);
+            ti.sh.nsrc = nrhs;
+            ti.sh.nslices = 1;
+            ti.sh.maxk = 1;
+        }
+    }
+    if (ok) {
         double tbest = 1e30;
         for (int v = 0; v < kStencilVariants; ++v) {
-            const double t = prec ? time_variant<float>(ctx, v, nrhs, ctx->bench_a.as<float2>(),
-                                                        ctx->bench_b.as<float2>(), ctx->U32.as<float2>())
-                                  : time_variant<double>(ctx, v, nrhs, ctx->bench_a.as<double2>(),
-                                                         ctx->bench_b.as<double2>(), ctx->U64.as<double2>());
+            const double t = prec ? time_variant<float>(ctx, v, nrhs, mode, ctx->bench_a.as<float2>(),
+                                                        ctx->bench_b.as<float2>(), ctx->U32.as<float2>(), ti)
+                                  : time_variant<double>(ctx, v, nrhs, mode, ctx->bench_a.as<double2>(),
+                                                         ctx->bench_b.as<double2>(), ctx->U64.as<double2>(), ti);
             if (t < tbest) {
                 tbest = t;
                 best = v;
@@ -777,12 +822,14 @@ struct Batch {
     std::vector<ovl_ctx*> ctx;
     std::vector<Work*> w;
     std::vector<JobDesc> desc;
-    int sten_total = 0, vec_total = 0, variant64 = 0, variant32 = 0, form = 0, maxJ = 0;
+    int sten_total[2] = {0, 0};  // stencil grid of the FP64 and of the FP32 variant
+    int vec_total = 0, variant64 = 0, variant32 = 0, form = 0, maxJ = 0;
     JobDesc* desc_dev = nullptr;
     int* kdev = nullptr;
 };
 
-void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, int variant, int& sten_b0, int& vec_b0) {
+void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], int (&sten_b0)[2],
+               int& vec_b0) {
     d.g = c->g;
     d.kappa = kappa_of(c->m0);
     d.zs = c->zseed;
@@ -790,9 +837,11 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, int variant, int& sten_b0, int& 
     d.U[1] = c->U32.p;
     d.nsrc = w.nsrc;
     d.nsb = wilson_blocks(c->g);
-    d.sten_b0 = sten_b0;
-    d.sten_nb = wilson_grid_blocks(c->g, w.nsrc, variant);
-    sten_b0 += d.sten_nb;
+    for (int f = 0; f < 2; ++f) {
+        d.sten_b0[f] = sten_b0[f];
+        d.sten_nb[f] = wilson_grid_blocks(c->g, w.nsrc, variant[f]);
+        sten_b0[f] += d.sten_nb[f];
+    }
     d.vec_b0 = vec_b0;
     d.nbe = w.nbe;
     vec_b0 += w.nbe * w.nsrc;
@@ -839,7 +888,7 @@ void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool pr
         (void)k_host;
         {
             ProfScope ps(lead, s, prof ? 0 + c32 : -1, sten_b);
-            launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.sten_total, var, s);
+            launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.sten_total[c32], var, s);
         }
         {
             // K2: r update (r, q read, r written) plus p update (p read and
@@ -860,7 +909,7 @@ int replay_chunk(Batch& B, hipStream_t s) {
     const int ph = sizeof(R) == 4 ? 1 : 0;
     char kb[256];
     snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d", (void*)B.desc_dev, (void*)B.kdev,
-             B.desc.size(), B.sten_total, B.vec_total, ph ? B.variant32 : B.variant64, B.form, B.maxJ);
+             B.desc.size(), B.sten_total[ph], B.vec_total, ph ? B.variant32 : B.variant64, B.form, B.maxJ);
     auto& gc = lead->graphs[ph];
     if (!gc.exec || gc.key != kb) {
         if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
@@ -988,20 +1037,19 @@ static int solve_batch(Batch& B) {
     size_t big = 0;
     for (size_t i = 1; i < B.w.size(); ++i)
         if (B.ctx[i]->g.V * B.w[i]->nsrc > B.ctx[big]->g.V * B.w[big]->nsrc) big = i;
-    B.variant64 = stencil_variant(B.ctx[big], B.w[big]->nsrc, 0);
-    B.variant32 = mixed ? stencil_variant(B.ctx[big], B.w[big]->nsrc, 1) : 0;
-    // both phases share one stencil grid layout, which depends on the rhs per
-    // lane: the FP32 variant takes the FP64 variant's choice of it
-    if (mixed) B.variant32 = (B.variant32 & ~2) | (B.variant64 & 2);
+    B.variant64 = stencil_variant(B.ctx[big], B.w[big]->nsrc, 0, 1);
+    B.variant32 = mixed ? stencil_variant(B.ctx[big], B.w[big]->nsrc, 1, 1) : 0;
     B.form = form;
     B.maxJ = 0;
     B.desc.resize(B.w.size());
-    int sb = 0, vb = 0;
+    int sb[2] = {0, 0}, vb = 0;
+    const int vars[2] = {B.variant64, B.variant32};
     for (size_t i = 0; i < B.w.size(); ++i) {
-        fill_desc(B.ctx[i], *B.w[i], B.desc[i], B.variant64, sb, vb);
+        fill_desc(B.ctx[i], *B.w[i], B.desc[i], vars, sb, vb);
         B.maxJ = std::max(B.maxJ, B.w[i]->J);
     }
-    B.sten_total = sb;
+    B.sten_total[0] = sb[0];
+    B.sten_total[1] = sb[1];
     B.vec_total = vb;
     const size_t dbytes = (B.desc.size() * sizeof(JobDesc) + 255) & ~(size_t)255;
     HIPCHK(lead, lead->jobs_dev.ensure(dbytes + 256));

@@ -121,7 +121,7 @@ struct JobDesc {
     const void* U[2];           // links, [0] FP64 [1] FP32 (internal layout)
     int nsrc;
     int nsb;                    // site blocks of the stencil
-    int sten_b0, sten_nb;       // this job's blocks in the stencil grid
+    int sten_b0[2], sten_nb[2]; // this job's blocks in the FP64 / FP32 stencil grid
     int vec_b0, nbe;            // this job's first block in the vector grid; blocks per source
     SrcState* st;
     ShiftDev sh;

@@ -1,8 +1,9 @@
 // The hermitian Wilson stencil H_W = gamma5 D_W(-m0) for gfx950 (HIP).
 // Bandwidth bound (at most ~3.6 flop per algorithmic byte in FP64), so no
-// matrix cores: one lane per site (and rhs), structure-of-arrays spinors and
-// links, 32-bit offsets from uniform bases, an XCD-aware block order, and
-// eight register/latency trade-off variants chosen by the autotuner.
+// matrix cores: one or two lanes per site (and rhs), structure-of-arrays
+// spinors and links, 32-bit offsets from uniform bases, an XCD-aware block
+// order, an optional LDS tile of the block's sites, and 24
+// register/latency/locality trade-off variants chosen by the autotuner.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -57,25 +58,42 @@ __device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
 // One hop for RPT right-hand sides sharing the link: project each neighbour
 // spinor to a half-spinor, move it through the link (U_mu(x) forward,
 // U_mu(x-mu)^dag backward), reconstruct into acc.  Per-lane offsets are 32-bit
-// element indices from uniform base pointers.
-template <typename R, int RPT>
+// element indices from uniform base pointers.  With an LDS tile (TIL = 1:
+// the block's 256 sites [s0, s0 + 256) of every rhs, component-major), a
+// neighbour inside the tile is read from LDS instead of memory.
+template <typename R, int RPT, int TIL>
 __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
                                     const C2<R>* const (&psi)[RPT],
                                     const C2<R>* __restrict__ Um, uint32_t V, uint32_t nb,
-                                    uint32_t lsite) {
+                                    uint32_t lsite, const C2<R>* tile, uint32_t s0) {
     const R sg = fwd ? R(-1) : R(1);
+    cx<R> pv[RPT][4][3];
+    const uint32_t lo = nb - s0;
+    if (TIL && lo < (uint32_t)kBlock) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const C2<R> v = tile[(uint32_t)((r * 12 + 3 * a + c) * kBlock) + lo];
+                    pv[r][a][c] = mk<R>(v.x, v.y);
+                }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pv[r][a][c] = ld<R>(psi[r], (uint32_t)(3 * a + c) * V + nb);
+    }
     cx<R> h[RPT][2][3];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
+    for (int r = 0; r < RPT; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const cx<R> p0 = ld<R>(psi[r], (uint32_t)(0 + c) * V + nb);
-            const cx<R> p1 = ld<R>(psi[r], (uint32_t)(3 + c) * V + nb);
-            const cx<R> p2 = ld<R>(psi[r], (uint32_t)(6 + c) * V + nb);
-            const cx<R> p3 = ld<R>(psi[r], (uint32_t)(9 + c) * V + nb);
-            project<R>(mu, sg, p0, p1, p2, p3, h[r][0][c], h[r][1][c]);
-        }
-    }
+        for (int c = 0; c < 3; ++c)
+            project<R>(mu, sg, pv[r][0][c], pv[r][1][c], pv[r][2][c], pv[r][3][c], h[r][0][c],
+                       h[r][1][c]);
     // element (a,b) of the hop matrix: U[a][b] forward, conj(U[b][a]) backward
     const R ci = fwd ? R(1) : R(-1);
     cx<R> u[RPT][2][3];
@@ -111,30 +129,52 @@ __device__ __forceinline__ uint32_t nbr(const Geom& g, uint32_t s, const int (&c
     return (cm == 0) ? s + (uint32_t)(L - 1) * sd : s - sd;
 }
 
-// acc = sum over the 8 hops.  The hop loop stays rolled so that only HPI hops'
-// loads are live at a time (fully unrolled, the scheduler hoists every
-// neighbour's loads and the kernel spills).  HPI = 2 takes both hops of one
-// direction per iteration: twice the loads in flight for more registers.
-template <typename R, int HPI, int RPT>
+// acc = sum over the hops of this lane.  The hop loop stays rolled so that
+// only HPI hops' loads are live at a time (fully unrolled, the scheduler
+// hoists every neighbour's loads and the kernel spills).  SPL = 1: one lane
+// takes all 8 hops; HPI = 2 takes both hops of one direction per iteration
+// (twice the loads in flight for more registers).  SPL = 2: two neighbouring
+// lanes share a site, lane h = 0 the four forward hops and h = 1 the four
+// backward ones, so mu stays wave-uniform; HPI = 2 takes two directions per
+// iteration.
+template <typename R, int HPI, int RPT, int SPL, int TIL>
 __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
                                             const C2<R>* const (&psi)[RPT],
                                             const C2<R>* __restrict__ U, const Geom& g,
-                                            uint32_t s, const int (&coord)[4]) {
+                                            uint32_t s, const int (&coord)[4], int h,
+                                            const C2<R>* tile, uint32_t s0) {
     const uint32_t V = (uint32_t)g.V;
-    if constexpr (HPI == 1) {
+    if constexpr (SPL == 2) {
+        const bool fwd = h == 0;
+        if constexpr (HPI == 1) {
+#pragma unroll 1
+            for (int mu = 0; mu < 4; ++mu) {
+                const uint32_t nb = nbr(g, s, coord, mu, fwd);
+                hop<R, RPT, TIL>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb, tile, s0);
+            }
+        } else {
+#pragma unroll 1
+            for (int mu = 0; mu < 4; mu += 2) {
+                const uint32_t n0 = nbr(g, s, coord, mu, fwd), n1 = nbr(g, s, coord, mu + 1, fwd);
+                hop<R, RPT, TIL>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, n0, fwd ? s : n0, tile, s0);
+                hop<R, RPT, TIL>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * 9 * V, V, n1,
+                                 fwd ? s : n1, tile, s0);
+            }
+        }
+    } else if constexpr (HPI == 1) {
 #pragma unroll 1
         for (int d = 0; d < 8; ++d) {
             const int mu = d >> 1;
             const bool fwd = (d & 1) == 0;
             const uint32_t nb = nbr(g, s, coord, mu, fwd);
-            hop<R, RPT>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb);
+            hop<R, RPT, TIL>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb, tile, s0);
         }
     } else {
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
-            hop<R, RPT>(mu, true, acc, psi, U + (size_t)mu * 9 * V, V, fw, s);
-            hop<R, RPT>(mu, false, acc, psi, U + (size_t)mu * 9 * V, V, bw, bw);
+            hop<R, RPT, TIL>(mu, true, acc, psi, U + (size_t)mu * 9 * V, V, fw, s, tile, s0);
+            hop<R, RPT, TIL>(mu, false, acc, psi, U + (size_t)mu * 9 * V, V, bw, bw, tile, s0);
         }
     }
 }
@@ -142,7 +182,7 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 
 // Body of the stencil for one block, `tile` being the block's position in
 // the (site tile, rhs group) space after the XCD-aware remap.
-template <typename R, int MODE, int HPI, int RPT, int ORD>
+template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL>
 __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>* __restrict__ out,
                                              const C2<R>* __restrict__ U, const Geom& g, R kappa,
                                              double zsr, double zsi,
@@ -167,53 +207,100 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
         any = any || on[r];
     }
     if (!any) return;
+    constexpr int NT = kBlock * SPL;
     const uint32_t V = (uint32_t)g.V;
-    const uint32_t s = (uint32_t)sb * kBlock + threadIdx.x;
+    const int h = SPL == 2 ? (int)(threadIdx.x & 1u) : 0;
+    const uint32_t s = (uint32_t)sb * kBlock + (SPL == 2 ? threadIdx.x >> 1 : threadIdx.x);
     const bool valid = s < V;
     // per rhs: <r, q> (re, im), ||q||^2 and ||r||^2 of this block's sites
     double dre[RPT], dim[RPT], dqq[RPT], drr[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) dre[r] = dim[r] = dqq[r] = drr[r] = 0.0;
-    if (valid) {
-        const C2<R>* psi[RPT];
+    const C2<R>* psi[RPT];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) psi[r] = in + (size_t)(n0 + (on[r] ? r : 0)) * 12 * V;
+    for (int r = 0; r < RPT; ++r) psi[r] = in + (size_t)(n0 + (on[r] ? r : 0)) * 12 * V;
+    cx<R> acc[RPT][4][3];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[r][a][c] = mk<R>(0, 0);
+    // TIL: the block's sites of every rhs staged in LDS once, read there by
+    // the site itself and by every neighbour that falls inside the block
+    static_assert(TIL == 0 || SPL == 1, "the LDS tile assumes one lane per site");
+    __shared__ C2<R> lt[TIL ? RPT * 12 * kBlock : 1];
+    const uint32_t s0 = (uint32_t)sb * kBlock;
+    if constexpr (TIL == 1) {
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+#pragma unroll
+                for (int comp = 0; comp < 12; ++comp) {
+                    const cx<R> v = ld<R>(psi[r], (uint32_t)comp * V + s);
+                    C2<R> w;
+                    w.x = v.re;
+                    w.y = v.im;
+                    lt[(r * 12 + comp) * kBlock + threadIdx.x] = w;
+                }
+        }
+        __syncthreads();
+    }
+    if (valid) {
         uint32_t rem = s;
         int coord[4];
         coord[0] = (int)(rem % (uint32_t)g.L[0]); rem /= (uint32_t)g.L[0];
         coord[1] = (int)(rem % (uint32_t)g.L[1]); rem /= (uint32_t)g.L[1];
         coord[2] = (int)(rem % (uint32_t)g.L[2]);
         coord[3] = (int)(rem / (uint32_t)g.L[2]);
-        cx<R> acc[RPT][4][3];
+        dslash_site<R, HPI, RPT, SPL, TIL>(acc, psi, U, g, s, coord, h, lt, s0);
+    }
+    if constexpr (SPL == 2) {
+        // lane h keeps spins 2h, 2h+1 (in acc[.][0..1]) and adds the partner's
+        // partial sums of them; both lanes of a pair share the site's validity
 #pragma unroll
         for (int r = 0; r < RPT; ++r)
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) acc[r][a][c] = mk<R>(0, 0);
-        dslash_site<R, HPI, RPT>(acc, psi, U, g, s, coord);
+                for (int c = 0; c < 3; ++c) {
+                    const cx<R> lo = acc[r][i][c], hi = acc[r][2 + i][c];
+                    const cx<R> snd = h ? lo : hi;
+                    const cx<R> got = mk<R>(__shfl_xor(snd.re, 1), __shfl_xor(snd.im, 1));
+                    acc[r][i][c] = (h ? hi : lo) + got;
+                }
+    }
+    if (valid) {
+        constexpr int NA = 4 / SPL;  // spins written by this lane: 2h + ai
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (!on[r]) continue;
             C2<R>* o = out + (size_t)(n0 + r) * 12 * V;
             const C2<R>* rd = (MODE == 1) ? rdot + (size_t)(n0 + r) * 12 * V : nullptr;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
+            for (int ai = 0; ai < NA; ++ai) {
+                const int a = SPL == 2 ? 2 * h + ai : ai;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const int comp = 3 * a + c;
-                    const cx<R> p = ld<R>(psi[r], (uint32_t)comp * V + s);
+                    const uint32_t comp = (uint32_t)(3 * a + c);
+                    cx<R> p;
+                    if constexpr (TIL == 1) {
+                        const C2<R> w = lt[(r * 12 + (int)comp) * kBlock + threadIdx.x];
+                        p = mk<R>(w.x, w.y);
+                    } else {
+                        p = ld<R>(psi[r], comp * V + s);
+                    }
                     // D psi = psi - kappa acc ; H = gamma5 D
-                    cx<R> hv = p - kappa * acc[r][a][c];
+                    cx<R> hv = p - kappa * acc[r][ai][c];
                     if (a >= 2) hv = -hv;
                     if constexpr (MODE == 0) {
-                        stc<R>(o, (uint32_t)comp * V + s, hv);
+                        stc<R>(o, comp * V + s, hv);
                     } else {
                         // q = zs p - H p
                         const R zr = (R)zsr, zi = (R)zsi;
                         cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
-                        stc<R>(o, (uint32_t)comp * V + s, q);
-                        const cx<R> rv = ld<R>(rd, (uint32_t)comp * V + s);
+                        stc<R>(o, comp * V + s, q);
+                        const cx<R> rv = ld<R>(rd, comp * V + s);
                         // <r, q> = sum conj(r) q, accumulated in FP64
                         dre[r] += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
                         dim[r] += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
@@ -225,21 +312,21 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
         }
     }
     if constexpr (MODE == 1) {
-        __shared__ double shd[kBlock / 64];
+        __shared__ double shd[NT / 64];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const double tr = block_sum<kBlock>(dre[r], shd);
-            const double ti_ = block_sum<kBlock>(dim[r], shd);
-            const double tq = block_sum<kBlock>(dqq[r], shd);
-            const double tn = block_sum<kBlock>(drr[r], shd);
+            const double tr = block_sum<NT>(dre[r], shd);
+            const double ti_ = block_sum<NT>(dim[r], shd);
+            const double tq = block_sum<NT>(dqq[r], shd);
+            const double tn = block_sum<NT>(drr[r], shd);
             if (on[r] && threadIdx.x == 0)
                 partial[(int64_t)(n0 + r) * nsb + sb] = make_double4(tr, ti_, tq, tn);
         }
     }
 }
 
-template <typename R, int MODE, int HPI, int RPT, int ORD>
-__global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
+template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL>
+__global__ __launch_bounds__(kBlock * SPL) void k_wilson(const C2<R>* __restrict__ in,
                                                    C2<R>* __restrict__ out,
                                                    const C2<R>* __restrict__ U, Geom g, R kappa,
                                                    double zsr, double zsi,
@@ -248,26 +335,26 @@ __global__ __launch_bounds__(kBlock) void k_wilson(const C2<R>* __restrict__ in,
                                                    const SrcState* __restrict__ stt,
                                                    ShiftDev sh, int k, int nsb, int nrhs) {
     const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
-    wilson_block<R, MODE, HPI, RPT, ORD>(in, out, U, g, kappa, zsr, zsi, rdot, partial, stt, sh,
+    wilson_block<R, MODE, HPI, RPT, ORD, SPL, TIL>(in, out, U, g, kappa, zsr, zsi, rdot, partial, stt, sh,
                                          k, nsb, nrhs, tile);
 }
 
 // K1 over a job table: q = z_s p - H p and <r_k, q> partials for every job of
 // a batch in one launch; the iteration index k is read from device memory so
 // a captured graph can be replayed for any k.
-template <typename R, int HPI, int RPT, int ORD>
-__global__ __launch_bounds__(kBlock) void k_wilson_jobs(const JobDesc* __restrict__ jobs, int njobs,
+template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL>
+__global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __restrict__ jobs, int njobs,
                                                         const int* __restrict__ kdev) {
     const int k = (int)uniform((uint32_t)*kdev);
     const unsigned gb = uniform(xcd_remap(blockIdx.x, gridDim.x));
     int j = 0;
-    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0) ++j;
-    const JobDesc& J = jobs[j];
     const int f = sizeof(R) == 4 ? 1 : 0;
-    wilson_block<R, 1, HPI, RPT, ORD>(static_cast<const C2<R>*>(J.p[f]), static_cast<C2<R>*>(J.q[f]),
+    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
+    const JobDesc& J = jobs[j];
+    wilson_block<R, 1, HPI, RPT, ORD, SPL, TIL>(static_cast<const C2<R>*>(J.p[f]), static_cast<C2<R>*>(J.q[f]),
                                       static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
                                       J.zs.y, job_rk<const C2<R>>(J, k, f), J.part_w, J.st, J.sh,
-                                      k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0);
+                                      k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0[f]);
 }
 
 int wilson_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
@@ -276,26 +363,41 @@ int wilson_grid_blocks(const Geom& g, int nrhs, int variant) {
     return wilson_blocks(g) * ((nrhs + rpt - 1) / rpt);
 }
 
+// Calls f(HPI, RPT, ORD, SPL, TIL) as integral constants for variant v =
+// 16 TIL + 8 (SPL - 1) + 4 ORD + 2 (RPT - 1) + (HPI - 1), v < 24 (the LDS
+// tile takes one lane per site); other values take variant 0.
+template <typename F>
+void with_variant(int v, F&& f) {
+    using std::integral_constant;
+    switch (v) {
+#define OVL_V(n)                                                                     \
+    case n:                                                                          \
+        f(integral_constant<int, ((n)&1) + 1>{}, integral_constant<int, (((n) >> 1) & 1) + 1>{}, \
+          integral_constant<int, ((n) >> 2) & 1>{}, integral_constant<int, (((n) >> 3) & 1) + 1>{}, \
+          integral_constant<int, ((n) >> 4) & 1>{});                                 \
+        break;
+        OVL_V(1) OVL_V(2) OVL_V(3) OVL_V(4) OVL_V(5) OVL_V(6) OVL_V(7)
+        OVL_V(8) OVL_V(9) OVL_V(10) OVL_V(11) OVL_V(12) OVL_V(13) OVL_V(14) OVL_V(15)
+        OVL_V(16) OVL_V(17) OVL_V(18) OVL_V(19) OVL_V(20) OVL_V(21) OVL_V(22) OVL_V(23)
+#undef OVL_V
+        default:
+            f(integral_constant<int, 1>{}, integral_constant<int, 1>{}, integral_constant<int, 0>{},
+              integral_constant<int, 1>{}, integral_constant<int, 0>{});
+    }
+}
+
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
                         int variant, hipStream_t s) {
-#define OVL_WJ(H, P, O) hipLaunchKernelGGL((k_wilson_jobs<R, H, P, O>), dim3(total_blocks), dim3(kBlock), 0, s, jobs, njobs, kdev)
-    switch (variant) {
-        case 1: OVL_WJ(2, 1, 0); break;
-        case 2: OVL_WJ(1, 2, 0); break;
-        case 3: OVL_WJ(2, 2, 0); break;
-        case 4: OVL_WJ(1, 1, 1); break;
-        case 5: OVL_WJ(2, 1, 1); break;
-        case 6: OVL_WJ(1, 2, 1); break;
-        case 7: OVL_WJ(2, 2, 1); break;
-        default: OVL_WJ(1, 1, 0); break;
-    }
-#undef OVL_WJ
+    with_variant(variant, [&](auto H, auto P, auto O, auto S, auto C) {
+        hipLaunchKernelGGL((k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value>),
+                           dim3(total_blocks), dim3(kBlock * S.value), 0, s, jobs, njobs, kdev);
+    });
 }
 template void launch_wilson_jobs<double>(const JobDesc*, int, const int*, int, int, hipStream_t);
 template void launch_wilson_jobs<float>(const JobDesc*, int, const int*, int, int, hipStream_t);
 
-template <typename R, int HPI, int RPT, int ORD>
+template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL>
 void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                      double kappa, double2 zs, const C2<R>* r, double4* partial,
                      const SrcState* stt, const ShiftDev& sh, int k, int nrhs, hipStream_t s) {
@@ -303,11 +405,11 @@ void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, cons
     const int ngrp = (nrhs + RPT - 1) / RPT;
     dim3 grid((unsigned)nsb * (unsigned)ngrp);
     if (mode == 0)
-        hipLaunchKernelGGL((k_wilson<R, 0, HPI, RPT, ORD>), grid, dim3(kBlock), 0, s, in, out, U, g,
-                           (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
+        hipLaunchKernelGGL((k_wilson<R, 0, HPI, RPT, ORD, SPL, TIL>), grid, dim3(kBlock * SPL), 0, s, in,
+                           out, U, g, (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
     else
-        hipLaunchKernelGGL((k_wilson<R, 1, HPI, RPT, ORD>), grid, dim3(kBlock), 0, s, in, out, U, g,
-                           (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
+        hipLaunchKernelGGL((k_wilson<R, 1, HPI, RPT, ORD, SPL, TIL>), grid, dim3(kBlock * SPL), 0, s, in,
+                           out, U, g, (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
 }
 
 template <typename R>
@@ -317,18 +419,10 @@ void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const 
                    int variant) {
     ShiftDev none{};
     const ShiftDev& shv = sh ? *sh : none;
-#define OVL_WV(H, P, O) launch_wilson_v<R, H, P, O>(mode, in, out, U, g, kappa, zs, r, partial, stt, shv, k, nrhs, s)
-    switch (variant) {
-        case 1: OVL_WV(2, 1, 0); break;
-        case 2: OVL_WV(1, 2, 0); break;
-        case 3: OVL_WV(2, 2, 0); break;
-        case 4: OVL_WV(1, 1, 1); break;
-        case 5: OVL_WV(2, 1, 1); break;
-        case 6: OVL_WV(1, 2, 1); break;
-        case 7: OVL_WV(2, 2, 1); break;
-        default: OVL_WV(1, 1, 0); break;
-    }
-#undef OVL_WV
+    with_variant(variant, [&](auto H, auto P, auto O, auto S, auto C) {
+        launch_wilson_v<R, H.value, P.value, O.value, S.value, C.value>(mode, in, out, U, g, kappa, zs, r,
+                                                               partial, stt, shv, k, nrhs, s);
+    });
 }
 template void launch_wilson<double>(int, const double2*, double2*, const double2*, const Geom&,
                                     double, double2, const double2*, double4*, const SrcState*,
