@@ -79,7 +79,9 @@ typedef struct {
     double  seconds;           /* wall time of the apply on the stream                       */
     int32_t stencil_variant64; /* stencil variant used in FP64 (autotuned, see ovl_bench_kernel) */
     int32_t stencil_variant32; /* ... in FP32, or -1                                        */
-    double  reserved[3];
+    double  max_true_rel_res;  /* max ||b - (z_j - H) x_j|| / ||b|| over the checked shifts, or
+                                  -1 when not checked (see ovl_set_residual_check)           */
+    double  reserved[2];
 } ovl_stats;
 
 /* Create a context for a Lx*Ly*Lz*Lt lattice on HIP device `device`.
@@ -120,6 +122,18 @@ int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* z_reim, const double* c
  * switch point (ignored for FP64; <= 0 picks 1e-4). */
 int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, int32_t maxiter,
                    double zseed_re, double zseed_im, double switch_res);
+
+/* Opt-in check of the recurrence's residual estimates (the stopping rule of
+ * sec. 3 uses ||r_k|| / |pi_k^j| in place of the true residual).  After each
+ * ovl_apply_sign / ovl_apply_dov, for the `nsample` shifts of each rhs with
+ * the largest final estimate, x_j is formed (stored by OVL_FORM_REFERENCE,
+ * rebuilt from the stored basis by OVL_FORM_BASIS) and
+ * ||b - (z_j - H_W) x_j|| / ||b|| is computed with one more stencil; the
+ * maximum goes to ovl_stats.max_true_rel_res.  The fused and two-pass forms
+ * keep no x_j and report -1.  The check synchronises the stream and costs one
+ * basis sum per checked shift.  nsample in [0, 64]; 0 (default) turns it off.
+ * Returns OVL_E_ARG for an out-of-range nsample. */
+int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample);
 
 /* out = H_W in for nrhs spinors (eq. (1): H_W = gamma5 D_W(-m0)).  out must
  * not alias in. */

@@ -72,10 +72,14 @@ void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_strid
 // d = a b + bm gamma5 s, psi = bm gamma5 d, partial[blk] = |d|^2 (one source, SoA)
 void launch_dov_psi(const double2* b, const double2* s, double2* psi, double a, double bm,
                     int64_t V, double* partial, int nblk, hipStream_t st);
-// Y[j] (+)= sum over one slot chunk of u_i^{j0+j} r_i, j < jn (one source)
+// Y[j] (+)= sum over one slot chunk of u_i^{j0+j} r_i, j < jn, for the source
+// whose slot elements start at element eoff (W already offset to that source)
 void launch_materialize(const char* chunk, size_t slot_bytes, int g0, int l1, int ksw,
                         const double2* W, int J, int j0, int jn, int K, double2* Y, int64_t n12,
-                        bool accumulate, hipStream_t s);
+                        int64_t eoff, bool accumulate, hipStream_t s);
+// partial[blk] = (|b - (z x - H x)|^2, |b|^2) per block over one source
+void launch_true_res(const double2* b, const double2* x, const double2* hx, double2 z,
+                     double2* partial, int nblk, int64_t n12, hipStream_t s);
 // per-link accumulation of sum_j c_j X_j^dag dH Y_j; on the last chunk writes
 // the complex gradient (kind 1) or the traceless hermitian force (kind 0)
 void launch_force(const double2* X, const double2* Y, const double2* c, int jn, const Geom& g,

@@ -675,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const char* __restrict__
                                                         int ksw, const double2* __restrict__ W,
                                                         int J, int j0, int jn, int K,
                                                         double2* __restrict__ Y, int64_t n12,
-                                                        int accumulate) {
+                                                        int64_t eoff, int accumulate) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n12) return;
     double re[JG], im[JG];
@@ -687,11 +687,11 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const char* __restrict__
         const char* slot = chunk + (size_t)l * slot_bytes;
         double vr, vi;
         if (i < ksw) {
-            const double2 v = reinterpret_cast<const double2*>(slot)[e];
+            const double2 v = reinterpret_cast<const double2*>(slot)[eoff + e];
             vr = v.x;
             vi = v.y;
         } else {
-            const float2 v = reinterpret_cast<const float2*>(slot)[e];
+            const float2 v = reinterpret_cast<const float2*>(slot)[eoff + e];
             vr = v.x;
             vi = v.y;
         }
@@ -722,14 +722,38 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const char* __restrict__
 constexpr int kMatGroup = 8;
 void launch_materialize(const char* chunk, size_t slot_bytes, int g0, int l1, int ksw,
                         const double2* W, int J, int j0, int jn, int K, double2* Y, int64_t n12,
-                        bool accumulate, hipStream_t s) {
+                        int64_t eoff, bool accumulate, hipStream_t s) {
     dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock));
     for (int q0 = 0; q0 < jn; q0 += kMatGroup) {
         const int m = jn - q0 < kMatGroup ? jn - q0 : kMatGroup;
         hipLaunchKernelGGL(k_materialize<kMatGroup>, grid, dim3(kBlock), 0, s, chunk, slot_bytes,
-                           g0, l1, ksw, W, J, j0 + q0, m, K, Y + (size_t)q0 * n12, n12,
+                           g0, l1, ksw, W, J, j0 + q0, m, K, Y + (size_t)q0 * n12, n12, eoff,
                            (int)accumulate);
     }
+}
+
+// t = b - (z x - H x) over one source; partial[blk] = (|t|^2, |b|^2) of the block
+__global__ __launch_bounds__(kBlock) void k_true_res(const double2* __restrict__ b,
+                                                     const double2* __restrict__ x,
+                                                     const double2* __restrict__ hx, double2 z,
+                                                     double2* __restrict__ partial, int64_t n12) {
+    double tt = 0.0, bb = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
+        const double2 bv = b[e], xv = x[e], hv = hx[e];
+        const double tr = bv.x - (z.x * xv.x - z.y * xv.y - hv.x);
+        const double ti = bv.y - (z.x * xv.y + z.y * xv.x - hv.y);
+        tt += tr * tr + ti * ti;
+        bb += bv.x * bv.x + bv.y * bv.y;
+    }
+    __shared__ double sh[kBlock / 64];
+    tt = block_sum<kBlock>(tt, sh);
+    bb = block_sum<kBlock>(bb, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(tt, bb);
+}
+void launch_true_res(const double2* b, const double2* x, const double2* hx, double2 z,
+                     double2* partial, int nblk, int64_t n12, hipStream_t s) {
+    hipLaunchKernelGGL(k_true_res, dim3(nblk), dim3(kBlock), 0, s, b, x, hx, z, partial, n12);
 }
 
 // (M v) for M = gamma5 (1 -+ gamma_mu) (sg = -1: 1 - gamma, +1: 1 + gamma):

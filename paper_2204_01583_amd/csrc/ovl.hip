@@ -70,7 +70,8 @@ struct ovl_ctx {
     DBuf part_w, part_b, state, shifts, lists, nodes_dev, hist, W, h;
     SrcState* host_state = nullptr;  // pinned mirror
     int host_state_n = 0;
-    DBuf bench_a, bench_b, bench_c, tune_state;
+    DBuf bench_a, bench_b, bench_c, tune_state, chk;
+    int check_n = 0;  // shifts per source whose true residual is checked after a solve
     DBuf fY, fX, fpsi, facc, fc, fpart;  // force work space
     DBuf slot_table;                       // basis form: device table of slot-chunk bases
     // solve stream (graphs cannot be captured on the legacy null stream) and handoff events
@@ -257,7 +258,7 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
                     &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
                     &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_b,
                     &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
-                    &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->bench_c, &ctx->tune_state, &ctx->fY, &ctx->fX, &ctx->fpsi,
+                    &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->bench_c, &ctx->tune_state, &ctx->chk, &ctx->fY, &ctx->fX, &ctx->fpsi,
                     &ctx->facc, &ctx->fc, &ctx->fpart, &ctx->slot_table, &ctx->jobs_dev};
     for (DBuf* b : bufs) b->release();
     for (DBuf& b : ctx->slot_chunks) b.release();
@@ -1195,6 +1196,7 @@ static int solve_batch(Batch& B) {
         L.seconds = ms * 1e-3;
         L.stencil_variant64 = B.variant64;
         L.stencil_variant32 = mixed ? B.variant32 : -1;
+        L.max_true_rel_res = -1.0;
         if (status < 0) fail(c, status, "solver stopped: %s", ovl_status_string(status));
         if (status == OVL_NOT_CONVERGED)
             fail(c, status, "maxiter=%d reached with %d shifts above tol (max est. res %.3e)",
@@ -1210,6 +1212,75 @@ static int solve(ovl_ctx* ctx, Work& w) {
     return solve_batch(B);
 }
 
+static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y, int n, int K);
+
+// True residuals ||b - (z_j - H) x_j|| / ||b|| of the last solve for the
+// ctx->check_n shifts of each source with the largest final residual
+// estimates (ties: lower j).  x_j is stored by the reference form and
+// rebuilt from the stored basis by the basis form; the fused and two-pass
+// forms keep neither, and report -1.  Diagnostic: synchronous.
+static int true_residuals(ovl_ctx* ctx, const Work& w) {
+    ctx->last.max_true_rel_res = -1.0;
+    if (ctx->check_n <= 0 || (ctx->form != OVL_FORM_BASIS && ctx->form != OVL_FORM_REFERENCE))
+        return OVL_OK;
+    hipStream_t s = ctx->stream;
+    const int J = w.J;
+    const int64_t N = w.N;
+    const int nblk = 256;
+    std::vector<double> est((size_t)w.nsrc * J);
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    HIPCHK(ctx, hipMemcpy(est.data(), w.sh.res, est.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(ctx, ctx->chk.ensure((size_t)2 * N * sizeof(double2) + nblk * sizeof(double2)));
+    double2* X = ctx->chk.as<double2>();
+    double2* HX = X + N;
+    double2* part = HX + N;
+    const int var = stencil_variant(ctx, 1, 0);
+    const SrcState* hs = reinterpret_cast<const SrcState*>(ctx->host_state);
+    std::vector<double2> hp(nblk);
+    double worst = 0.0;
+    for (int n = 0; n < w.nsrc; ++n) {
+        std::vector<int> order(J);
+        for (int j = 0; j < J; ++j) order[j] = j;
+        const double* e = est.data() + (size_t)n * J;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e[a] > e[b]; });
+        const int m = std::min(ctx->check_n, J);
+        for (int q = 0; q < m; ++q) {
+            const int j = order[q];
+            const double2* x;
+            if (ctx->form == OVL_FORM_REFERENCE) {
+                x = w.xj + ((size_t)n * J + j) * N;
+            } else {
+                const int rc = materialize(ctx, w, j, 1, X, n, hs[n].iter);
+                if (rc) return rc;
+                x = X;
+            }
+            launch_wilson<double>(0, x, HX, ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0),
+                                  make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, 1, s,
+                                  var);
+            launch_true_res(w.b64 + (size_t)n * N, x, HX, ctx->z[j], part, nblk, N, s);
+            HIPCHK(ctx, hipGetLastError());
+            HIPCHK(ctx, hipMemcpyAsync(hp.data(), part, nblk * sizeof(double2),
+                                       hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            double tt = 0.0, bb = 0.0;
+            for (int b = 0; b < nblk; ++b) {
+                tt += hp[b].x;
+                bb += hp[b].y;
+            }
+            if (bb > 0.0) worst = std::max(worst, std::sqrt(tt / bb));
+        }
+    }
+    ctx->last.max_true_rel_res = worst;
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample) {
+    if (!ctx) return OVL_E_ARG;
+    if (nsample < 0 || nsample > 64) return fail(ctx, OVL_E_ARG, "nsample must be in [0, 64]");
+    ctx->check_n = nsample;
+    return OVL_OK;
+}
+
 static int apply_common(ovl_ctx* ctx, const void* in, void* out, int nrhs, ovl_stats* st,
                         bool dov) {
     if (!ctx) return OVL_E_ARG;
@@ -1223,6 +1294,8 @@ static int apply_common(ovl_ctx* ctx, const void* in, void* out, int nrhs, ovl_s
     HIPCHK(ctx, hipGetLastError());
     rc = solve(ctx, w);
     if (rc < 0) return rc;
+    const int rcc = true_residuals(ctx, w);
+    if (rcc < 0) return rcc;
     if (dov)
         launch_unpack_dov(w.s64, static_cast<const double2*>(in), static_cast<double2*>(out),
                           0.5 * (1.0 + ctx->mq), 0.5 * (1.0 - ctx->mq), ctx->g.V, nrhs,
@@ -1245,14 +1318,18 @@ extern "C" int ovl_apply_dov(ovl_ctx* ctx, const void* in, void* out, int32_t nr
     return apply_common(ctx, in, out, nrhs, st, true);
 }
 
-// Y[j] = sum_i u_i^j r_i for shifts [j0, j0+jn) of the last basis solve (one source)
-static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y) {
-    const int K = w.K;
+// Y[j] = sum_{i < K} u_i^j r_i for shifts [j0, j0+jn) of source n of the last
+// basis solve, K being that source's iteration count
+static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y, int n = 0,
+                       int K = -1) {
+    if (K < 0) K = w.K;
     const int ksw = w.k_switch < 0 ? K + 1 : w.k_switch;
+    const double2* Wn = w.W + (size_t)n * (w.maxk + 1) * w.J;
     bool acc = false;
     for (int c0 = 0; c0 < K; c0 += kSlotChunk) {
-        launch_materialize(w.chunks[c0 / kSlotChunk], w.slot_bytes, c0, kSlotChunk, ksw, w.W, w.J,
-                           j0, jn, K, Y, w.N, acc, ctx->stream);  // after solve's handoff
+        launch_materialize(w.chunks[c0 / kSlotChunk], w.slot_bytes, c0, kSlotChunk, ksw, Wn, w.J,
+                           j0, jn, K, Y, w.N, (int64_t)n * w.N, acc,
+                           ctx->stream);  // after solve's handoff
         acc = true;
     }
     if (!acc) HIPCHK(ctx, hipMemsetAsync(Y, 0, (size_t)jn * w.N * sizeof(double2), ctx->stream));

@@ -27,7 +27,8 @@ BENCH_STENCIL64, BENCH_STENCIL32 = 0, 1
 # every function declared in include/ovl.h
 EXPORTS = [
     "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
-    "ovl_set_contour", "ovl_set_nodes", "ovl_set_solver", "ovl_apply_hw", "ovl_apply_sign",
+    "ovl_set_contour", "ovl_set_nodes", "ovl_set_solver", "ovl_set_residual_check",
+    "ovl_apply_hw", "ovl_apply_sign",
     "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
     "ovl_bench_kernel", "ovl_set_profiling", "ovl_get_profile", "ovl_status_string",
     "ovl_last_error",
@@ -46,7 +47,8 @@ class Stats(ctypes.Structure):
         ("seconds", ctypes.c_double),
         ("stencil_variant64", ctypes.c_int32),
         ("stencil_variant32", ctypes.c_int32),
-        ("reserved", ctypes.c_double * 3),
+        ("max_true_rel_res", ctypes.c_double),
+        ("reserved", ctypes.c_double * 2),
     ]
 
     def as_dict(self):
@@ -81,6 +83,7 @@ def load():
         "ovl_set_contour": ([P, I, D, D, D], I),
         "ovl_set_nodes": ([P, I, ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "ovl_set_solver": ([P, I, I, D, I, D, D, D], I),
+        "ovl_set_residual_check": ([P, I], I),
         "ovl_apply_hw": ([P, P, P, I], I),
         "ovl_apply_sign": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "ovl_apply_dov": ([P, P, P, I, ctypes.POINTER(Stats)], I),
@@ -190,6 +193,11 @@ class Context:
                                          int(maxiter), float(complex(zseed).real),
                                          float(complex(zseed).imag), float(switch_res)),
                  "ovl_set_solver")
+
+    def set_residual_check(self, nsample):
+        """After each apply, check the true residual of the `nsample` shifts per
+        rhs with the largest residual estimates (Stats.max_true_rel_res)."""
+        self._rc(self.lib.ovl_set_residual_check(self._h, int(nsample)), "ovl_set_residual_check")
 
     # -- operators ------------------------------------------------------------
     def _spinor_in(self, x):

@@ -211,6 +211,53 @@ def test_deterministic():
     ctx.close()
 
 
+@pytest.mark.parametrize("form", [0, 2])
+def test_true_residual_single_node(form):
+    """With one node and weight 1 the output is x = (z - H)^-1 b itself, so
+    the true residual the library reports can be recomputed here from the
+    oracle's H; loose tolerance so the residual is far above rounding."""
+    dims = (4, 4, 4, 4)
+    U = gauge(dims, 0.3, 0)
+    ctx = make_ctx(dims, U, form=form, tol=1e-6)
+    z = 0.3 + 0.4j
+    ctx.set_nodes([z], [1.0])
+    ctx.set_residual_check(1)
+    b = si.gaussian_sources(dims, 2, first_seed=21)
+    out, st = ctx.apply_sign(to_dev(b))
+    x = out.cpu().numpy()
+    H = oracle_H(dims, 0.3, 0, 1.4)
+    mine = 0.0
+    for n in range(2):
+        bv, xv = b[n].ravel(), x[n].ravel()
+        mine = max(mine, np.linalg.norm(bv - (z * xv - H @ xv)) / np.linalg.norm(bv))
+    assert 1e-9 < mine < 1e-5, mine
+    assert abs(st.max_true_rel_res - mine) <= 1e-6 * mine, (st.max_true_rel_res, mine)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,form", [(0, 2), (0, 0), (1, 2), (0, 1)])
+def test_true_residual_contour(precision, form):
+    """On the full contour the recurrence's residual estimates track the true
+    residuals of the shifts it reports worst (FP64), and the mixed path stays
+    within a small factor of the tolerance; forms that keep no x_j report -1."""
+    dims = (4, 4, 4, 8)
+    U = gauge(dims, 0.3, 3)
+    tol = 1e-10
+    ctx = make_ctx(dims, U, nq=32, precision=precision, form=form, tol=tol)
+    ctx.set_residual_check(3)
+    b = si.gaussian_sources(dims, 2, first_seed=31)
+    _, st = ctx.apply_sign(to_dev(b))
+    print("true", st.max_true_rel_res, "est", st.max_est_rel_res, "iters", st.iterations)
+    if form == 1:
+        assert st.max_true_rel_res == -1.0
+    elif precision == 0:
+        assert 0.5 * st.max_est_rel_res < st.max_true_rel_res < 2.0 * st.max_est_rel_res + 1e-14
+        assert st.max_true_rel_res < 2 * tol
+    else:
+        assert 0.0 < st.max_true_rel_res < 100 * tol
+    ctx.close()
+
+
 @pytest.mark.parametrize("variant", list(range(24)))
 def test_stencil_variants(variant, monkeypatch):
     """Every stencil variant the autotuner may pick gives the oracle's H_W,
