@@ -43,11 +43,11 @@ int wilson_grid_blocks(const Geom& g, int nrhs, int variant);
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
                         int variant, hipStream_t s);
-// K2: seed and shift scalars, shift bookkeeping, r update and p update or sweep
+// K2: seed and shift scalars, shift bookkeeping, r update and p update or
+// sweep; reads the iteration index from kread and writes its successor to kwrite
 template <typename R>
-void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
-                             int form, int maxJ, hipStream_t s);
-void launch_advance(int* kdev, hipStream_t s);
+void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
+                             int vec_blocks_total, int form, int maxJ, hipStream_t s);
 // two-pass form, second pass: s = h_0 b
 void launch_s_init(const double2* b, const double2* h, int maxk, double2* s, int64_t n12, int nsrc,
                    hipStream_t st);

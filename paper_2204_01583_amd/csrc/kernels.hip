@@ -406,35 +406,35 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
     }
 }
 
+// The iteration counter lives in two device slots: iteration k reads slot
+// kread and the update kernel's first lane publishes k + 1 in the other slot,
+// kwrite, which no block of the same launch reads.
 template <typename R, int KIND>
 __global__ __launch_bounds__(kBlock) void k_update_jobs(const JobDesc* __restrict__ jobs, int njobs,
-                                                        const int* __restrict__ kdev) {
-    const int k = (int)uniform((uint32_t)*kdev);
+                                                        const int* __restrict__ kread,
+                                                        int* __restrict__ kwrite) {
+    const int k = (int)uniform((uint32_t)*kread);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *kwrite = k + 1;
     const VecBlock v = vec_block(jobs, njobs);
     update_block<R, KIND>(jobs[v.j], v.n, v.bx, k);
 }
-// the iteration counter of a batch, advanced once per seed iteration
-__global__ void k_advance(int* kdev) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *kdev += 1;
-}
 
 template <typename R>
-void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kdev, int vec_blocks_total,
-                             int form, int maxJ, hipStream_t s) {
+void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
+                             int vec_blocks_total, int form, int maxJ, hipStream_t s) {
     const dim3 grid(vec_blocks_total), blk(kBlock);
     const size_t lds = (size_t)maxJ * (3 * sizeof(double2) + sizeof(int));
     if (form == OVL_FORM_BASIS || form == OVL_FORM_TWOPASS)
-        hipLaunchKernelGGL((k_update_jobs<R, 0>), grid, blk, 0, s, jobs, njobs, kdev);
+        hipLaunchKernelGGL((k_update_jobs<R, 0>), grid, blk, 0, s, jobs, njobs, kread, kwrite);
     else if (form == OVL_FORM_FUSED)
-        hipLaunchKernelGGL((k_update_jobs<R, 1>), grid, blk, lds, s, jobs, njobs, kdev);
+        hipLaunchKernelGGL((k_update_jobs<R, 1>), grid, blk, lds, s, jobs, njobs, kread, kwrite);
     else
-        hipLaunchKernelGGL((k_update_jobs<R, 2>), grid, blk, lds, s, jobs, njobs, kdev);
+        hipLaunchKernelGGL((k_update_jobs<R, 2>), grid, blk, lds, s, jobs, njobs, kread, kwrite);
 }
-template void launch_iteration_update<double>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
-template void launch_iteration_update<float>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
-void launch_advance(int* kdev, hipStream_t s) {
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, kdev);
-}
+template void launch_iteration_update<double>(const JobDesc*, int, const int*, int*, int, int, int,
+                                              hipStream_t);
+template void launch_iteration_update<float>(const JobDesc*, int, const int*, int*, int, int, int,
+                                             hipStream_t);
 
 // two-pass form, second pass: s = h_0 b (r_0 = b)
 __global__ __launch_bounds__(kBlock) void k_s_init(const double2* __restrict__ b,

@@ -818,6 +818,8 @@ bool graphs_enabled(const ovl_ctx* ctx) {
 }
 
 constexpr int kChunk = 16;  // seed iterations per captured graph / per convergence poll
+// iteration i of a chunk reads the counter slot i & 1, so a chunk starts at slot 0
+static_assert(kChunk % 2 == 0, "chunks must hold an even number of iterations");
 
 struct Batch {
     std::vector<ovl_ctx*> ctx;
@@ -889,17 +891,17 @@ void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool pr
         (void)k_host;
         {
             ProfScope ps(lead, s, prof ? 0 + c32 : -1, sten_b);
-            launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.sten_total[c32], var, s);
+            launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
+                                  B.sten_total[c32], var, s);
         }
         {
             // K2: r update (r, q read, r written) plus p update (p read and
             // written) or the sweep
             ProfScope ps(lead, s, prof ? (sweep ? 4 + c32 : 2 + c32) : -1,
                          sweep ? vec_b + sweep_b : 5.0 / 3.0 * vec_b);
-            launch_iteration_update<R>(B.desc_dev, (int)B.desc.size(), B.kdev, B.vec_total,
-                                       B.form, B.maxJ, s);
+            launch_iteration_update<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
+                                       B.kdev + ((i + 1) & 1), B.vec_total, B.form, B.maxJ, s);
         }
-        launch_advance(B.kdev, s);
     }
 }
 
@@ -1062,7 +1064,7 @@ static int solve_batch(Batch& B) {
     }
     HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(), B.desc.size() * sizeof(JobDesc),
                                 hipMemcpyHostToDevice, s));
-    HIPCHK(lead, hipMemsetAsync(B.kdev, 0, sizeof(int), s));  // outside any captured graph
+    HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));  // outside any captured graph
 
     bool low = false;
     int k_switch = -1, k_host = 0, status = OVL_OK;
@@ -1149,7 +1151,7 @@ static int solve_batch(Batch& B) {
             }
             HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(), B.desc.size() * sizeof(JobDesc),
                                         hipMemcpyHostToDevice, s));
-            HIPCHK(lead, hipMemsetAsync(B.kdev, 0, sizeof(int), s));
+            HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));
             bool low2 = false;
             for (int k2 = 0; k2 < k_run; k2 += kChunk) {
                 if (mixed && !low2 && k2 == k_switch) {
