@@ -347,7 +347,41 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
     C2<R>* ro = job_rk<C2<R>>(J, k + 1, f) + (size_t)n * n12;
     const C2<R>* qq = static_cast<const C2<R>*>(J.q[f]) + (size_t)n * n12;
     C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
-    if constexpr (!SWEEP) {
+    if constexpr (!SWEEP && sizeof(R) == 4) {
+        // FP32: two components per lane in one 16-byte access of each array
+        // (every vector starts 16-byte aligned and 12V is even)
+        const bool acc2 = J.h != nullptr;
+        const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
+        double2* sacc = J.s64 + (size_t)n * n12;
+        const float4* ri4 = reinterpret_cast<const float4*>(ri);
+        const float4* qq4 = reinterpret_cast<const float4*>(qq);
+        float4* ro4 = reinterpret_cast<float4*>(ro);
+        float4* pp4 = reinterpret_cast<float4*>(pp);
+        const int64_t n2 = n12 / 2;
+        for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n2; e += (int64_t)J.nbe * kBlock) {
+            const float4 r = ri4[e], qv = qq4[e], po = pp4[e];
+            float4 rn, pn;
+            rn.x = r.x - ((float)ar * qv.x - (float)ai * qv.y);
+            rn.y = r.y - ((float)ar * qv.y + (float)ai * qv.x);
+            rn.z = r.z - ((float)ar * qv.z - (float)ai * qv.w);
+            rn.w = r.w - ((float)ar * qv.w + (float)ai * qv.z);
+            pn.x = rn.x + (float)br * po.x - (float)bi * po.y;
+            pn.y = rn.y + (float)br * po.y + (float)bi * po.x;
+            pn.z = rn.z + (float)br * po.z - (float)bi * po.w;
+            pn.w = rn.w + (float)br * po.w + (float)bi * po.z;
+            ro4[e] = rn;
+            pp4[e] = pn;
+            if (acc2) {
+                double2 s0 = sacc[2 * e], s1 = sacc[2 * e + 1];
+                s0.x += hk.x * (double)rn.x - hk.y * (double)rn.y;
+                s0.y += hk.x * (double)rn.y + hk.y * (double)rn.x;
+                s1.x += hk.x * (double)rn.z - hk.y * (double)rn.w;
+                s1.y += hk.x * (double)rn.w + hk.y * (double)rn.z;
+                sacc[2 * e] = s0;
+                sacc[2 * e + 1] = s1;
+            }
+        }
+    } else if constexpr (!SWEEP) {
         const bool acc2 = J.h != nullptr;
         const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
         double2* sacc = J.s64 + (size_t)n * n12;
