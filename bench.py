@@ -140,6 +140,53 @@ def batched_uneven(torch, ovl):
             "err_vs_own_fp64_solve": errs}
 
 
+def paper_workload(torch, ovl):
+    """The workload of the paper's Table I and Fig. 4 on seeded stand-in fields:
+    8^4, m0 = 1, the paper's ellipse (alpha 0.1, rho 1.1999, gamma +-1.2),
+    seed 1 + 0.05i, one Gaussian vector, FP64 basis form at tol 1e-14, for N
+    points per contour in {100, 250, 500, 1000}; sigma = |s^dag s - y^dag y|
+    / y^dag y averaged over three fields, and the time per sgn(H_W) y."""
+    import numpy as np
+    import seeded_inputs as si
+    dims = (8, 8, 8, 8)
+    y = si.gaussian_sources(dims, 1, first_seed=1000)
+    yd = torch.from_numpy(np.ascontiguousarray(y)).to("cuda:0")
+    yy = float(np.vdot(y, y).real)
+    out = {}
+    for nq in (100, 250, 500, 1000):
+        sig, secs, iters = [], [], []
+        for seed in range(3):
+            c = ovl.Context(dims, device=0)
+            c.set_gauge(torch.from_numpy(si.gauge_field(dims, 0.3, seed)).to("cuda:0"))
+            c.set_masses(1.0, 0.0)
+            c.set_contour(nq, 1.2, 1.1999, 0.1)
+            c.set_solver(ovl.PREC_FP64, ovl.FORM_BASIS, tol=1e-14, maxiter=4000)
+            c.apply_sign(yd)                      # warm-up (allocation, tuning)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, st = c.apply_sign(yd)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            ss = float((s.abs() ** 2).sum())
+            sig.append(abs(ss - yy) / yy)
+            iters.append(st.iterations)
+            c.close()
+        out[f"N{nq}"] = {"sigma_mean": float(np.mean(sig)), "sigma_per_field": sig,
+                         "seconds_per_apply": round(float(np.mean(secs)), 5),
+                         "iterations": iters, "shifts": 2 * nq}
+        log(f"paper workload N={nq}: sigma {np.mean(sig):.2e}, {np.mean(secs)*1e3:.1f} ms, "
+            f"iters {iters}")
+    t1000 = out["N1000"]["seconds_per_apply"]
+    out["paper_table1_context"] = {
+        "note": "the paper's own times for one sgn(H_W) y at N = 1000 on 8^4 (30 quenched "
+                "beta = 5.7 fields, Xeon Gold 6242R cores, FP64): 959 s on 1 core, 62.3 s on "
+                "120 cores; other hardware and fields, context only",
+        "speedup_vs_1_core": round(959.0 / t1000, 1),
+        "speedup_vs_120_cores": round(62.3 / t1000, 1),
+    }
+    return out
+
+
 def cpu_baseline(U, B, nsample):
     """The FP64 oracle (independent GMRES solve per node) on a stratified sample
     of the 256 shifted systems of source 0, one node per host core."""
@@ -178,6 +225,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-lattice run")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's 8^4 sigma / timing workload")
     ap.add_argument("--only-steps", action="store_true",
                     help="only the warm-up and timed steps (for profiler runs)")
     ap.add_argument("--cpu-nodes", type=int, default=16)
@@ -303,6 +352,11 @@ def main():
         "mixed_basis_speedup_vs_fp64_fused": round(forms["fp64_fused"] / t_mixed, 3),
         "mixed_basis_speedup_vs_fp64_reference": round(forms["fp64_reference"] / t_mixed, 3),
     }
+
+    # ---- the paper's own workload (Table I, Fig. 4) on stand-in fields
+    if not args.no_paper:
+        log("paper workload (8^4, ellipse, N = 100 .. 1000)")
+        rec["paper_workload"] = paper_workload(torch, ovl)
 
     # ---- the stencil on a batch far larger than the 256 MB last-level cache
     sten = {}

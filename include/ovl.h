@@ -107,13 +107,15 @@ int ovl_set_masses(ovl_ctx* ctx, double m0, double mq);
 /* Nodes and weights of eq. (7) on both ellipses: theta_j = 2 pi (j-1/2)/nq,
  * z_j = +-gamma + rho (cos theta_j + i alpha sin theta_j),
  * c_j = +-rho (alpha cos theta_j + i sin theta_j)/nq.  nq counts the points
- * of ONE contour and must be even (an odd nq puts a node on the real axis).
- * The paper's contour: alpha = 0.1, rho = 1.1999, gamma = 1.2. */
+ * of ONE contour and must be even (an odd nq puts a node on the real axis);
+ * 2*nq <= 2048, and the fused and reference forms take at most 1024 shifts
+ * (OVL_E_ARG at apply time).  The paper's contour: alpha = 0.1,
+ * rho = 1.1999, gamma = 1.2. */
 int ovl_set_contour(ovl_ctx* ctx, int32_t nq, double gamma, double rho, double alpha);
 
 /* General rational function s = sum_j c_j (z_j - H_W)^-1 b: n nodes given as
- * interleaved host arrays z_reim[2n], c_reim[2n].  Every Im z_j must be
- * nonzero.  Replaces any contour set before. */
+ * interleaved host arrays z_reim[2n], c_reim[2n], 1 <= n <= 2048.  Every
+ * Im z_j must be nonzero.  Replaces any contour set before. */
 int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* z_reim, const double* c_reim);
 
 /* precision: OVL_PREC_*; form: OVL_FORM_*; tol: shift j stops when its
@@ -123,8 +125,8 @@ int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* z_reim, const double* c
 int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, int32_t maxiter,
                    double zseed_re, double zseed_im, double switch_res);
 
-/* Opt-in check of the recurrence's residual estimates (the stopping rule of
- * sec. 3 uses ||r_k|| / |pi_k^j| in place of the true residual).  After each
+/* Opt-in check of the recurrence's residual estimates (shift j stops on the
+ * estimate ||r_k|| / |pi_k^j|, not on its true residual).  After each
  * ovl_apply_sign / ovl_apply_dov, for the `nsample` shifts of each rhs with
  * the largest final estimate, x_j is formed (stored by OVL_FORM_REFERENCE,
  * rebuilt from the stored basis by OVL_FORM_BASIS) and

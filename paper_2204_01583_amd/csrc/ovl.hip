@@ -660,6 +660,9 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     const int64_t N = n12(ctx);
     const bool mixed = ctx->precision == OVL_PREC_MIXED;
     const int form = ctx->form;
+    if ((form == OVL_FORM_FUSED || form == OVL_FORM_REFERENCE) && J > kMaxSweepShifts)
+        return fail(ctx, OVL_E_ARG, "the fused and reference forms take at most %d shifts (have %d)",
+                    kMaxSweepShifts, J);
     w.nsrc = nsrc;
     w.J = J;
     w.N = N;

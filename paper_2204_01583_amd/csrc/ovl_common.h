@@ -75,7 +75,8 @@ struct Geom {
 };
 
 constexpr int kBlock = 256;           // threads per block of the site kernels
-constexpr int kMaxShifts = 1024;      // shifted systems per apply
+constexpr int kMaxShifts = 2048;      // shifted systems per apply
+constexpr int kMaxSweepShifts = 1024; // ... for the sweep forms (LDS list of the active shifts)
 
 constexpr int kMaxSlices = kMaxShifts / 256;  // 256-shift slices
 

@@ -197,6 +197,15 @@ def test_error_paths():
     z0 = b * 0
     s, st = ctx.apply_sign(z0)
     assert float(s.abs().max()) == 0.0
+    # shift limits: 2048 in all, 1024 for the sweep forms
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.set_contour(1026, *CIRCLE)
+    assert e.value.status == ovl.E_ARG
+    ctx.set_contour(600, *CIRCLE)
+    ctx.set_solver(0, 1, tol=1e-12, maxiter=500)
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.apply_sign(b)
+    assert e.value.status == ovl.E_ARG
     ctx.close()
 
 
