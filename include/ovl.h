@@ -113,6 +113,15 @@ int ovl_set_masses(ovl_ctx* ctx, double m0, double mq);
  * rho = 1.1999, gamma = 1.2. */
 int ovl_set_contour(ovl_ctx* ctx, int32_t nq, double gamma, double rho, double alpha);
 
+/* One contour only: sgn(H_W) = P_+ - P_- and P_+ + P_- = 1 when H_W has no
+ * exact zero mode, so sgn(H_W) b ~ 2 P_{Gamma+} b - b from the nq nodes of
+ * Gamma_+ (eq. (7), the same parametrisation as ovl_set_contour) with twice
+ * their weights: half the shifted systems.  Opt-in: an exact zero mode of
+ * H_W gets 2 F_+(0) - 1 (F_+ the Gamma_+ filter; towards -1 as nq grows, the
+ * faster the further 0 lies outside Gamma_+) where the sign function and
+ * the two-contour form give 0.  nq even, 2 <= nq <= 2048. */
+int ovl_set_contour_single(ovl_ctx* ctx, int32_t nq, double gamma, double rho, double alpha);
+
 /* General rational function s = sum_j c_j (z_j - H_W)^-1 b: n nodes given as
  * interleaved host arrays z_reim[2n], c_reim[2n], 1 <= n <= 2048.  Every
  * Im z_j must be nonzero.  Replaces any contour set before. */

@@ -29,6 +29,15 @@ def nodes(nq, gamma, rho, alpha):
     return z, c
 
 
+def nodes_single(nq, gamma, rho, alpha):
+    """(z, c, c0) of the one-contour form sgn(H) = 2 P_+ - 1, which holds when
+    H has no exact zero mode (P_+ + P_- = 1, eq. (3)): the Gamma_+ nodes
+    with twice their weights, and the constant term c0 = -1."""
+    z, c = nodes(nq, gamma, rho, alpha)
+    nq = int(nq)
+    return z[:nq], 2.0 * c[:nq], -1.0
+
+
 def scalar_filter(lam, z, c):
     """sum_j c_j / (z_j - lam): the scalar function the quadrature applies
     to each eigenvalue lam of H_W (the resolvent expansion under eq. (4))."""

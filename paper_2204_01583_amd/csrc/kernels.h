@@ -17,6 +17,8 @@ void launch_unpack_dov(const double2* s_int, const double2* b_ext, double2* out_
 void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, const Geom& g,
                        const int bc[4], hipStream_t s);
 void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t s);
+// y += a x (complex vectors, real a)
+void launch_axpy(double2* y, const double2* x, double a, int64_t n, hipStream_t s);
 
 // ---- Wilson stencil --------------------------------------------------------
 // out = H_W in                                               (mode 0)

@@ -117,6 +117,24 @@ void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, const Geom
     hipLaunchKernelGGL(k_pack_gauge, grid, dim3(kBlock), 0, s, ext, U64, U32, g, bc[0], bc[1],
                        bc[2], bc[3]);
 }
+// y += a x
+__global__ __launch_bounds__(kBlock) void k_axpy(double2* __restrict__ y,
+                                                 const double2* __restrict__ x, double a,
+                                                 int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < n) {
+        double2 v = y[e];
+        const double2 w = x[e];
+        v.x += a * w.x;
+        v.y += a * w.y;
+        y[e] = v;
+    }
+}
+void launch_axpy(double2* y, const double2* x, double a, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, y,
+                       x, a, n);
+}
+
 void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, a, b, n);

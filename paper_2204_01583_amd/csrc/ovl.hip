@@ -53,6 +53,7 @@ struct ovl_ctx {
     bool masses_set = false, gauge_set = false;
     // nodes and weights (host, FP64)
     std::vector<double2> z, c;
+    double c0 = 0.0;  // constant term: s = c0 b + sum_j c_j (z_j - H)^-1 b
     // solver settings
     int precision = OVL_PREC_FP64;
     int form = OVL_FORM_FUSED;
@@ -324,6 +325,28 @@ extern "C" int ovl_set_contour(ovl_ctx* ctx, int32_t nq, double gamma, double rh
         ctx->z[nq + j - 1] = make_double2(-gamma + er, ei);
         ctx->c[nq + j - 1] = make_double2(-wr, -wi);
     }
+    ctx->c0 = 0.0;
+    return OVL_OK;
+}
+
+extern "C" int ovl_set_contour_single(ovl_ctx* ctx, int32_t nq, double gamma, double rho,
+                                      double alpha) {
+    if (!ctx) return OVL_E_ARG;
+    if (nq < 2 || (nq & 1) || nq > kMaxShifts)
+        return fail(ctx, OVL_E_ARG, "nq must be even and 2 <= nq <= %d (got %d)", kMaxShifts, nq);
+    if (!(rho > 0.0) || !(alpha > 0.0) || !std::isfinite(gamma))
+        return fail(ctx, OVL_E_ARG, "need rho > 0, alpha > 0, finite gamma");
+    // sgn = P_+ - P_- and P_+ + P_- = 1 without exact zero modes, so
+    // sgn = 2 P_+ - 1 from the Gamma_+ quadrature alone (twice its weights)
+    ctx->z.assign(nq, make_double2(0, 0));
+    ctx->c.assign(nq, make_double2(0, 0));
+    for (int j = 1; j <= nq; ++j) {
+        const double th = 2.0 * M_PI * (j - 0.5) / nq;
+        const double ct = std::cos(th), sn = std::sin(th);
+        ctx->z[j - 1] = make_double2(gamma + rho * ct, rho * alpha * sn);
+        ctx->c[j - 1] = make_double2(2.0 * rho * alpha * ct / nq, 2.0 * rho * sn / nq);
+    }
+    ctx->c0 = -1.0;
     return OVL_OK;
 }
 
@@ -344,6 +367,7 @@ extern "C" int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* zr, const do
         ctx->z[j] = make_double2(zr[2 * j], zr[2 * j + 1]);
         ctx->c[j] = make_double2(cr[2 * j], cr[2 * j + 1]);
     }
+    ctx->c0 = 0.0;
     return OVL_OK;
 }
 
@@ -1167,6 +1191,10 @@ static int solve_batch(Batch& B) {
             HIPCHK(lead, hipGetLastError());
         }
     }
+    // constant term of the rational function (single-contour form)
+    if (lead->c0 != 0.0)
+        for (size_t i = 0; i < B.w.size(); ++i)
+            launch_axpy(B.w[i]->s64, B.w[i]->b64, lead->c0, (int64_t)B.w[i]->nsrc * B.w[i]->N, s);
     HIPCHK(lead, hipEventRecord(e1, s));
     HIPCHK(lead, hipEventSynchronize(e1));
     prof_collect(lead);

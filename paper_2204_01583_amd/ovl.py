@@ -27,7 +27,8 @@ BENCH_STENCIL64, BENCH_STENCIL32 = 0, 1
 # every function declared in include/ovl.h
 EXPORTS = [
     "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
-    "ovl_set_contour", "ovl_set_nodes", "ovl_set_solver", "ovl_set_residual_check",
+    "ovl_set_contour", "ovl_set_contour_single", "ovl_set_nodes", "ovl_set_solver",
+    "ovl_set_residual_check",
     "ovl_apply_hw", "ovl_apply_sign",
     "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
     "ovl_bench_kernel", "ovl_set_profiling", "ovl_get_profile", "ovl_status_string",
@@ -81,6 +82,7 @@ def load():
         "ovl_set_gauge": ([P, P], I),
         "ovl_set_masses": ([P, D, D], I),
         "ovl_set_contour": ([P, I, D, D, D], I),
+        "ovl_set_contour_single": ([P, I, D, D, D], I),
         "ovl_set_nodes": ([P, I, ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "ovl_set_solver": ([P, I, I, D, I, D, D, D], I),
         "ovl_set_residual_check": ([P, I], I),
@@ -178,6 +180,12 @@ class Context:
     def set_contour(self, nq, gamma, rho, alpha):
         self._rc(self.lib.ovl_set_contour(self._h, int(nq), float(gamma), float(rho), float(alpha)),
                  "ovl_set_contour")
+
+    def set_contour_single(self, nq, gamma, rho, alpha):
+        """sgn(H_W) ~ 2 P_{Gamma+} - 1 from the nq nodes of Gamma_+ only (no exact
+        zero modes assumed: one would get 2 F_+(0) - 1, towards -1, not 0)."""
+        self._rc(self.lib.ovl_set_contour_single(self._h, int(nq), float(gamma), float(rho),
+                                                 float(alpha)), "ovl_set_contour_single")
 
     def set_nodes(self, z, c):
         import numpy as np

@@ -302,3 +302,24 @@ def test_stencil_variants(variant, monkeypatch):
         err = float(np.abs(out[i].ravel() - ref).max() / np.abs(ref).max())
         assert err < 1e-14, ("ragged", i, err)
     ctx.close()
+
+
+def test_single_contour_against_oracle():
+    """The one-contour form 2 P_+ - 1 (opt-in) against the oracle's direct
+    solves with the same nodes and constant term, in FP64 and mixed."""
+    from oracle.contour import nodes_single
+    from oracle.sign import sign_by_solves
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    b = si.gaussian_sources(c["dims"], 2, first_seed=41)
+    H = oracle_H(c["dims"], c["r"], c["seed"], c["m0"])
+    z, w, c0 = nodes_single(32, *CIRCLE)
+    for precision, form, tol in ((0, 2, 1e-11), (1, 2, 1e-10), (0, 1, 1e-11)):
+        ctx = make_ctx(c["dims"], U, precision=precision, form=form)
+        ctx.set_contour_single(32, *CIRCLE)
+        s, st = ctx.apply_sign(to_dev(b))
+        assert st.n_shifts == 32
+        for n in range(2):
+            ref = sign_by_solves(H, b[n].ravel(), z, w, method="dense") + c0 * b[n].ravel()
+            assert relerr(s[n].cpu().numpy(), ref) < tol, (precision, form, n)
+        ctx.close()

@@ -39,6 +39,38 @@ def test_filter_odd_real_and_zero_at_zero():
         assert abs(contour.scalar_filter(np.array([0.0]), z, c)[0]) < 1e-14
 
 
+def test_single_contour_form():
+    """2 P_+ - 1 agrees with the two-contour filter on the spectrum away from
+    zero (the circle closed form gives both); at lam = 0 it gives 2 F_+(0) - 1
+    (towards -1) where the two-contour filter gives exactly 0."""
+    from oracle.contour import nodes, nodes_single, scalar_filter
+    gamma, rho, alpha = 1.3, 1.2999, 1.0
+    nq = 64
+    z1, c1, c0 = nodes_single(nq, gamma, rho, alpha)
+    assert len(z1) == nq and c0 == -1.0
+    lam = np.concatenate([np.linspace(0.05, 2.5, 200), -np.linspace(0.05, 2.5, 200)])
+    f1 = 2 * scalar_filter(lam, z1, c1 / 2) + c0          # 2 F_+ - 1
+    # closed form of the circle filter F_+(lam) = 1 / (1 + ((lam - gamma)/rho)^N)
+    fp = 1.0 / (1.0 + ((lam - gamma) / rho) ** nq)
+    assert np.abs(f1 - (2 * fp - 1)).max() < 1e-13
+    z2, c2 = nodes(nq, gamma, rho, alpha)
+    f2 = scalar_filter(lam, z2, c2)
+    # same function up to F_+(lam) + F_+(-lam) - 1, tiny away from 0 and the
+    # spectrum's ends (where the filter itself departs from sgn)
+    diff = np.abs(f1 - f2)
+    assert diff.max() < 1e-2 and np.median(diff) < 1e-8
+    # at lam = 0 the two-contour filter is exactly 0 (odd in lam); the
+    # one-contour form gives 2 F_+(0) - 1, which tends to -1 with N, fast
+    # when 0 lies well outside Gamma_+ (closed form on a circle with margin)
+    zero = np.array([0.0])
+    assert abs(scalar_filter(zero, z2, c2)[0]) < 1e-15
+    for g, r in ((1.3, 1.2999), (1.3, 1.2)):
+        zs, cs, c0s = nodes_single(nq, g, r, 1.0)
+        f0 = scalar_filter(zero, zs, cs)[0] + c0s
+        assert abs(f0 - (2.0 / (1.0 + (g / r) ** nq) - 1.0)) < 1e-12
+    assert f0.real < -0.98
+
+
 def test_paper_contour_counts_per_contour_points():
     """With the paper's ellipse, N_qtot >= 500 gives sigma <= 1e-14 (Results
     summary).  The filter error on the spectrum range reaches that only if
