@@ -217,6 +217,25 @@ int ovl_set_profiling(ovl_ctx* ctx, int32_t enable);
 int ovl_get_profile(const ovl_ctx* ctx, int32_t kclass, double* total_ms, int64_t* launches,
                     double* bytes);
 
+/* Spectral bounds of H_W from the last solve's seed recurrence, a Lanczos
+ * process on H_W, for rhs `src` of the last apply: bounds[0] and bounds[1]
+ * are the smallest and largest Ritz value (inside the spectrum's hull and
+ * converging to its ends first), bounds[2] the square root of the smallest
+ * Ritz value of H_W^2 on the same Krylov space, an upper bound on
+ * min |lambda| (the gap the contour has to resolve) that converges to it.
+ * OVL_E_STATE before any apply. */
+int ovl_spectral_bounds(ovl_ctx* ctx, int32_t src, double* bounds);
+
+/* A circle contour (alpha = 1) for ovl_set_contour from a spectral gap
+ * (smallest |eigenvalue| of H_W, > 0) and the largest |eigenvalue|: centre
+ * gamma and radius rho put Gamma_+ from 1e-4 gap to 1.05 lmax, and nq is the
+ * smallest even count whose two-contour filter error at |lambda| = gap and
+ * at |lambda| = lmax (the circle's closed form, 1 - F(|lambda|) + F(-|lambda|)
+ * with F(lambda) = 1/(1 + ((lambda - gamma)/rho)^nq)) is below `target`.
+ * OVL_E_ARG for a bad input or when 2 nq would exceed 2048. */
+int ovl_suggest_contour(double gap, double lmax, double target, int32_t* nq, double* gamma,
+                        double* rho);
+
 const char* ovl_status_string(int status);
 const char* ovl_last_error(const ovl_ctx* ctx);
 

@@ -287,6 +287,12 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
         S.beta[k & 1] = sc.beta;
         S.rr[k & 1] = sc.rr;
         S.iter = k + 1;
+        if (sh.seed != nullptr) {
+            double2* sd = sh.seed + ((size_t)n * (sh.maxk + 1) + k) * 3;
+            sd[0] = sc.alpha;
+            sd[1] = sc.beta;
+            sd[2] = make_double2(sc.rr, sc.rrn);
+        }
     }
     const double2 c1 = cdiv(cmul(sc.alpha, S.beta[(k + 1) & 1]), S.alpha[(k + 1) & 1]);
     const size_t stride3 = (size_t)sh.nsrc * sh.J;

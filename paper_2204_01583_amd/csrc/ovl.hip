@@ -68,7 +68,11 @@ struct ovl_ctx {
     DBuf b64, r64, p64, q64, r32, p32, q32, s64, pj64, pj32, xj;
     std::vector<DBuf> slot_chunks;   // basis forms: kSlotChunk residual slots each
     size_t slot_chunk_bytes = 0;
-    DBuf part_w, part_b, state, shifts, lists, nodes_dev, hist, W, h;
+    DBuf part_w, part_b, state, shifts, lists, nodes_dev, hist, W, h, seed;
+    // iterations per rhs and maxk of the last solve, whose seed scalars stay in
+    // `seed` until the next one (for ovl_spectral_bounds)
+    std::vector<int> last_iters;
+    int last_maxk = 0;
     SrcState* host_state = nullptr;  // pinned mirror
     int host_state_n = 0;
     DBuf bench_a, bench_b, bench_c, tune_state, chk;
@@ -259,7 +263,7 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
                     &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
                     &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_b,
                     &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
-                    &ctx->h,    &ctx->bench_a, &ctx->bench_b, &ctx->bench_c, &ctx->tune_state, &ctx->chk, &ctx->fY, &ctx->fX, &ctx->fpsi,
+                    &ctx->h,    &ctx->seed,    &ctx->bench_a, &ctx->bench_b, &ctx->bench_c, &ctx->tune_state, &ctx->chk, &ctx->fY, &ctx->fX, &ctx->fpsi,
                     &ctx->facc, &ctx->fc, &ctx->fpart, &ctx->slot_table, &ctx->jobs_dev};
     for (DBuf* b : bufs) b->release();
     for (DBuf& b : ctx->slot_chunks) b.release();
@@ -795,6 +799,8 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     sh.h_a = w.h_a;
     sh.h_b = w.h_b;
     sh.h_pi = w.h_pi;
+    HIPCHK(ctx, ctx->seed.ensure((size_t)nsrc * (w.maxk + 1) * 3 * sizeof(double2)));
+    sh.seed = ctx->seed.as<double2>();
     if ((size_t)ctx->host_state_n < w.state_bytes) {
         if (ctx->host_state) (void)hipHostFree(ctx->host_state);
         ctx->host_state = nullptr;
@@ -1219,6 +1225,13 @@ static int solve_batch(Batch& B) {
                 na += hcnt[n * kMaxSlices + q];
                 mr = std::max(mr, hmres[n * kMaxSlices + q]);
             }
+        // iteration counts per rhs, for ovl_spectral_bounds
+        {
+            const SrcState* hs = reinterpret_cast<const SrcState*>(c->host_state);
+            c->last_iters.resize(w.nsrc);
+            for (int n = 0; n < w.nsrc; ++n) c->last_iters[n] = std::min(hs[n].iter, w.maxk);
+            c->last_maxk = w.maxk;
+        }
         ovl_stats& L = c->last;
         std::memset(&L, 0, sizeof(L));
         L.iterations = w.K;
@@ -1311,6 +1324,147 @@ extern "C" int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample) {
     if (!ctx) return OVL_E_ARG;
     if (nsample < 0 || nsample > 64) return fail(ctx, OVL_E_ARG, "nsample must be in [0, 64]");
     ctx->check_n = nsample;
+    return OVL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// spectral bounds from the seed recurrence and a contour suggestion
+// ---------------------------------------------------------------------------
+// The seed iteration is a Lanczos process on H: with A = z_s - H,
+//   A r_k = -(beta_{k-1}/alpha_{k-1}) r_{k-1} + (1/alpha_k + beta_{k-1}/alpha_{k-1}) r_k
+//           - (1/alpha_k) r_{k+1},
+// so in the orthonormal basis v_k = r_k/||r_k|| the matrix of H is tridiagonal
+// T with diagonal z_s - (1/alpha_k + beta_{k-1}/alpha_{k-1}) (real up to
+// rounding) and off-diagonal moduli e_k = ||r_{k+1}|| / (|alpha_k| ||r_k||).
+// Its eigenvalues (Ritz values) lie inside the spectrum's hull and converge
+// to the extreme eigenvalues first.  Near zero, Ritz values of an indefinite
+// H may fall into the gap; those of H^2 on the same space cannot: V^dag H^2 V
+// = T^2 + e_K^2 u u^T (u the last unit vector) is positive, and its smallest
+// eigenvalue bounds min |lambda|^2 from above.
+namespace {
+// number of eigenvalues below x of the symmetric tridiagonal (d, e) (Sturm)
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < d.size(); ++i) {
+        const double off = i ? e[i - 1] * e[i - 1] : 0.0;
+        q = d[i] - x - (i ? off / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+// number of eigenvalues below x of the symmetric pentadiagonal matrix with
+// diagonal a0, first and second superdiagonals a1, a2: negative pivots of
+// the banded LDL^T of M - x I (Sylvester's law of inertia)
+int penta_count(const std::vector<double>& a0, const std::vector<double>& a1,
+                const std::vector<double>& a2, double x) {
+    const size_t m = a0.size();
+    int cnt = 0;
+    double D1 = 0, D2 = 0;    // D_{i-1}, D_{i-2}
+    double l1m = 0, l2m = 0;  // L_{i,i-1}, L_{i+1,i-1} (from row i-1's column)
+    double l2mm = 0;          // L_{i,i-2}
+    for (size_t i = 0; i < m; ++i) {
+        double D = a0[i] - x - l1m * l1m * D1 - l2mm * l2mm * D2;
+        if (D == 0.0) D = -1e-300;
+        if (D < 0.0) ++cnt;
+        // column i of L: L_{i+1,i} and L_{i+2,i}
+        const double ai1 = i + 1 < m ? a1[i] : 0.0;
+        const double ai2 = i + 2 < m ? a2[i] : 0.0;
+        const double n1 = (ai1 - l2m * l1m * D1) / D;
+        const double n2 = ai2 / D;
+        l2mm = l2m;  // L_{i+1,i-1} becomes row i+1's L_{.,i-1}
+        D2 = D1;
+        D1 = D;
+        l1m = n1;
+        l2m = n2;
+    }
+    return cnt;
+}
+template <typename F>
+double bisect(F count, int k, double lo, double hi) {  // the k-th (0-based) eigenvalue
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo) + std::fabs(hi));
+         ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count(mid) > k) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+}  // namespace
+
+extern "C" int ovl_spectral_bounds(ovl_ctx* ctx, int32_t src, double* bounds) {
+    if (!ctx || !bounds) return OVL_E_ARG;
+    if (src < 0 || (size_t)src >= ctx->last_iters.size())
+        return fail(ctx, OVL_E_STATE, "no seed history for rhs %d (apply first)", src);
+    const int K = ctx->last_iters[src];
+    if (K < 2) return fail(ctx, OVL_E_STATE, "the last solve ran fewer than 2 iterations");
+    DeviceGuard dg(ctx->device);
+    std::vector<double2> h((size_t)K * 3);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(h.data(), ctx->seed.as<double2>() + (size_t)src * (ctx->last_maxk + 1) * 3,
+                          h.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    const int m = K;
+    std::vector<double> d(m), e(m);  // e[m-1]: coupling to the next (unbuilt) vector
+    const double2 zs = ctx->zseed;
+    for (int k = 0; k < m; ++k) {
+        const double2 a = h[3 * k];
+        const double aa = a.x * a.x + a.y * a.y;
+        double2 dk = make_double2(a.x / aa, -a.y / aa);  // 1/alpha_k
+        if (k > 0) {
+            const double2 ap = h[3 * (k - 1)], bp = h[3 * (k - 1) + 1];
+            const double apa = ap.x * ap.x + ap.y * ap.y;
+            dk.x += (bp.x * ap.x + bp.y * ap.y) / apa;  // + beta_{k-1} / alpha_{k-1}
+            dk.y += (bp.y * ap.x - bp.x * ap.y) / apa;
+        }
+        d[k] = zs.x - dk.x;
+        e[k] = std::sqrt(h[3 * k + 2].y / h[3 * k + 2].x) / std::sqrt(aa);
+    }
+    std::vector<double> et(e.begin(), e.end() - 1);
+    double lo = 1e300, hi = -1e300, emax = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double r = (k ? e[k - 1] : 0.0) + (k + 1 < m ? e[k] : 0.0);
+        lo = std::min(lo, d[k] - r);
+        hi = std::max(hi, d[k] + r);
+        emax = std::max(emax, e[k]);
+    }
+    bounds[0] = bisect([&](double x) { return sturm_count(d, et, x); }, 0, lo, hi);
+    bounds[1] = bisect([&](double x) { return sturm_count(d, et, x); }, m - 1, lo, hi);
+    // M = T^2 + e_{m-1}^2 u u^T
+    std::vector<double> a0(m), a1(m, 0.0), a2(m, 0.0);
+    for (int i = 0; i < m; ++i) {
+        a0[i] = d[i] * d[i] + (i ? e[i - 1] * e[i - 1] : 0.0) + e[i] * e[i];
+        if (i + 1 < m) a1[i] = e[i] * (d[i] + d[i + 1]);
+        if (i + 2 < m) a2[i] = e[i] * e[i + 1];
+    }
+    const double mhi = std::pow(std::max(std::fabs(lo), std::fabs(hi)) + 2.0 * emax, 2);
+    const double mu = bisect([&](double x) { return penta_count(a0, a1, a2, x); }, 0, 0.0, mhi);
+    bounds[2] = std::sqrt(std::max(mu, 0.0));
+    return OVL_OK;
+}
+
+extern "C" int ovl_suggest_contour(double gap, double lmax, double target, int32_t* nq,
+                                   double* gamma, double* rho) {
+    if (!nq || !gamma || !rho) return OVL_E_ARG;
+    if (!(gap > 0.0) || !(lmax > gap) || !(target > 0.0 && target < 1.0)) return OVL_E_ARG;
+    // circle (alpha = 1) from a hair above 0 to 5% beyond lmax.  On a circle the
+    // Gamma_+ filter is F(lam) = 1 / (1 + ((lam - gamma)/rho)^N), and the
+    // two-contour error at |lam| is 1 - F(|lam|) + F(-|lam|); it is largest at
+    // the ends |lam| = gap and |lam| = lmax, so take the smallest even N that
+    // brings both under target
+    const double eps = 1e-4 * gap;
+    const double right = 1.05 * lmax;
+    *rho = 0.5 * (right - eps);
+    *gamma = eps + *rho;
+    auto err = [&](double lam, int N) {
+        const double a = std::pow(std::fabs((lam - *gamma) / *rho), N);
+        const double b = std::pow((lam + *gamma) / *rho, N);
+        return a / (1.0 + a) + 1.0 / (1.0 + b);
+    };
+    int n = 2;
+    while (2 * n <= kMaxShifts && (err(gap, n) >= target || err(lmax, n) >= target)) n += 2;
+    if (2 * n > kMaxShifts) return OVL_E_ARG;
+    *nq = n;
     return OVL_OK;
 }
 

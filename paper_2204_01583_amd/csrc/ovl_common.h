@@ -106,6 +106,10 @@ struct ShiftDev {
     double tol;
     // basis forms, may be null: [nsrc][maxk+1][J]
     double2 *h_a, *h_b, *h_pi;
+    // seed scalars per iteration, may be null: [nsrc][maxk+1][3] =
+    // (alpha_k, beta_k, (||r_k||^2, ||r_{k+1}||^2)), the Lanczos data of the
+    // seed system
+    double2* seed;
     int maxk;
 };
 

@@ -28,7 +28,7 @@ BENCH_STENCIL64, BENCH_STENCIL32 = 0, 1
 EXPORTS = [
     "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
     "ovl_set_contour", "ovl_set_contour_single", "ovl_set_nodes", "ovl_set_solver",
-    "ovl_set_residual_check",
+    "ovl_set_residual_check", "ovl_spectral_bounds", "ovl_suggest_contour",
     "ovl_apply_hw", "ovl_apply_sign",
     "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
     "ovl_bench_kernel", "ovl_set_profiling", "ovl_get_profile", "ovl_status_string",
@@ -86,6 +86,8 @@ def load():
         "ovl_set_nodes": ([P, I, ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "ovl_set_solver": ([P, I, I, D, I, D, D, D], I),
         "ovl_set_residual_check": ([P, I], I),
+        "ovl_spectral_bounds": ([P, I, P], I),
+        "ovl_suggest_contour": ([D, D, D, P, P, P], I),
         "ovl_apply_hw": ([P, P, P, I], I),
         "ovl_apply_sign": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "ovl_apply_dov": ([P, P, P, I, ctypes.POINTER(Stats)], I),
@@ -202,6 +204,13 @@ class Context:
                                          float(complex(zseed).imag), float(switch_res)),
                  "ovl_set_solver")
 
+    def spectral_bounds(self, src=0):
+        """(lambda_min, lambda_max, gap) estimates of H_W from the last apply's
+        seed recurrence for rhs `src` (gap: an upper bound on min |lambda|)."""
+        b = (ctypes.c_double * 3)()
+        self._rc(self.lib.ovl_spectral_bounds(self._h, int(src), b), "ovl_spectral_bounds")
+        return tuple(b)
+
     def set_residual_check(self, nsample):
         """After each apply, check the true residual of the `nsample` shifts per
         rhs with the largest residual estimates (Stats.max_true_rel_res)."""
@@ -292,6 +301,18 @@ class Context:
         st = Stats()
         self._rc(self.lib.ovl_get_stats(self._h, ctypes.byref(st)), "ovl_get_stats")
         return st
+
+
+def suggest_contour(gap, lmax, target):
+    """(nq, gamma, rho) of a circle contour (alpha = 1) whose filter error at
+    |lambda| = gap is below target (ovl_suggest_contour)."""
+    lib = load()
+    nq, g, r = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+    rc = lib.ovl_suggest_contour(float(gap), float(lmax), float(target), ctypes.byref(nq),
+                                 ctypes.byref(g), ctypes.byref(r))
+    if rc != OK:
+        raise OvlError(rc, "ovl_suggest_contour: bad arguments or more than 2048 shifts needed")
+    return nq.value, g.value, r.value
 
 
 def apply_sign_batched(contexts, inputs, allow_not_converged=False):

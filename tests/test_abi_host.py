@@ -53,3 +53,24 @@ def test_create_without_gpu_reports_hip_error():
     d = (ctypes.c_int32 * 4)(4, 4, 4, 4)
     assert lib.ovl_create(ctypes.byref(h), d, None, 0, None) == ovl.E_HIP
     assert not h.value
+
+
+def test_suggest_contour_meets_target():
+    """The circle suggested for a gap and a spectral radius keeps the oracle's
+    two-contour filter within the target on the whole |lambda| in [gap, lmax]
+    (host-only call)."""
+    import numpy as np
+    from oracle.contour import nodes, scalar_filter
+    from paper_2204_01583_amd import ovl
+    for gap, lmax, target in ((0.126, 2.3, 1e-12), (0.05, 2.5, 1e-8), (0.3, 1.9, 1e-5)):
+        nq, g, r = ovl.suggest_contour(gap, lmax, target)
+        assert nq % 2 == 0 and 2 * nq <= 2048
+        z, c = nodes(nq, g, r, 1.0)
+        lam = np.concatenate([np.linspace(gap, lmax, 400), -np.linspace(gap, lmax, 400)])
+        err = np.abs(scalar_filter(lam, z, c) - np.sign(lam)).max()
+        assert err < target, (gap, lmax, target, nq, err)
+        # two fewer nodes would not do (the choice is the smallest even count)
+        z2, c2 = nodes(nq - 2, g, r, 1.0)
+        assert np.abs(scalar_filter(lam, z2, c2) - np.sign(lam)).max() > 0.5 * target
+    with pytest.raises(ovl.OvlError):
+        ovl.suggest_contour(1e-4, 2.3, 1e-14)     # needs more than 2048 shifts

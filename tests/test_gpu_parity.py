@@ -323,3 +323,29 @@ def test_single_contour_against_oracle():
             ref = sign_by_solves(H, b[n].ravel(), z, w, method="dense") + c0 * b[n].ravel()
             assert relerr(s[n].cpu().numpy(), ref) < tol, (precision, form, n)
         ctx.close()
+
+
+def test_spectral_bounds_and_suggested_contour():
+    """Ritz values of the seed recurrence bound H_W's spectrum (oracle eigh at
+    4^4), and the contour suggested from them reaches sgn^2 = 1 to the target."""
+    from oracle.sign import eigh_dense
+    from paper_2204_01583_amd import ovl
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    lam = np.linalg.eigvalsh(oracle_H(c["dims"], c["r"], c["seed"], c["m0"]).toarray())
+    b = si.gaussian_sources(c["dims"], 1, first_seed=51)
+    ctx = make_ctx(c["dims"], U, nq=32, form=2, tol=1e-12)
+    ctx.apply_sign(to_dev(b))
+    lo, hi, gap = ctx.spectral_bounds(0)
+    true_gap = np.abs(lam).min()
+    print("ritz", lo, hi, gap, "eig", lam[0], lam[-1], true_gap)
+    assert abs(lo - lam[0]) < 1e-8 and abs(hi - lam[-1]) < 1e-8
+    assert true_gap * (1 - 1e-10) <= gap < 1.01 * true_gap
+    lmax = max(-lo, hi)
+    nq, g, r = ovl.suggest_contour(gap, lmax, 1e-10)
+    ctx.set_contour(nq, g, r, 1.0)
+    s, _ = ctx.apply_sign(to_dev(b))
+    s2, _ = ctx.apply_sign(s)
+    err = relerr(s2.cpu().numpy(), b)
+    assert err < 1e-9, (nq, err)
+    ctx.close()
