@@ -77,7 +77,7 @@ typedef struct {
     int32_t n_active_end;      /* shifts still above tolerance at the end (0 if converged)   */
     double  max_est_rel_res;   /* max_j ||r_j|| / ||b|| from the recurrence, at the end      */
     double  seconds;           /* wall time of the apply on the stream                       */
-    int32_t stencil_variant64; /* stencil variant used in FP64 (autotuned, see ovl_bench_kernel) */
+    int32_t stencil_variant64; /* stencil choice used in FP64 (autotuned; see ovl_bench_kernel) */
     int32_t stencil_variant32; /* ... in FP32, or -1                                        */
     double  max_true_rel_res;  /* max ||b - (z_j - H) x_j|| / ||b|| over the checked shifts, or
                                   -1 when not checked (see ovl_set_residual_check)           */
@@ -190,13 +190,20 @@ int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
  * and the algorithmic bytes of one launch in *bytes.  which:
  *   0: FP64 stencil (out = H_W in) on nrhs internal spinors, autotuned variant
  *   1: the same in FP32
- *   100+v, 200+v: FP64 / FP32 stencil variant v (0..23),
- *      v = 4*order + 2*(rhs per lane - 1) + (hops per loop step - 1): one or
- *      both hops of a direction per step, one or two rhs per lane sharing each
- *      link load, blocks ordered rhs-fastest (0) or site-fastest (1).
- * The first use of a (lattice, nrhs, precision) picks the fastest variant by
- * timing all eight; OVL_STENCIL_VARIANT=v forces one, OVL_AUTOTUNE=0 keeps 0,
- * OVL_AUTOTUNE_CACHE=path persists the choices as a JSON object.
+ *   100+c, 200+c: FP64 / FP32 stencil choice c = v + 24 f: variant v (0..23)
+ *      = 16 tile + 8 (lanes per site - 1) + 4 order + 2 (rhs per lane - 1)
+ *      + (hops per loop step - 1), and link format f (0: full 3x3 links; 1:
+ *      the first two rows, the third rebuilt in the kernel, for SU(3) fields
+ *      only).  Variant bits: one or two hops per loop step; one or two rhs per
+ *      lane sharing each link load; blocks ordered rhs-fastest or
+ *      site-fastest; one lane per site or two (forward and backward hops);
+ *      the block's sites of every rhs staged in LDS (one lane per site).
+ * The first use of a (lattice, nrhs, precision, form) picks the fastest
+ * choice by timing every variant in every allowed link format;
+ * OVL_STENCIL_VARIANT=v forces variant v (two-row links for SU(3) fields
+ * unless OVL_LINKS=full), OVL_AUTOTUNE=0 keeps variant 0, and
+ * OVL_AUTOTUNE_CACHE=path persists the choices as a JSON object, and
+ * OVL_AUTOTUNE_VERBOSE=1 prints every candidate's time to stderr.
  * Buffers are internal scratch (contents arbitrary but finite). */
 int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
                      double* avg_ms, double* bytes);

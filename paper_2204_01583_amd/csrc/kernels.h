@@ -12,10 +12,13 @@ void launch_unpack_spinor64(const double2* in, double2* ext, int64_t V, int n, h
 // out_ext = a*b_ext + bm*gamma5*s_int  (D_ov assembly, eq. (1))
 void launch_unpack_dov(const double2* s_int, const double2* b_ext, double2* out_ext, double a,
                        double bm, int64_t V, int n, hipStream_t s);
-// ext [4][V][9] complex128 -> [4][9][V] FP64 and FP32, boundary signs folded into
-// the links on the last slice of each direction.
-void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, const Geom& g,
-                       const int bc[4], hipStream_t s);
+// ext [4][V][9] complex128 -> [4][9][V] FP64 and FP32 and the two-row form
+// [4][6][V], boundary signs (g.bc) folded into the links on the last slice of
+// each direction; defect[4][gauge_blocks] = per-block max of
+// max(|U U^dag - 1|, |det U - 1|) over the input links (NaN propagates).
+int gauge_blocks(const Geom& g);
+void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, double2* U64c, float2* U32c,
+                       const Geom& g, double* defect, hipStream_t s);
 void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t s);
 // y += a x (complex vectors, real a)
 void launch_axpy(double2* y, const double2* x, double a, int64_t n, hipStream_t s);
@@ -31,11 +34,13 @@ void launch_axpy(double2* y, const double2* x, double a, int64_t n, hipStream_t 
 // hops on neighbouring lanes, 512-thread blocks), and (v >= 16, one lane per
 // site) the block's 256 sites staged in LDS for the neighbours inside it.
 constexpr int kStencilVariants = 24;
+// lnk = 1: U holds the first two rows of every link ([mu][6][V]) and the
+// stencil rebuilds the third (SU(3) fields); lnk = 0: full [mu][9][V]
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                    double kappa, double2 zs, const C2<R>* r, double4* partial,
                    const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s,
-                   int variant = 0);
+                   int variant, int lnk);
 int wilson_blocks(const Geom& g);
 
 // ---- seed iteration over a job table (device-side iteration counter kdev) --
@@ -44,7 +49,7 @@ int wilson_grid_blocks(const Geom& g, int nrhs, int variant);
 // K1 for every job: q = z_s p - H p, <r_k, q> partials
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
-                        int variant, hipStream_t s);
+                        int variant, int lnk, hipStream_t s);
 // K2: seed and shift scalars, shift bookkeeping, r update and p update or
 // sweep; reads the iteration index from kread and writes its successor to kwrite
 template <typename R>

@@ -62,27 +62,72 @@ __global__ __launch_bounds__(kBlock) void k_unpack_dov(const double2* __restrict
     }
 }
 
+// ext [4][V][9] -> [4][9][V] FP64 and FP32, and rows 0 and 1 alone as
+// [4][6][V]; the boundary sign multiplies the links of the last slice of each
+// direction.  defect[mu][blk] = max over the block's input links of
+// max(|U U^dag - 1|, |det U - 1|) (NaN propagates).
 __global__ __launch_bounds__(kBlock) void k_pack_gauge(const double2* __restrict__ ext,
                                                        double2* __restrict__ U64,
-                                                       float2* __restrict__ U32, Geom g,
-                                                       int bc0, int bc1, int bc2, int bc3) {
+                                                       float2* __restrict__ U32,
+                                                       double2* __restrict__ U64c,
+                                                       float2* __restrict__ U32c, Geom g,
+                                                       double* __restrict__ defect) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int mu = blockIdx.y;
-    if (s >= g.V) return;
-    const int coord = (int)((s / g.stride[mu]) % g.L[mu]);
-    const int bcm = mu == 0 ? bc0 : mu == 1 ? bc1 : mu == 2 ? bc2 : bc3;
-    const double sign = (coord == g.L[mu] - 1) ? (double)bcm : 1.0;
-    const double2* src = ext + ((int64_t)mu * g.V + s) * 9;
+    double dev = 0.0;
+    if (s < g.V) {
+        const int coord = (int)((s / g.stride[mu]) % g.L[mu]);
+        const double sign = (coord == g.L[mu] - 1) ? (double)g.bc[mu] : 1.0;
+        const double2* src = ext + ((int64_t)mu * g.V + s) * 9;
+        double2 u[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        double2 v = src[e];
-        v.x *= sign;
-        v.y *= sign;
-        U64[((int64_t)mu * 9 + e) * g.V + s] = v;
-        float2 f;
-        f.x = (float)v.x;
-        f.y = (float)v.y;
-        U32[((int64_t)mu * 9 + e) * g.V + s] = f;
+        for (int e = 0; e < 9; ++e) u[e] = src[e];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const double2 v = make_double2(u[e].x * sign, u[e].y * sign);
+            U64[((int64_t)mu * 9 + e) * g.V + s] = v;
+            U32[((int64_t)mu * 9 + e) * g.V + s] = make_float2((float)v.x, (float)v.y);
+            if (e < 6) {
+                U64c[((int64_t)mu * 6 + e) * g.V + s] = v;
+                U32c[((int64_t)mu * 6 + e) * g.V + s] = make_float2((float)v.x, (float)v.y);
+            }
+        }
+        // unitarity: (U U^dag)_ab = sum_c u_ac conj(u_bc)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                double re = a == b ? -1.0 : 0.0, im = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double2 x = u[3 * a + c], y = u[3 * b + c];
+                    re += x.x * y.x + x.y * y.y;
+                    im += x.y * y.x - x.x * y.y;
+                }
+                dev = fmax(dev, sqrt(re * re + im * im));
+            }
+        const double2 m0 = csub(cmul(u[4], u[8]), cmul(u[5], u[7]));
+        const double2 m1 = csub(cmul(u[3], u[8]), cmul(u[5], u[6]));
+        const double2 m2 = csub(cmul(u[3], u[7]), cmul(u[4], u[6]));
+        const double2 det = cadd(csub(cmul(u[0], m0), cmul(u[1], m1)), cmul(u[2], m2));
+        const double dd = sqrt((det.x - 1.0) * (det.x - 1.0) + det.y * det.y);
+        dev = (dev != dev || dd != dd) ? dd + dev : fmax(dev, dd);
+    }
+    __shared__ double sh[kBlock / 64];
+    // max over the block; a NaN anywhere makes the result NaN
+    double v = dev;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        v = (v != v || w != w) ? v + w : fmax(v, w);
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+#pragma unroll
+        for (int i = 1; i < kBlock / 64; ++i) t = (t != t || sh[i] != sh[i]) ? t + sh[i] : fmax(t, sh[i]);
+        defect[(size_t)mu * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -111,11 +156,12 @@ void launch_unpack_dov(const double2* s_int, const double2* b_ext, double2* out_
     dim3 grid((unsigned)((V + kBlock - 1) / kBlock), n);
     hipLaunchKernelGGL(k_unpack_dov, grid, dim3(kBlock), 0, s, s_int, b_ext, out_ext, a, bm, V);
 }
-void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, const Geom& g,
-                       const int bc[4], hipStream_t s) {
-    dim3 grid((unsigned)((g.V + kBlock - 1) / kBlock), 4);
-    hipLaunchKernelGGL(k_pack_gauge, grid, dim3(kBlock), 0, s, ext, U64, U32, g, bc[0], bc[1],
-                       bc[2], bc[3]);
+int gauge_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
+void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, double2* U64c, float2* U32c,
+                       const Geom& g, double* defect, hipStream_t s) {
+    dim3 grid((unsigned)gauge_blocks(g), 4);
+    hipLaunchKernelGGL(k_pack_gauge, grid, dim3(kBlock), 0, s, ext, U64, U32, U64c, U32c, g,
+                       defect);
 }
 // y += a x
 __global__ __launch_bounds__(kBlock) void k_axpy(double2* __restrict__ y,

@@ -63,7 +63,9 @@ struct ovl_ctx {
     double switch_res = 1e-4;
     int poll = 8;  // iterations between convergence polls
     // device buffers
-    DBuf U64, U32;
+    DBuf U64, U32;    // links [mu][9][V] with the boundary sign folded in
+    DBuf U64c, U32c;  // rows 0 and 1 only, [mu][6][V] (SU(3) fields)
+    bool links12 = false;  // the field is SU(3): the stencil rebuilds row 2
     DBuf hw_in, hw_out;
     DBuf b64, r64, p64, q64, r32, p32, q32, s64, pj64, pj32, xj;
     std::vector<DBuf> slot_chunks;   // basis forms: kSlotChunk residual slots each
@@ -75,7 +77,7 @@ struct ovl_ctx {
     int last_maxk = 0;
     SrcState* host_state = nullptr;  // pinned mirror
     int host_state_n = 0;
-    DBuf bench_a, bench_b, bench_c, tune_state, chk;
+    DBuf bench_a, bench_b, bench_c, tune_state, tune_flush, chk;
     int check_n = 0;  // shifts per source whose true residual is checked after a solve
     DBuf fY, fX, fpsi, facc, fc, fpart;  // force work space
     DBuf slot_table;                       // basis form: device table of slot-chunk bases
@@ -144,6 +146,16 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 double kappa_of(double m0) { return 1.0 / (2.0 * (4.0 - m0)); }
 
 int64_t n12(const ovl_ctx* ctx) { return 12 * ctx->g.V; }
+// A stencil choice is code = variant + kStencilVariants * lnk: the variant
+// (0 .. kStencilVariants-1) and the link format (lnk = 1: the two-row form,
+// only for SU(3) fields).  The links the stencil reads for a format:
+template <typename R> const C2<R>* stencil_links(const ovl_ctx* ctx, int lnk);
+template <> const double2* stencil_links<double>(const ovl_ctx* ctx, int lnk) {
+    return lnk ? ctx->U64c.as<double2>() : ctx->U64.as<double2>();
+}
+template <> const float2* stencil_links<float>(const ovl_ctx* ctx, int lnk) {
+    return lnk ? ctx->U32c.as<float2>() : ctx->U32.as<float2>();
+}
 
 struct DeviceGuard {
     int prev = 0;
@@ -249,6 +261,7 @@ extern "C" int ovl_create(ovl_ctx** out, const int32_t dims[4], const int32_t bc
         ctx->g.stride[i] = stride;
         stride *= dims[i];
         if (bc) ctx->bc[i] = bc[i];
+        ctx->g.bc[i] = ctx->bc[i];
     }
     ctx->g.V = V;
     *out = ctx;
@@ -259,11 +272,11 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
     if (!ctx) return OVL_OK;
     DeviceGuard dg(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    DBuf* bufs[] = {&ctx->U64,  &ctx->U32,   &ctx->hw_in,  &ctx->hw_out, &ctx->b64,   &ctx->r64,
+    DBuf* bufs[] = {&ctx->U64,  &ctx->U32, &ctx->U64c, &ctx->U32c,   &ctx->hw_in,  &ctx->hw_out, &ctx->b64,   &ctx->r64,
                     &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
                     &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_b,
                     &ctx->state, &ctx->shifts, &ctx->lists, &ctx->nodes_dev, &ctx->hist, &ctx->W,
-                    &ctx->h,    &ctx->seed,    &ctx->bench_a, &ctx->bench_b, &ctx->bench_c, &ctx->tune_state, &ctx->chk, &ctx->fY, &ctx->fX, &ctx->fpsi,
+                    &ctx->h,    &ctx->seed,    &ctx->bench_a, &ctx->bench_b, &ctx->bench_c, &ctx->tune_state, &ctx->tune_flush, &ctx->chk, &ctx->fY, &ctx->fX, &ctx->fpsi,
                     &ctx->facc, &ctx->fc, &ctx->fpart, &ctx->slot_table, &ctx->jobs_dev};
     for (DBuf* b : bufs) b->release();
     for (DBuf& b : ctx->slot_chunks) b.release();
@@ -292,9 +305,24 @@ extern "C" int ovl_set_gauge(ovl_ctx* ctx, const void* U) {
     const size_t nl = (size_t)36 * ctx->g.V;
     HIPCHK(ctx, ctx->U64.ensure(nl * sizeof(double2)));
     HIPCHK(ctx, ctx->U32.ensure(nl * sizeof(float2)));
+    HIPCHK(ctx, ctx->U64c.ensure(nl / 9 * 6 * sizeof(double2)));
+    HIPCHK(ctx, ctx->U32c.ensure(nl / 9 * 6 * sizeof(float2)));
+    const int nblk = gauge_blocks(ctx->g);
+    HIPCHK(ctx, ctx->chk.ensure((size_t)4 * nblk * sizeof(double)));
     launch_pack_gauge(static_cast<const double2*>(U), ctx->U64.as<double2>(),
-                      ctx->U32.as<float2>(), ctx->g, ctx->bc, ctx->stream);
+                      ctx->U32.as<float2>(), ctx->U64c.as<double2>(), ctx->U32c.as<float2>(),
+                      ctx->g, ctx->chk.as<double>(), ctx->stream);
     HIPCHK(ctx, hipGetLastError());
+    // SU(3) to rounding (unitary, det 1) -> the two-row form; anything else
+    // (a perturbed field, say) keeps the full matrices
+    std::vector<double> defect((size_t)4 * nblk);
+    HIPCHK(ctx, hipMemcpyAsync(defect.data(), ctx->chk.p, defect.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double dmax = 0.0;
+    for (double d : defect) dmax = std::max(dmax, d);  // NaN-safe: NaN fails the test below
+    const char* lf = getenv("OVL_LINKS");
+    ctx->links12 = dmax < 1e-12 && !(lf && std::strcmp(lf, "full") == 0);
     ctx->gauge_set = true;
     return OVL_OK;
 }
@@ -431,15 +459,16 @@ namespace {
 
 std::mutex g_tune_mu;
 
-std::string tune_key(const ovl_ctx* ctx, int nrhs, int prec, int mode) {
+std::string tune_key(const ovl_ctx* ctx, int nrhs, int prec, int mode, int lnk) {
     hipDeviceProp_t prop;
     const char* arch = "gpu";
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
     int rt = 0;
     (void)hipRuntimeGetVersion(&rt);
     char buf[256];
-    snprintf(buf, sizeof(buf), "%s|hip%d|%dx%dx%dx%d|n%d|%s|m%d", arch, rt, ctx->g.L[0],
-             ctx->g.L[1], ctx->g.L[2], ctx->g.L[3], nrhs, prec ? "fp32" : "fp64", mode);
+    snprintf(buf, sizeof(buf), "%s|hip%d|%dx%dx%dx%d|n%d|%s|m%d|%s", arch, rt, ctx->g.L[0],
+             ctx->g.L[1], ctx->g.L[2], ctx->g.L[3], nrhs, prec ? "fp32" : "fp64", mode,
+             lnk ? "su3" : "gen");
     std::string k(buf);
     for (char& c : k)
         if (c == '"' || c == '\\') c = '_';
@@ -492,8 +521,8 @@ struct TuneInputs {
 };
 
 template <typename R>
-double time_variant(ovl_ctx* ctx, int v, int nrhs, int mode, C2<R>* a, C2<R>* b, const C2<R>* U,
-                    const TuneInputs& ti) {
+double time_variant(ovl_ctx* ctx, int v, int nrhs, int mode, int lnk, C2<R>* a, C2<R>* b,
+                    const C2<R>* U, const TuneInputs& ti) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 1e30;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -504,26 +533,32 @@ double time_variant(ovl_ctx* ctx, int v, int nrhs, int mode, C2<R>* a, C2<R>* b,
         if (mode == 1)
             launch_wilson<R>(1, a, b, U, ctx->g, kappa_of(ctx->m0), ctx->zseed,
                              static_cast<const C2<R>*>(ti.r), ti.partial, ti.st, &ti.sh, 0, nrhs,
-                             ctx->stream, v);
+                             ctx->stream, v, lnk);
         else
             launch_wilson<R>(0, a, b, U, ctx->g, kappa_of(ctx->m0), make_double2(0, 0), nullptr,
-                             nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, v);
+                             nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, v, lnk);
     };
     run();
-    const int reps = 4;
-    float best = 1e30f;
-    for (int trial = 0; trial < 3; ++trial) {  // best of 3 trials damps timing noise
+    // In the solver the stencil's operands arrive after the update kernel has
+    // streamed the basis slot and the vectors through the caches, so each
+    // timed launch here follows 512 MB of writes (twice the last-level cache)
+    // and is timed on its own; the median of 9 is kept.
+    const bool flush = ctx->tune_flush.ensure((size_t)512 << 20) == hipSuccess;
+    std::vector<float> t;
+    for (int i = 0; i < 9; ++i) {
+        if (flush) (void)hipMemsetAsync(ctx->tune_flush.p, i & 0xff, (size_t)512 << 20, ctx->stream);
         (void)hipEventRecord(e0, ctx->stream);
-        for (int i = 0; i < reps; ++i) run();
+        run();
         (void)hipEventRecord(e1, ctx->stream);
         float ms = 1e30f;
         if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
             ms = 1e30f;
-        best = std::min(best, ms);
+        t.push_back(ms);
     }
+    std::nth_element(t.begin(), t.begin() + 4, t.end());
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return best / reps;
+    return t[4];
 }
 
 }  // namespace
@@ -531,24 +566,25 @@ double time_variant(ovl_ctx* ctx, int v, int nrhs, int mode, C2<R>* a, C2<R>* b,
 // Variant of the stencil for nrhs right-hand sides in precision prec (0 FP64,
 // 1 FP32) and mode (0: H_W alone; 1: the solver's q = z_s p - H p with its
 // dot products, timed with every source live).
-static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec, int mode = 0) {
+static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec, int mode) {
+    const int nfmt = ctx->links12 ? 2 : 1;  // link formats to try: full, and two-row if SU(3)
     const char* force = getenv("OVL_STENCIL_VARIANT");
     if (force && *force) {
         const int v = atoi(force);
-        if (v >= 0 && v < kStencilVariants) return v;
+        if (v >= 0 && v < kStencilVariants) return v + kStencilVariants * (nfmt - 1);
     }
     const auto key = std::make_pair(nrhs, prec + 2 * mode);
     auto it = ctx->stencil_variant.find(key);
     if (it != ctx->stencil_variant.end()) return it->second;
     const char* at = getenv("OVL_AUTOTUNE");
-    if (at && at[0] == '0') return ctx->stencil_variant[key] = 0;
+    if (at && at[0] == '0') return ctx->stencil_variant[key] = kStencilVariants * (nfmt - 1);
     const char* path = getenv("OVL_AUTOTUNE_CACHE");
-    const std::string k = tune_key(ctx, nrhs, prec, mode);
+    const std::string k = tune_key(ctx, nrhs, prec, mode, nfmt == 2);
     if (path && *path) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto m = read_cache(path);
         auto f = m.find(k);
-        if (f != m.end() && f->second >= 0 && f->second < kStencilVariants)
+        if (f != m.end() && f->second >= 0 && f->second < kStencilVariants * nfmt)
             return ctx->stencil_variant[key] = f->second;
     }
     const size_t es = prec ? sizeof(float2) : sizeof(double2);
@@ -584,19 +620,30 @@ static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec, int mode = 0) {
             ti.sh.maxk = 1;
         }
     }
+    const char* vb = getenv("OVL_AUTOTUNE_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
     if (ok) {
         double tbest = 1e30;
-        for (int v = 0; v < kStencilVariants; ++v) {
-            const double t = prec ? time_variant<float>(ctx, v, nrhs, mode, ctx->bench_a.as<float2>(),
-                                                        ctx->bench_b.as<float2>(), ctx->U32.as<float2>(), ti)
-                                  : time_variant<double>(ctx, v, nrhs, mode, ctx->bench_a.as<double2>(),
-                                                         ctx->bench_b.as<double2>(), ctx->U64.as<double2>(), ti);
+        for (int code = 0; code < kStencilVariants * nfmt; ++code) {
+            const int v = code % kStencilVariants, lnk = code / kStencilVariants;
+            const float2* U32 = lnk ? ctx->U32c.as<float2>() : ctx->U32.as<float2>();
+            const double2* U64 = lnk ? ctx->U64c.as<double2>() : ctx->U64.as<double2>();
+            const double t =
+                prec ? time_variant<float>(ctx, v, nrhs, mode, lnk, ctx->bench_a.as<float2>(),
+                                           ctx->bench_b.as<float2>(), U32, ti)
+                     : time_variant<double>(ctx, v, nrhs, mode, lnk, ctx->bench_a.as<double2>(),
+                                            ctx->bench_b.as<double2>(), U64, ti);
+            if (verbose)
+                fprintf(stderr, "ovl autotune %s: choice %d (variant %d, %s links) %.2f us\n",
+                        k.c_str(), code, v, lnk ? "two-row" : "full", t * 1e3);
             if (t < tbest) {
                 tbest = t;
-                best = v;
+                best = code;
             }
         }
     }
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->tune_flush.release();  // only needed while tuning
     (void)hipGetLastError();
     ctx->stencil_variant[key] = best;
     if (path && *path) {
@@ -637,10 +684,12 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
     HIPCHK(ctx, ctx->hw_out.ensure(nb));
     launch_pack_spinor64(static_cast<const double2*>(in), ctx->hw_in.as<double2>(), ctx->g.V,
                          nrhs, ctx->stream);
-    const int var = stencil_variant(ctx, nrhs, 0);
+    const int code = stencil_variant(ctx, nrhs, 0, 0);
+    const int var = code % kStencilVariants, lnk = code / kStencilVariants;
     launch_wilson<double>(0, ctx->hw_in.as<double2>(), ctx->hw_out.as<double2>(),
-                          ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0), make_double2(0, 0),
-                          nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, var);
+                          stencil_links<double>(ctx, lnk), ctx->g, kappa_of(ctx->m0),
+                          make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs,
+                          ctx->stream, var, lnk);
     launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, nrhs,
                            ctx->stream);
     HIPCHK(ctx, hipGetLastError());
@@ -860,17 +909,18 @@ struct Batch {
     std::vector<JobDesc> desc;
     int sten_total[2] = {0, 0};  // stencil grid of the FP64 and of the FP32 variant
     int vec_total = 0, variant64 = 0, variant32 = 0, form = 0, maxJ = 0;
+    int lnk[2] = {0, 0};  // link format of the FP64 and of the FP32 stencil
     JobDesc* desc_dev = nullptr;
     int* kdev = nullptr;
 };
 
-void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], int (&sten_b0)[2],
-               int& vec_b0) {
+void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], const int (&lnk)[2],
+               int (&sten_b0)[2], int& vec_b0) {
     d.g = c->g;
     d.kappa = kappa_of(c->m0);
     d.zs = c->zseed;
-    d.U[0] = c->U64.p;
-    d.U[1] = c->U32.p;
+    d.U[0] = lnk[0] ? c->U64c.p : c->U64.p;
+    d.U[1] = lnk[1] ? c->U32c.p : c->U32.p;
     d.nsrc = w.nsrc;
     d.nsb = wilson_blocks(c->g);
     for (int f = 0; f < 2; ++f) {
@@ -901,7 +951,7 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], int (&s
 
 // Enqueue `count` seed iterations of every job in precision R.
 template <typename R>
-void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool prof,
+void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
                    int nact_total) {
     ovl_ctx* lead = B.ctx[0];
     const int c32 = sizeof(R) == 4 ? 1 : 0;
@@ -910,7 +960,7 @@ void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool pr
     if (prof) {
         for (size_t i = 0; i < B.w.size(); ++i) {
             const double V = (double)B.ctx[i]->g.V, n = B.w[i]->nsrc, N = 12 * V;
-            sten_b += V * es * (36.0 + 36.0 * n);
+            sten_b += V * es * ((B.lnk[c32] ? 24.0 : 36.0) + 36.0 * n);
             vec_b += 3.0 * es * N * n;
             const bool ref = B.form == OVL_FORM_REFERENCE;
             sweep_b += N * (n * (2.0 * es + (ref ? 0.0 : 32.0)));
@@ -921,11 +971,10 @@ void enqueue_chunk(const Batch& B, int count, int k_host, hipStream_t s, bool pr
     const int var = c32 ? B.variant32 : B.variant64;
     const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
     for (int i = 0; i < count; ++i) {
-        (void)k_host;
         {
             ProfScope ps(lead, s, prof ? 0 + c32 : -1, sten_b);
             launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
-                                  B.sten_total[c32], var, s);
+                                  B.sten_total[c32], var, B.lnk[c32], s);
         }
         {
             // K2: r update (r, q read, r written) plus p update (p read and
@@ -944,15 +993,16 @@ int replay_chunk(Batch& B, hipStream_t s) {
     ovl_ctx* lead = B.ctx[0];
     const int ph = sizeof(R) == 4 ? 1 : 0;
     char kb[256];
-    snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d", (void*)B.desc_dev, (void*)B.kdev,
-             B.desc.size(), B.sten_total[ph], B.vec_total, ph ? B.variant32 : B.variant64, B.form, B.maxJ);
+    snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d|%d", (void*)B.desc_dev, (void*)B.kdev,
+             B.desc.size(), B.sten_total[ph], B.vec_total, ph ? B.variant32 : B.variant64, B.form,
+             B.maxJ, B.lnk[ph]);
     auto& gc = lead->graphs[ph];
     if (!gc.exec || gc.key != kb) {
         if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
         gc.exec = nullptr;
         hipGraph_t graph;
         HIPCHK(lead, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        enqueue_chunk<R>(B, kChunk, 0, s, false, 0);
+        enqueue_chunk<R>(B, kChunk, s, false, 0);
         HIPCHK(lead, hipStreamEndCapture(s, &graph));
         const hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -963,11 +1013,11 @@ int replay_chunk(Batch& B, hipStream_t s) {
     return OVL_OK;
 }
 
-int run_chunk(Batch& B, bool low, bool graphs, hipStream_t s, int k_host, int nact_total) {
+int run_chunk(Batch& B, bool low, bool graphs, hipStream_t s, int nact_total) {
     if (graphs) return low ? replay_chunk<float>(B, s) : replay_chunk<double>(B, s);
     const bool prof = B.ctx[0]->prof_on;
-    if (low) enqueue_chunk<float>(B, kChunk, k_host, s, prof, nact_total);
-    else enqueue_chunk<double>(B, kChunk, k_host, s, prof, nact_total);
+    if (low) enqueue_chunk<float>(B, kChunk, s, prof, nact_total);
+    else enqueue_chunk<double>(B, kChunk, s, prof, nact_total);
     HIPCHK(B.ctx[0], hipGetLastError());
     return OVL_OK;
 }
@@ -1073,15 +1123,22 @@ static int solve_batch(Batch& B) {
     size_t big = 0;
     for (size_t i = 1; i < B.w.size(); ++i)
         if (B.ctx[i]->g.V * B.w[i]->nsrc > B.ctx[big]->g.V * B.w[big]->nsrc) big = i;
-    B.variant64 = stencil_variant(B.ctx[big], B.w[big]->nsrc, 0, 1);
-    B.variant32 = mixed ? stencil_variant(B.ctx[big], B.w[big]->nsrc, 1, 1) : 0;
+    // the two-row link form only where every job's field is SU(3)
+    bool all12 = true;
+    for (ovl_ctx* c : B.ctx) all12 = all12 && c->links12;
+    const int c64 = stencil_variant(B.ctx[big], B.w[big]->nsrc, 0, 1);
+    const int c32 = mixed ? stencil_variant(B.ctx[big], B.w[big]->nsrc, 1, 1) : 0;
+    B.variant64 = c64 % kStencilVariants;
+    B.variant32 = c32 % kStencilVariants;
+    B.lnk[0] = all12 ? c64 / kStencilVariants : 0;
+    B.lnk[1] = all12 ? c32 / kStencilVariants : 0;
     B.form = form;
     B.maxJ = 0;
     B.desc.resize(B.w.size());
     int sb[2] = {0, 0}, vb = 0;
     const int vars[2] = {B.variant64, B.variant32};
     for (size_t i = 0; i < B.w.size(); ++i) {
-        fill_desc(B.ctx[i], *B.w[i], B.desc[i], vars, sb, vb);
+        fill_desc(B.ctx[i], *B.w[i], B.desc[i], vars, B.lnk, sb, vb);
         B.maxJ = std::max(B.maxJ, B.w[i]->J);
     }
     B.sten_total[0] = sb[0];
@@ -1111,7 +1168,7 @@ static int solve_batch(Batch& B) {
                 rc = ensure_slots(B.ctx[i], *B.w[i], k_host + kChunk + 1, s);
                 if (rc) return rc;
             }
-        rc = run_chunk(B, low, graphs, s, k_host, nact_known);
+        rc = run_chunk(B, low, graphs, s, nact_known);
         if (rc) return rc;
         k_host += kChunk;
         int prc;
@@ -1191,7 +1248,7 @@ static int solve_batch(Batch& B) {
                     low2 = true;
                     for (size_t i = 0; i < B.w.size(); ++i) convert_job(B.ctx[i], *B.w[i], k2, s);
                 }
-                rc = run_chunk(B, low2, graphs, s, k2, nact_known);
+                rc = run_chunk(B, low2, graphs, s, nact_known);
                 if (rc) return rc;
             }
             HIPCHK(lead, hipGetLastError());
@@ -1240,8 +1297,8 @@ static int solve_batch(Batch& B) {
         L.n_active_end = na;
         L.max_est_rel_res = mr;
         L.seconds = ms * 1e-3;
-        L.stencil_variant64 = B.variant64;
-        L.stencil_variant32 = mixed ? B.variant32 : -1;
+        L.stencil_variant64 = B.variant64 + kStencilVariants * B.lnk[0];
+        L.stencil_variant32 = mixed ? B.variant32 + kStencilVariants * B.lnk[1] : -1;
         L.max_true_rel_res = -1.0;
         if (status < 0) fail(c, status, "solver stopped: %s", ovl_status_string(status));
         if (status == OVL_NOT_CONVERGED)
@@ -1280,7 +1337,8 @@ static int true_residuals(ovl_ctx* ctx, const Work& w) {
     double2* X = ctx->chk.as<double2>();
     double2* HX = X + N;
     double2* part = HX + N;
-    const int var = stencil_variant(ctx, 1, 0);
+    const int code = stencil_variant(ctx, 1, 0, 0);
+    const int var = code % kStencilVariants, lnk = code / kStencilVariants;
     const SrcState* hs = reinterpret_cast<const SrcState*>(ctx->host_state);
     std::vector<double2> hp(nblk);
     double worst = 0.0;
@@ -1300,9 +1358,9 @@ static int true_residuals(ovl_ctx* ctx, const Work& w) {
                 if (rc) return rc;
                 x = X;
             }
-            launch_wilson<double>(0, x, HX, ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0),
+            launch_wilson<double>(0, x, HX, stencil_links<double>(ctx, lnk), ctx->g, kappa_of(ctx->m0),
                                   make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, 1, s,
-                                  var);
+                                  var, lnk);
             launch_true_res(w.b64 + (size_t)n * N, x, HX, ctx->z[j], part, nblk, N, s);
             HIPCHK(ctx, hipGetLastError());
             HIPCHK(ctx, hipMemcpyAsync(hp.data(), part, nblk * sizeof(double2),
@@ -1711,9 +1769,11 @@ extern "C" int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const 
 extern "C" int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
                                 double* avg_ms, double* bytes) {
     if (!ctx || !avg_ms || !bytes) return OVL_E_ARG;
-    // which 0/1: FP64/FP32 stencil with the autotuned variant; 100+v / 200+v: FP64/FP32 variant v
-    const bool explicit_v = (which >= 100 && which < 100 + kStencilVariants) ||
-                            (which >= 200 && which < 200 + kStencilVariants);
+    // which 0/1: FP64/FP32 stencil with the autotuned choice; 100+c / 200+c: FP64/FP32
+    // choice c = variant + kStencilVariants * (two-row links)
+    const int nfmt = ctx->links12 ? 2 : 1;
+    const bool explicit_v = (which >= 100 && which < 100 + kStencilVariants * nfmt) ||
+                            (which >= 200 && which < 200 + kStencilVariants * nfmt);
     if (nrhs < 1 || reps < 1 || !(which == 0 || which == 1 || explicit_v))
         return fail(ctx, OVL_E_ARG, "bad bench arguments");
     if (!ctx->gauge_set || !ctx->masses_set) return fail(ctx, OVL_E_STATE, "gauge/masses not set");
@@ -1722,19 +1782,22 @@ extern "C" int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32
     const bool f32 = which == 1 || which >= 200;
     const size_t es = f32 ? sizeof(float2) : sizeof(double2);
     const size_t nb = (size_t)nrhs * N * es;
-    const int var = explicit_v ? which % 100 : stencil_variant(ctx, nrhs, f32 ? 1 : 0);
+    const int code = explicit_v ? which % 100 : stencil_variant(ctx, nrhs, f32 ? 1 : 0, 0);
+    const int var = code % kStencilVariants, lnk = code / kStencilVariants;
     HIPCHK(ctx, ctx->bench_a.ensure(nb));
     HIPCHK(ctx, ctx->bench_b.ensure(nb));
     HIPCHK(ctx, hipMemsetAsync(ctx->bench_a.p, 0, nb, ctx->stream));
     auto launch = [&]() {
         if (f32)
             launch_wilson<float>(0, ctx->bench_a.as<float2>(), ctx->bench_b.as<float2>(),
-                                 ctx->U32.as<float2>(), ctx->g, kappa_of(ctx->m0),
-                                 make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, var);
+                                 stencil_links<float>(ctx, lnk), ctx->g, kappa_of(ctx->m0),
+                                 make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs,
+                                 ctx->stream, var, lnk);
         else
             launch_wilson<double>(0, ctx->bench_a.as<double2>(), ctx->bench_b.as<double2>(),
-                                  ctx->U64.as<double2>(), ctx->g, kappa_of(ctx->m0),
-                                  make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs, ctx->stream, var);
+                                  stencil_links<double>(ctx, lnk), ctx->g, kappa_of(ctx->m0),
+                                  make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs,
+                                  ctx->stream, var, lnk);
     };
     launch();
     HIPCHK(ctx, hipGetLastError());
@@ -1752,6 +1815,6 @@ extern "C" int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32
     *avg_ms = ms / reps;
     // algorithmic bytes: links once (36 complex per site), each spinor read once and
     // written once (12 complex per site per rhs)
-    *bytes = (double)ctx->g.V * (36.0 * es + 2.0 * 12.0 * es * nrhs);
+    *bytes = (double)ctx->g.V * ((lnk ? 24.0 : 36.0) * es + 2.0 * 12.0 * es * nrhs);
     return OVL_OK;
 }

@@ -72,6 +72,7 @@ struct Geom {
     int L[4];        // Lx, Ly, Lz, Lt
     int64_t stride[4];
     int64_t V;
+    int bc[4];       // boundary sign per direction (+1 periodic, -1 antiperiodic)
 };
 
 constexpr int kBlock = 256;           // threads per block of the site kernels

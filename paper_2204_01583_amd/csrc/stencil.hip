@@ -60,12 +60,15 @@ __device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
 // U_mu(x-mu)^dag backward), reconstruct into acc.  Per-lane offsets are 32-bit
 // element indices from uniform base pointers.  With an LDS tile (TIL = 1:
 // the block's 256 sites [s0, s0 + 256) of every rhs, component-major), a
-// neighbour inside the tile is read from LDS instead of memory.
-template <typename R, int RPT, int TIL>
+// neighbour inside the tile is read from LDS instead of memory.  With LNK = 1
+// the links are stored as their first two rows ([6][V] per direction) and the
+// third is rebuilt as lsgn * conj(row0 x row1), exact for SU(3); lsgn is the
+// boundary sign folded into the stored rows of that link.
+template <typename R, int RPT, int TIL, int LNK>
 __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
                                     const C2<R>* const (&psi)[RPT],
                                     const C2<R>* __restrict__ Um, uint32_t V, uint32_t nb,
-                                    uint32_t lsite, const C2<R>* tile, uint32_t s0) {
+                                    uint32_t lsite, const C2<R>* tile, uint32_t s0, R lsgn) {
     const R sg = fwd ? R(-1) : R(1);
     cx<R> pv[RPT][4][3];
     const uint32_t lo = nb - s0;
@@ -97,6 +100,41 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
     // element (a,b) of the hop matrix: U[a][b] forward, conj(U[b][a]) backward
     const R ci = fwd ? R(1) : R(-1);
     cx<R> u[RPT][2][3];
+    if constexpr (LNK == 1) {
+        cx<R> m[3][3];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) m[a][b] = ld<R>(Um, (uint32_t)(3 * a + b) * V + lsite);
+        // row 2 = lsgn * conj(row0 x row1)
+        const cx<R> c0 = m[0][1] * m[1][2] - m[0][2] * m[1][1];
+        const cx<R> c1 = m[0][2] * m[1][0] - m[0][0] * m[1][2];
+        const cx<R> c2 = m[0][0] * m[1][1] - m[0][1] * m[1][0];
+        m[2][0] = mk<R>(lsgn * c0.re, -lsgn * c0.im);
+        m[2][1] = mk<R>(lsgn * c1.re, -lsgn * c1.im);
+        m[2][2] = mk<R>(lsgn * c2.re, -lsgn * c2.im);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                u[r][0][a] = mk<R>(0, 0);
+                u[r][1][a] = mk<R>(0, 0);
+            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                cx<R> l = fwd ? m[a][b] : m[b][a];
+                l.im *= ci;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    fma_(u[r][0][a], l, h[r][0][b]);
+                    fma_(u[r][1][a], l, h[r][1][b]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) reconstruct<R>(mu, sg, acc[r], u[r]);
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -137,28 +175,35 @@ __device__ __forceinline__ uint32_t nbr(const Geom& g, uint32_t s, const int (&c
 // lanes share a site, lane h = 0 the four forward hops and h = 1 the four
 // backward ones, so mu stays wave-uniform; HPI = 2 takes two directions per
 // iteration.
-template <typename R, int HPI, int RPT, int SPL, int TIL>
+template <typename R, int HPI, int RPT, int SPL, int TIL, int LNK>
 __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
                                             const C2<R>* const (&psi)[RPT],
                                             const C2<R>* __restrict__ U, const Geom& g,
                                             uint32_t s, const int (&coord)[4], int h,
                                             const C2<R>* tile, uint32_t s0) {
     const uint32_t V = (uint32_t)g.V;
+    constexpr uint32_t NE = LNK ? 6 : 9;  // stored elements per link
+    // boundary sign of the link a hop uses: U_mu(x) forward (last slice when
+    // x_mu = L-1), U_mu(x - mu) backward (last slice when x_mu = 0)
+    auto lsg = [&](int mu, bool fwd) -> R {
+        const int edge = fwd ? g.L[mu] - 1 : 0;
+        return (coord[mu] == edge && g.bc[mu] < 0) ? R(-1) : R(1);
+    };
     if constexpr (SPL == 2) {
         const bool fwd = h == 0;
         if constexpr (HPI == 1) {
 #pragma unroll 1
             for (int mu = 0; mu < 4; ++mu) {
                 const uint32_t nb = nbr(g, s, coord, mu, fwd);
-                hop<R, RPT, TIL>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb, tile, s0);
+                hop<R, RPT, TIL, LNK>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd));
             }
         } else {
 #pragma unroll 1
             for (int mu = 0; mu < 4; mu += 2) {
                 const uint32_t n0 = nbr(g, s, coord, mu, fwd), n1 = nbr(g, s, coord, mu + 1, fwd);
-                hop<R, RPT, TIL>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, n0, fwd ? s : n0, tile, s0);
-                hop<R, RPT, TIL>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * 9 * V, V, n1,
-                                 fwd ? s : n1, tile, s0);
+                hop<R, RPT, TIL, LNK>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd));
+                hop<R, RPT, TIL, LNK>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * V, V, n1,
+                                 fwd ? s : n1, tile, s0, lsg(mu + 1, fwd));
             }
         }
     } else if constexpr (HPI == 1) {
@@ -167,14 +212,14 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
             const int mu = d >> 1;
             const bool fwd = (d & 1) == 0;
             const uint32_t nb = nbr(g, s, coord, mu, fwd);
-            hop<R, RPT, TIL>(mu, fwd, acc, psi, U + (size_t)mu * 9 * V, V, nb, fwd ? s : nb, tile, s0);
+            hop<R, RPT, TIL, LNK>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd));
         }
     } else {
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
-            hop<R, RPT, TIL>(mu, true, acc, psi, U + (size_t)mu * 9 * V, V, fw, s, tile, s0);
-            hop<R, RPT, TIL>(mu, false, acc, psi, U + (size_t)mu * 9 * V, V, bw, bw, tile, s0);
+            hop<R, RPT, TIL, LNK>(mu, true, acc, psi, U + (size_t)mu * NE * V, V, fw, s, tile, s0, lsg(mu, true));
+            hop<R, RPT, TIL, LNK>(mu, false, acc, psi, U + (size_t)mu * NE * V, V, bw, bw, tile, s0, lsg(mu, false));
         }
     }
 }
@@ -182,7 +227,7 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 
 // Body of the stencil for one block, `tile` being the block's position in
 // the (site tile, rhs group) space after the XCD-aware remap.
-template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL>
+template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>* __restrict__ out,
                                              const C2<R>* __restrict__ U, const Geom& g, R kappa,
                                              double zsr, double zsi,
@@ -253,7 +298,7 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
         coord[1] = (int)(rem % (uint32_t)g.L[1]); rem /= (uint32_t)g.L[1];
         coord[2] = (int)(rem % (uint32_t)g.L[2]);
         coord[3] = (int)(rem / (uint32_t)g.L[2]);
-        dslash_site<R, HPI, RPT, SPL, TIL>(acc, psi, U, g, s, coord, h, lt, s0);
+        dslash_site<R, HPI, RPT, SPL, TIL, LNK>(acc, psi, U, g, s, coord, h, lt, s0);
     }
     if constexpr (SPL == 2) {
         // lane h keeps spins 2h, 2h+1 (in acc[.][0..1]) and adds the partner's
@@ -325,7 +370,7 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
     }
 }
 
-template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL>
+template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 __global__ __launch_bounds__(kBlock * SPL) void k_wilson(const C2<R>* __restrict__ in,
                                                    C2<R>* __restrict__ out,
                                                    const C2<R>* __restrict__ U, Geom g, R kappa,
@@ -335,14 +380,14 @@ __global__ __launch_bounds__(kBlock * SPL) void k_wilson(const C2<R>* __restrict
                                                    const SrcState* __restrict__ stt,
                                                    ShiftDev sh, int k, int nsb, int nrhs) {
     const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
-    wilson_block<R, MODE, HPI, RPT, ORD, SPL, TIL>(in, out, U, g, kappa, zsr, zsi, rdot, partial, stt, sh,
+    wilson_block<R, MODE, HPI, RPT, ORD, SPL, TIL, LNK>(in, out, U, g, kappa, zsr, zsi, rdot, partial, stt, sh,
                                          k, nsb, nrhs, tile);
 }
 
 // K1 over a job table: q = z_s p - H p and <r_k, q> partials for every job of
 // a batch in one launch; the iteration index k is read from device memory so
 // a captured graph can be replayed for any k.
-template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL>
+template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __restrict__ jobs, int njobs,
                                                         const int* __restrict__ kdev) {
     const int k = (int)uniform((uint32_t)*kdev);
@@ -351,7 +396,7 @@ __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __r
     const int f = sizeof(R) == 4 ? 1 : 0;
     while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
     const JobDesc& J = jobs[j];
-    wilson_block<R, 1, HPI, RPT, ORD, SPL, TIL>(static_cast<const C2<R>*>(J.p[f]), static_cast<C2<R>*>(J.q[f]),
+    wilson_block<R, 1, HPI, RPT, ORD, SPL, TIL, LNK>(static_cast<const C2<R>*>(J.p[f]), static_cast<C2<R>*>(J.q[f]),
                                       static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
                                       J.zs.y, job_rk<const C2<R>>(J, k, f), J.part_w, J.st, J.sh,
                                       k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0[f]);
@@ -388,16 +433,20 @@ void with_variant(int v, F&& f) {
 
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
-                        int variant, hipStream_t s) {
+                        int variant, int lnk, hipStream_t s) {
     with_variant(variant, [&](auto H, auto P, auto O, auto S, auto C) {
-        hipLaunchKernelGGL((k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value>),
-                           dim3(total_blocks), dim3(kBlock * S.value), 0, s, jobs, njobs, kdev);
+        if (lnk)
+            hipLaunchKernelGGL((k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value, 1>),
+                               dim3(total_blocks), dim3(kBlock * S.value), 0, s, jobs, njobs, kdev);
+        else
+            hipLaunchKernelGGL((k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value, 0>),
+                               dim3(total_blocks), dim3(kBlock * S.value), 0, s, jobs, njobs, kdev);
     });
 }
-template void launch_wilson_jobs<double>(const JobDesc*, int, const int*, int, int, hipStream_t);
-template void launch_wilson_jobs<float>(const JobDesc*, int, const int*, int, int, hipStream_t);
+template void launch_wilson_jobs<double>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
+template void launch_wilson_jobs<float>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
 
-template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL>
+template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                      double kappa, double2 zs, const C2<R>* r, double4* partial,
                      const SrcState* stt, const ShiftDev& sh, int k, int nrhs, hipStream_t s) {
@@ -405,30 +454,36 @@ void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, cons
     const int ngrp = (nrhs + RPT - 1) / RPT;
     dim3 grid((unsigned)nsb * (unsigned)ngrp);
     if (mode == 0)
-        hipLaunchKernelGGL((k_wilson<R, 0, HPI, RPT, ORD, SPL, TIL>), grid, dim3(kBlock * SPL), 0, s, in,
-                           out, U, g, (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
+        hipLaunchKernelGGL((k_wilson<R, 0, HPI, RPT, ORD, SPL, TIL, LNK>), grid, dim3(kBlock * SPL),
+                           0, s, in, out, U, g, (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb,
+                           nrhs);
     else
-        hipLaunchKernelGGL((k_wilson<R, 1, HPI, RPT, ORD, SPL, TIL>), grid, dim3(kBlock * SPL), 0, s, in,
-                           out, U, g, (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb, nrhs);
+        hipLaunchKernelGGL((k_wilson<R, 1, HPI, RPT, ORD, SPL, TIL, LNK>), grid, dim3(kBlock * SPL),
+                           0, s, in, out, U, g, (R)kappa, zs.x, zs.y, r, partial, stt, sh, k, nsb,
+                           nrhs);
 }
 
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                    double kappa, double2 zs, const C2<R>* r, double4* partial,
                    const SrcState* stt, const ShiftDev* sh, int k, int nrhs, hipStream_t s,
-                   int variant) {
+                   int variant, int lnk) {
     ShiftDev none{};
     const ShiftDev& shv = sh ? *sh : none;
     with_variant(variant, [&](auto H, auto P, auto O, auto S, auto C) {
-        launch_wilson_v<R, H.value, P.value, O.value, S.value, C.value>(mode, in, out, U, g, kappa, zs, r,
-                                                               partial, stt, shv, k, nrhs, s);
+        if (lnk)
+            launch_wilson_v<R, H.value, P.value, O.value, S.value, C.value, 1>(
+                mode, in, out, U, g, kappa, zs, r, partial, stt, shv, k, nrhs, s);
+        else
+            launch_wilson_v<R, H.value, P.value, O.value, S.value, C.value, 0>(
+                mode, in, out, U, g, kappa, zs, r, partial, stt, shv, k, nrhs, s);
     });
 }
 template void launch_wilson<double>(int, const double2*, double2*, const double2*, const Geom&,
                                     double, double2, const double2*, double4*, const SrcState*,
-                                    const ShiftDev*, int, int, hipStream_t, int);
+                                    const ShiftDev*, int, int, hipStream_t, int, int);
 template void launch_wilson<float>(int, const float2*, float2*, const float2*, const Geom&,
                                    double, double2, const float2*, double4*, const SrcState*,
-                                   const ShiftDev*, int, int, hipStream_t, int);
+                                   const ShiftDev*, int, int, hipStream_t, int, int);
 
 }  // namespace ovl

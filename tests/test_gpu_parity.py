@@ -267,12 +267,16 @@ def test_true_residual_contour(precision, form):
     ctx.close()
 
 
+@pytest.mark.parametrize("links", ["two-row", "full"])
 @pytest.mark.parametrize("variant", list(range(24)))
-def test_stencil_variants(variant, monkeypatch):
+def test_stencil_variants(variant, links, monkeypatch):
     """Every stencil variant the autotuner may pick gives the oracle's H_W,
     including an odd number of right-hand sides (the two-rhs tail), and the
-    same sign function in both precisions."""
+    same sign function in both precisions; SU(3) fields in the two-row link
+    form (third row rebuilt, boundary sign applied) and in the full form."""
     monkeypatch.setenv("OVL_STENCIL_VARIANT", str(variant))
+    if links == "full":
+        monkeypatch.setenv("OVL_LINKS", "full")
     dims = (4, 6, 4, 8)
     U = gauge(dims, 0.3, 1)
     ctx = make_ctx(dims, U, nq=16, precision=1, form=2)
@@ -286,7 +290,9 @@ def test_stencil_variants(variant, monkeypatch):
             assert err < 1e-14, (nrhs, i, err)
     b = si.gaussian_sources(dims, 3, first_seed=7)
     s, st = ctx.apply_sign(to_dev(b))
-    assert st.stencil_variant64 == variant and st.stencil_variant32 == variant
+    fmt = 0 if links == "full" else 1
+    assert st.stencil_variant64 == variant + 24 * fmt
+    assert st.stencil_variant32 == variant + 24 * fmt
     ref = oracle_sign(dims, 0.3, 1, 1.4, 16, CIRCLE, 7)
     assert relerr(s[0].cpu().numpy(), ref) < 1e-10
     ctx.close()
@@ -348,4 +354,21 @@ def test_spectral_bounds_and_suggested_contour():
     s2, _ = ctx.apply_sign(s)
     err = relerr(s2.cpu().numpy(), b)
     assert err < 1e-9, (nq, err)
+    ctx.close()
+
+
+def test_non_su3_links_keep_full_form():
+    """A field that is not SU(3) (scaled links) cannot use the two-row form:
+    the library must detect it, and H_W and sgn must still match the oracle
+    built from the same links."""
+    from oracle.wilson import hermitian_wilson
+    dims = (4, 4, 4, 4)
+    U = gauge(dims, 0.3, 0) * 1.001
+    ctx = make_ctx(dims, U, nq=32, form=2)
+    H = hermitian_wilson(U, 1.4)
+    b = si.gaussian_sources(dims, 2, first_seed=61)
+    out = ctx.apply_hw(to_dev(b)).cpu().numpy()
+    for n in range(2):
+        ref = H @ b[n].ravel()
+        assert float(np.abs(out[n].ravel() - ref).max() / np.abs(ref).max()) < 1e-14
     ctx.close()
