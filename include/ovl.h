@@ -190,14 +190,16 @@ int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
  * and the algorithmic bytes of one launch in *bytes.  which:
  *   0: FP64 stencil (out = H_W in) on nrhs internal spinors, autotuned variant
  *   1: the same in FP32
- *   100+c, 200+c: FP64 / FP32 stencil choice c = v + 24 f: variant v (0..23)
- *      = 16 tile + 8 (lanes per site - 1) + 4 order + 2 (rhs per lane - 1)
- *      + (hops per loop step - 1), and link format f (0: full 3x3 links; 1:
- *      the first two rows, the third rebuilt in the kernel, for SU(3) fields
- *      only).  Variant bits: one or two hops per loop step; one or two rhs per
- *      lane sharing each link load; blocks ordered rhs-fastest or
+ *   100+c, 200+c: FP64 / FP32 stencil choice c = v + 28 f: variant v and
+ *      link format f (0: full 3x3 links; 1: the first two rows, the third
+ *      rebuilt in the kernel, for SU(3) fields only).  Variants 0..23 are
+ *      16 tile + 8 (lanes per site - 1) + 4 order + 2 (rhs per lane - 1)
+ *      + (hops per loop step - 1): one or two hops per loop step; one or two
+ *      rhs per lane sharing each link load; blocks ordered rhs-fastest or
  *      site-fastest; one lane per site or two (forward and backward hops);
  *      the block's sites of every rhs staged in LDS (one lane per site).
+ *      Variants 24..27 stage the forward links of a 256-site tile in LDS,
+ *      shared by the 2 or 4 rhs of a block: 24 + 2 (4 rhs) + (hops - 1).
  * The first use of a (lattice, nrhs, precision, form) picks the fastest
  * choice by timing every variant in every allowed link format;
  * OVL_STENCIL_VARIANT=v forces variant v (two-row links for SU(3) fields

@@ -33,7 +33,11 @@ void launch_axpy(double2* y, const double2* x, double a, int64_t n, hipStream_t 
 // (sites fastest), 1 lane per site (all 8 hops) or 2 (forward and backward
 // hops on neighbouring lanes, 512-thread blocks), and (v >= 16, one lane per
 // site) the block's 256 sites staged in LDS for the neighbours inside it.
-constexpr int kStencilVariants = 24;
+// Variants 24 .. 27 keep one lane per site and rhs and stage the forward
+// links of a 256-site tile in LDS, shared by the 2 or 4 rhs of the block
+// (bit 1) with 1 or 2 hops per loop step (bit 0).
+constexpr int kShapeVariants = 24;
+constexpr int kStencilVariants = 28;
 // lnk = 1: U holds the first two rows of every link ([mu][6][V]) and the
 // stencil rebuilds the third (SU(3) fields); lnk = 0: full [mu][9][V]
 template <typename R>

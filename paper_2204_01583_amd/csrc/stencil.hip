@@ -64,12 +64,25 @@ __device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
 // the links are stored as their first two rows ([6][V] per direction) and the
 // third is rebuilt as lsgn * conj(row0 x row1), exact for SU(3); lsgn is the
 // boundary sign folded into the stored rows of that link.
-template <typename R, int RPT, int TIL, int LNK>
+template <typename R, int RPT, int TIL, int LNK, int LT = 0>
 __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
                                     const C2<R>* const (&psi)[RPT],
                                     const C2<R>* __restrict__ Um, uint32_t V, uint32_t nb,
-                                    uint32_t lsite, const C2<R>* tile, uint32_t s0, R lsgn) {
+                                    uint32_t lsite, const C2<R>* tile, uint32_t s0, R lsgn,
+                                    const C2<R>* lut = nullptr) {
     const R sg = fwd ? R(-1) : R(1);
+    // link element e of this hop's link: from the LDS link tile (LT = 1: the
+    // forward links of the block's sites, [NE][256] for this mu) when the
+    // link's site lies in the tile, else from memory
+    const uint32_t llo = lsite - s0;
+    const bool lin = LT && llo < (uint32_t)kBlock;
+    auto lload = [&](uint32_t e) -> cx<R> {
+        if (LT && lin) {
+            const C2<R> v = lut[e * (uint32_t)kBlock + llo];
+            return mk<R>(v.x, v.y);
+        }
+        return ld<R>(Um, e * V + lsite);
+    };
     cx<R> pv[RPT][4][3];
     const uint32_t lo = nb - s0;
     if (TIL && lo < (uint32_t)kBlock) {
@@ -105,7 +118,7 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) m[a][b] = ld<R>(Um, (uint32_t)(3 * a + b) * V + lsite);
+            for (int b = 0; b < 3; ++b) m[a][b] = lload((uint32_t)(3 * a + b));
         // row 2 = lsgn * conj(row0 x row1)
         const cx<R> c0 = m[0][1] * m[1][2] - m[0][2] * m[1][1];
         const cx<R> c1 = m[0][2] * m[1][0] - m[0][0] * m[1][2];
@@ -145,7 +158,7 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             const uint32_t e = fwd ? (uint32_t)(3 * a + b) : (uint32_t)(3 * b + a);
-            cx<R> l = ld<R>(Um, e * V + lsite);
+            cx<R> l = lload(e);
             l.im *= ci;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -175,12 +188,13 @@ __device__ __forceinline__ uint32_t nbr(const Geom& g, uint32_t s, const int (&c
 // lanes share a site, lane h = 0 the four forward hops and h = 1 the four
 // backward ones, so mu stays wave-uniform; HPI = 2 takes two directions per
 // iteration.
-template <typename R, int HPI, int RPT, int SPL, int TIL, int LNK>
+template <typename R, int HPI, int RPT, int SPL, int TIL, int LNK, int LT = 0>
 __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
                                             const C2<R>* const (&psi)[RPT],
                                             const C2<R>* __restrict__ U, const Geom& g,
                                             uint32_t s, const int (&coord)[4], int h,
-                                            const C2<R>* tile, uint32_t s0) {
+                                            const C2<R>* tile, uint32_t s0,
+                                            const C2<R>* lu = nullptr) {
     const uint32_t V = (uint32_t)g.V;
     constexpr uint32_t NE = LNK ? 6 : 9;  // stored elements per link
     // boundary sign of the link a hop uses: U_mu(x) forward (last slice when
@@ -195,15 +209,15 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 #pragma unroll 1
             for (int mu = 0; mu < 4; ++mu) {
                 const uint32_t nb = nbr(g, s, coord, mu, fwd);
-                hop<R, RPT, TIL, LNK>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd));
+                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
             }
         } else {
 #pragma unroll 1
             for (int mu = 0; mu < 4; mu += 2) {
                 const uint32_t n0 = nbr(g, s, coord, mu, fwd), n1 = nbr(g, s, coord, mu + 1, fwd);
-                hop<R, RPT, TIL, LNK>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd));
-                hop<R, RPT, TIL, LNK>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * V, V, n1,
-                                 fwd ? s : n1, tile, s0, lsg(mu + 1, fwd));
+                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
+                hop<R, RPT, TIL, LNK, LT>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * V, V, n1,
+                                 fwd ? s : n1, tile, s0, lsg(mu + 1, fwd), lu + (size_t)(mu + 1) * NE * kBlock);
             }
         }
     } else if constexpr (HPI == 1) {
@@ -212,14 +226,14 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
             const int mu = d >> 1;
             const bool fwd = (d & 1) == 0;
             const uint32_t nb = nbr(g, s, coord, mu, fwd);
-            hop<R, RPT, TIL, LNK>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd));
+            hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
         }
     } else {
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
-            hop<R, RPT, TIL, LNK>(mu, true, acc, psi, U + (size_t)mu * NE * V, V, fw, s, tile, s0, lsg(mu, true));
-            hop<R, RPT, TIL, LNK>(mu, false, acc, psi, U + (size_t)mu * NE * V, V, bw, bw, tile, s0, lsg(mu, false));
+            hop<R, RPT, TIL, LNK, LT>(mu, true, acc, psi, U + (size_t)mu * NE * V, V, fw, s, tile, s0, lsg(mu, true), lu + (size_t)(mu) * NE * kBlock);
+            hop<R, RPT, TIL, LNK, LT>(mu, false, acc, psi, U + (size_t)mu * NE * V, V, bw, bw, tile, s0, lsg(mu, false), lu + (size_t)(mu) * NE * kBlock);
         }
     }
 }
@@ -370,6 +384,138 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
     }
 }
 
+// Link-tile body: RB right-hand sides of one 256-site tile per block (RB
+// groups of four waves, one lane per site and rhs).  The block stages the
+// forward links of its sites in LDS once and every rhs reads them there, as
+// does a backward hop whose link site lies in the tile; blocks are ordered
+// rhs-group fastest, so the blocks of one tile run back to back on one XCD.
+template <typename R, int MODE, int HPI, int RB, int LNK>
+__device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2<R>* __restrict__ out,
+                                                const C2<R>* __restrict__ U, const Geom& g, R kappa,
+                                                double zsr, double zsi,
+                                                const C2<R>* __restrict__ rdot,
+                                                double4* __restrict__ partial,
+                                                const SrcState* __restrict__ stt,
+                                                const ShiftDev& sh, int k, int nsb, int nrhs,
+                                                unsigned tile) {
+    constexpr int NT = kBlock * RB;
+    constexpr uint32_t NE = LNK ? 6 : 9;
+    const int ngrp = (nrhs + RB - 1) / RB;
+    const int grp = (int)uniform(tile % (unsigned)ngrp);
+    const int sb = (int)uniform(tile / (unsigned)ngrp);
+    bool onr[RB];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int n = grp * RB + r;
+        onr[r] = n < nrhs;
+        if constexpr (MODE == 1) onr[r] = onr[r] && src_live(stt[n], sh, n, k);
+        any = any || onr[r];
+    }
+    if (!any) return;
+    const int w = (int)(threadIdx.x / kBlock);  // rhs of this lane within the block (wave-uniform)
+    const uint32_t t = threadIdx.x % kBlock;
+    bool on = false;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (r == w) on = onr[r];
+    const int n = grp * RB + w;
+    const uint32_t V = (uint32_t)g.V;
+    const uint32_t s0 = (uint32_t)sb * kBlock;
+    const uint32_t s = s0 + t;
+    const bool valid = s < V;
+    __shared__ C2<R> lu[4 * NE * kBlock];
+    for (uint32_t q = threadIdx.x; q < 4 * NE * (uint32_t)kBlock; q += NT) {
+        const uint32_t me = q / (uint32_t)kBlock, tt = q % (uint32_t)kBlock;
+        if (s0 + tt < V) lu[q] = U[(size_t)me * V + s0 + tt];
+    }
+    __syncthreads();
+    double dre = 0.0, dim = 0.0, dqq = 0.0, drr = 0.0;
+    if (valid && on) {
+        const C2<R>* psi[1] = {in + (size_t)n * 12 * V};
+        cx<R> acc[1][4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[0][a][c] = mk<R>(0, 0);
+        uint32_t rem = s;
+        int coord[4];
+        coord[0] = (int)(rem % (uint32_t)g.L[0]); rem /= (uint32_t)g.L[0];
+        coord[1] = (int)(rem % (uint32_t)g.L[1]); rem /= (uint32_t)g.L[1];
+        coord[2] = (int)(rem % (uint32_t)g.L[2]);
+        coord[3] = (int)(rem / (uint32_t)g.L[2]);
+        dslash_site<R, HPI, 1, 1, 0, LNK, 1>(acc, psi, U, g, s, coord, 0, nullptr, s0, lu);
+        C2<R>* o = out + (size_t)n * 12 * V;
+        const C2<R>* rd = (MODE == 1) ? rdot + (size_t)n * 12 * V : nullptr;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t comp = (uint32_t)(3 * a + c);
+                const cx<R> p = ld<R>(psi[0], comp * V + s);
+                cx<R> hv = p - kappa * acc[0][a][c];
+                if (a >= 2) hv = -hv;
+                if constexpr (MODE == 0) {
+                    stc<R>(o, comp * V + s, hv);
+                } else {
+                    const R zr = (R)zsr, zi = (R)zsi;
+                    cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
+                    stc<R>(o, comp * V + s, q);
+                    const cx<R> rv = ld<R>(rd, comp * V + s);
+                    dre += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
+                    dim += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
+                    dqq += (double)q.re * (double)q.re + (double)q.im * (double)q.im;
+                    drr += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+                }
+            }
+        }
+    }
+    if constexpr (MODE == 1) {
+        __shared__ double shd[NT / 64];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool mine = w == r;
+            const double tr = block_sum<NT>(mine ? dre : 0.0, shd);
+            const double ti_ = block_sum<NT>(mine ? dim : 0.0, shd);
+            const double tq = block_sum<NT>(mine ? dqq : 0.0, shd);
+            const double tn = block_sum<NT>(mine ? drr : 0.0, shd);
+            if (onr[r] && threadIdx.x == 0)
+                partial[(int64_t)(grp * RB + r) * nsb + sb] = make_double4(tr, ti_, tq, tn);
+        }
+    }
+}
+
+template <typename R, int MODE, int HPI, int RB, int LNK>
+__global__ __launch_bounds__(kBlock * RB) void k_wilson_lt(const C2<R>* __restrict__ in,
+                                                           C2<R>* __restrict__ out,
+                                                           const C2<R>* __restrict__ U, Geom g,
+                                                           R kappa, double zsr, double zsi,
+                                                           const C2<R>* __restrict__ rdot,
+                                                           double4* __restrict__ partial,
+                                                           const SrcState* __restrict__ stt,
+                                                           ShiftDev sh, int k, int nsb, int nrhs) {
+    const unsigned tile = uniform(xcd_remap(blockIdx.x, gridDim.x));
+    wilson_block_lt<R, MODE, HPI, RB, LNK>(in, out, U, g, kappa, zsr, zsi, rdot, partial, stt, sh,
+                                           k, nsb, nrhs, tile);
+}
+
+template <typename R, int HPI, int RB, int LNK>
+__global__ __launch_bounds__(kBlock * RB) void k_wilson_jobs_lt(const JobDesc* __restrict__ jobs,
+                                                                int njobs,
+                                                                const int* __restrict__ kdev) {
+    const int k = (int)uniform((uint32_t)*kdev);
+    const unsigned gb = uniform(xcd_remap(blockIdx.x, gridDim.x));
+    int j = 0;
+    const int f = sizeof(R) == 4 ? 1 : 0;
+    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
+    const JobDesc& J = jobs[j];
+    wilson_block_lt<R, 1, HPI, RB, LNK>(static_cast<const C2<R>*>(J.p[f]),
+                                        static_cast<C2<R>*>(J.q[f]),
+                                        static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
+                                        J.zs.y, job_rk<const C2<R>>(J, k, f), J.part_w, J.st,
+                                        J.sh, k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0[f]);
+}
+
 template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 __global__ __launch_bounds__(kBlock * SPL) void k_wilson(const C2<R>* __restrict__ in,
                                                    C2<R>* __restrict__ out,
@@ -403,9 +549,28 @@ __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __r
 }
 
 int wilson_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
+// right-hand sides per block of a variant: the rhs per lane (variants < 24)
+// or the link tile's rhs groups (24 .. 27)
+static int rhs_per_block(int variant) {
+    if (variant >= kShapeVariants) return ((variant - kShapeVariants) & 2) ? 4 : 2;
+    return (variant & 2) ? 2 : 1;
+}
 int wilson_grid_blocks(const Geom& g, int nrhs, int variant) {
-    const int rpt = (variant & 2) ? 2 : 1;
-    return wilson_blocks(g) * ((nrhs + rpt - 1) / rpt);
+    const int rb = rhs_per_block(variant);
+    return wilson_blocks(g) * ((nrhs + rb - 1) / rb);
+}
+
+// Link-tile variants 24 .. 27: hops per step (bit 0) and rhs per block 2 or 4
+// (bit 1); calls f(HPI, RB) as integral constants.
+template <typename F>
+void with_lt_variant(int v, F&& f) {
+    using std::integral_constant;
+    switch (v - kShapeVariants) {
+        case 1: f(integral_constant<int, 2>{}, integral_constant<int, 2>{}); break;
+        case 2: f(integral_constant<int, 1>{}, integral_constant<int, 4>{}); break;
+        case 3: f(integral_constant<int, 2>{}, integral_constant<int, 4>{}); break;
+        default: f(integral_constant<int, 1>{}, integral_constant<int, 2>{}); break;
+    }
 }
 
 // Calls f(HPI, RPT, ORD, SPL, TIL) as integral constants for variant v =
@@ -434,6 +599,17 @@ void with_variant(int v, F&& f) {
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
                         int variant, int lnk, hipStream_t s) {
+    if (variant >= kShapeVariants) {
+        with_lt_variant(variant, [&](auto H, auto B) {
+            if (lnk)
+                hipLaunchKernelGGL((k_wilson_jobs_lt<R, H.value, B.value, 1>), dim3(total_blocks),
+                                   dim3(kBlock * B.value), 0, s, jobs, njobs, kdev);
+            else
+                hipLaunchKernelGGL((k_wilson_jobs_lt<R, H.value, B.value, 0>), dim3(total_blocks),
+                                   dim3(kBlock * B.value), 0, s, jobs, njobs, kdev);
+        });
+        return;
+    }
     with_variant(variant, [&](auto H, auto P, auto O, auto S, auto C) {
         if (lnk)
             hipLaunchKernelGGL((k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value, 1>),
@@ -470,6 +646,29 @@ void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const 
                    int variant, int lnk) {
     ShiftDev none{};
     const ShiftDev& shv = sh ? *sh : none;
+    if (variant >= kShapeVariants) {
+        const int nsb = wilson_blocks(g);
+        with_lt_variant(variant, [&](auto H, auto B) {
+            const dim3 grid((unsigned)nsb * (unsigned)((nrhs + B.value - 1) / B.value));
+            const dim3 blk(kBlock * B.value);
+            if (lnk) {
+                if (mode == 0)
+                    hipLaunchKernelGGL((k_wilson_lt<R, 0, H.value, B.value, 1>), grid, blk, 0, s, in, out,
+                                       U, g, (R)kappa, zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
+                else
+                    hipLaunchKernelGGL((k_wilson_lt<R, 1, H.value, B.value, 1>), grid, blk, 0, s, in, out,
+                                       U, g, (R)kappa, zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
+            } else {
+                if (mode == 0)
+                    hipLaunchKernelGGL((k_wilson_lt<R, 0, H.value, B.value, 0>), grid, blk, 0, s, in, out,
+                                       U, g, (R)kappa, zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
+                else
+                    hipLaunchKernelGGL((k_wilson_lt<R, 1, H.value, B.value, 0>), grid, blk, 0, s, in, out,
+                                       U, g, (R)kappa, zs.x, zs.y, r, partial, stt, shv, k, nsb, nrhs);
+            }
+        });
+        return;
+    }
     with_variant(variant, [&](auto H, auto P, auto O, auto S, auto C) {
         if (lnk)
             launch_wilson_v<R, H.value, P.value, O.value, S.value, C.value, 1>(

@@ -269,7 +269,7 @@ def test_true_residual_contour(precision, form):
 
 
 @pytest.mark.parametrize("links", ["two-row", "full"])
-@pytest.mark.parametrize("variant", list(range(24)))
+@pytest.mark.parametrize("variant", list(range(28)))
 def test_stencil_variants(variant, links, monkeypatch):
     """Every stencil variant the autotuner may pick gives the oracle's H_W,
     including an odd number of right-hand sides (the two-rhs tail), and the
@@ -292,8 +292,8 @@ def test_stencil_variants(variant, links, monkeypatch):
     b = si.gaussian_sources(dims, 3, first_seed=7)
     s, st = ctx.apply_sign(to_dev(b))
     fmt = 0 if links == "full" else 1
-    assert st.stencil_variant64 == variant + 24 * fmt
-    assert st.stencil_variant32 == variant + 24 * fmt
+    assert st.stencil_variant64 == variant + 28 * fmt
+    assert st.stencil_variant32 == variant + 28 * fmt
     ref = oracle_sign(dims, 0.3, 1, 1.4, 16, CIRCLE, 7)
     assert relerr(s[0].cpu().numpy(), ref) < 1e-10
     ctx.close()
