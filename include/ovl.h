@@ -211,10 +211,13 @@ int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
                      double* avg_ms, double* bytes);
 
 /* Per-kernel timing of the solver's own launches, for benchmarks.  While
- * enabled, every launch of the classes below is bracketed by HIP events on
- * the context's stream; ovl_get_profile returns the summed duration, the
- * number of launches and the summed algorithmic bytes since the last
- * ovl_set_profiling(ctx, 1).  kclass:
+ * enabled, the solver launches eagerly (no graph replay) and times every
+ * launch of the classes below with HIP events on the context's stream: the
+ * kernels of classes 0-5 are launched with hipExtLaunchKernel, whose events
+ * take the kernel's own start and end; the others are bracketed by event
+ * records, which adds their dispatch latency.  ovl_get_profile returns the
+ * summed duration, the number of launches and the summed algorithmic bytes
+ * since the last ovl_set_profiling(ctx, 1).  kclass:
  *   0 stencil FP64 (q = z_s p - H p with <r,q>,   1 the same in FP32
  *     ||q||^2 and ||r||^2)
  *   2 r and p update FP64 (one kernel)             3 the same in FP32

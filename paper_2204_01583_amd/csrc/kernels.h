@@ -50,15 +50,19 @@ int wilson_blocks(const Geom& g);
 // ---- seed iteration over a job table (device-side iteration counter kdev) --
 int vec_blocks(int64_t n12, int nslices);
 int wilson_grid_blocks(const Geom& g, int nrhs, int variant);
-// K1 for every job: q = z_s p - H p, <r_k, q> partials
+// K1 for every job: q = z_s p - H p, <r_k, q> partials.  For this launch and
+// the next: non-null ev0/ev1 take the kernel's own start and end timestamps
+// (hipExtLaunchKernel), for per-kernel timing without marker packets.
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
-                        int variant, int lnk, hipStream_t s);
+                        int variant, int lnk, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 // K2: seed and shift scalars, shift bookkeeping, r update and p update or
 // sweep; reads the iteration index from kread and writes its successor to kwrite
 template <typename R>
 void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
-                             int vec_blocks_total, int form, int maxJ, hipStream_t s);
+                             int vec_blocks_total, int form, int maxJ, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // two-pass form, second pass: s = h_0 b
 void launch_s_init(const double2* b, const double2* h, int maxk, double2* s, int64_t n12, int nsrc,
                    hipStream_t st);

@@ -3,6 +3,7 @@
 // shift sweeps and the basis-form sum.  Everything here is bandwidth bound (no
 // dense contraction), so the kernels stream structure-of-arrays vectors with
 // one lane per complex component.  The stencil is in stencil.hip.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -525,20 +526,28 @@ __global__ __launch_bounds__(kBlock) void k_update_jobs(const JobDesc* __restric
 
 template <typename R>
 void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
-                             int vec_blocks_total, int form, int maxJ, hipStream_t s) {
+                             int vec_blocks_total, int form, int maxJ, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 grid(vec_blocks_total), blk(kBlock);
     const size_t lds = (size_t)maxJ * (3 * sizeof(double2) + sizeof(int));
+    auto go = [&](auto kern, size_t shmem) {
+        if (ev0)
+            hipExtLaunchKernelGGL(kern, grid, blk, (uint32_t)shmem, s, ev0, ev1, 0, jobs, njobs,
+                                  kread, kwrite);
+        else
+            hipLaunchKernelGGL(kern, grid, blk, shmem, s, jobs, njobs, kread, kwrite);
+    };
     if (form == OVL_FORM_BASIS || form == OVL_FORM_TWOPASS)
-        hipLaunchKernelGGL((k_update_jobs<R, 0>), grid, blk, 0, s, jobs, njobs, kread, kwrite);
+        go(k_update_jobs<R, 0>, 0);
     else if (form == OVL_FORM_FUSED)
-        hipLaunchKernelGGL((k_update_jobs<R, 1>), grid, blk, lds, s, jobs, njobs, kread, kwrite);
+        go(k_update_jobs<R, 1>, lds);
     else
-        hipLaunchKernelGGL((k_update_jobs<R, 2>), grid, blk, lds, s, jobs, njobs, kread, kwrite);
+        go(k_update_jobs<R, 2>, lds);
 }
 template void launch_iteration_update<double>(const JobDesc*, int, const int*, int*, int, int, int,
-                                              hipStream_t);
+                                              hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_iteration_update<float>(const JobDesc*, int, const int*, int*, int, int, int,
-                                             hipStream_t);
+                                             hipStream_t, hipEvent_t, hipEvent_t);
 
 // two-pass form, second pass: s = h_0 b (r_0 = b)
 __global__ __launch_bounds__(kBlock) void k_s_init(const double2* __restrict__ b,

@@ -170,12 +170,17 @@ struct DeviceGuard {
     }
 };
 
-// Brackets one launch of class `cls` with two events (profiling only).
+// Times one launch of class `cls` (profiling only): by default two marker
+// events bracket the launch; with kernel_events the caller hands start() and
+// stop() to a hipExtLaunchKernel launch instead, which stamps them with the
+// kernel's own start and end, free of the markers' dispatch overhead.
 struct ProfScope {
     ovl_ctx* ctx;
     hipStream_t st;
     int idx = -1;
-    ProfScope(ovl_ctx* c, hipStream_t s, int cls, double bytes) : ctx(c), st(s) {
+    bool ext;
+    ProfScope(ovl_ctx* c, hipStream_t s, int cls, double bytes, bool kernel_events = false)
+        : ctx(c), st(s), ext(kernel_events) {
         if (!ctx->prof_on) return;
         const size_t need = 2 * (ctx->prof_pending.size() + 1);
         while (ctx->ev_pool.size() < need) {
@@ -185,10 +190,12 @@ struct ProfScope {
         }
         idx = (int)ctx->prof_pending.size();
         ctx->prof_pending.push_back({cls, 2 * idx, bytes});
-        (void)hipEventRecord(ctx->ev_pool[2 * idx], st);
+        if (!ext) (void)hipEventRecord(ctx->ev_pool[2 * idx], st);
     }
+    hipEvent_t start() const { return idx >= 0 && ext ? ctx->ev_pool[2 * idx] : nullptr; }
+    hipEvent_t stop() const { return idx >= 0 && ext ? ctx->ev_pool[2 * idx + 1] : nullptr; }
     ~ProfScope() {
-        if (idx >= 0) (void)hipEventRecord(ctx->ev_pool[2 * idx + 1], st);
+        if (idx >= 0 && !ext) (void)hipEventRecord(ctx->ev_pool[2 * idx + 1], st);
     }
 };
 
@@ -972,17 +979,18 @@ void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
     const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
     for (int i = 0; i < count; ++i) {
         {
-            ProfScope ps(lead, s, prof ? 0 + c32 : -1, sten_b);
+            ProfScope ps(lead, s, prof ? 0 + c32 : -1, sten_b, true);
             launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
-                                  B.sten_total[c32], var, B.lnk[c32], s);
+                                  B.sten_total[c32], var, B.lnk[c32], s, ps.start(), ps.stop());
         }
         {
             // K2: r update (r, q read, r written) plus p update (p read and
             // written) or the sweep
             ProfScope ps(lead, s, prof ? (sweep ? 4 + c32 : 2 + c32) : -1,
-                         sweep ? vec_b + sweep_b : 5.0 / 3.0 * vec_b);
+                         sweep ? vec_b + sweep_b : 5.0 / 3.0 * vec_b, true);
             launch_iteration_update<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
-                                       B.kdev + ((i + 1) & 1), B.vec_total, B.form, B.maxJ, s);
+                                       B.kdev + ((i + 1) & 1), B.vec_total, B.form, B.maxJ, s,
+                                       ps.start(), ps.stop());
         }
     }
 }

@@ -4,6 +4,7 @@
 // spinors and links, 32-bit offsets from uniform bases, an XCD-aware block
 // order, an optional LDS tile of the block's sites, and 24
 // register/latency/locality trade-off variants chosen by the autotuner.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -598,29 +599,34 @@ void with_variant(int v, F&& f) {
 
 template <typename R>
 void launch_wilson_jobs(const JobDesc* jobs, int njobs, const int* kdev, int total_blocks,
-                        int variant, int lnk, hipStream_t s) {
+                        int variant, int lnk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    auto go = [&](auto kern, int threads) {
+        if (ev0)
+            hipExtLaunchKernelGGL(kern, dim3(total_blocks), dim3(threads), 0, s, ev0, ev1, 0, jobs,
+                                  njobs, kdev);
+        else
+            hipLaunchKernelGGL(kern, dim3(total_blocks), dim3(threads), 0, s, jobs, njobs, kdev);
+    };
     if (variant >= kShapeVariants) {
         with_lt_variant(variant, [&](auto H, auto B) {
             if (lnk)
-                hipLaunchKernelGGL((k_wilson_jobs_lt<R, H.value, B.value, 1>), dim3(total_blocks),
-                                   dim3(kBlock * B.value), 0, s, jobs, njobs, kdev);
+                go(k_wilson_jobs_lt<R, H.value, B.value, 1>, kBlock * B.value);
             else
-                hipLaunchKernelGGL((k_wilson_jobs_lt<R, H.value, B.value, 0>), dim3(total_blocks),
-                                   dim3(kBlock * B.value), 0, s, jobs, njobs, kdev);
+                go(k_wilson_jobs_lt<R, H.value, B.value, 0>, kBlock * B.value);
         });
         return;
     }
     with_variant(variant, [&](auto H, auto P, auto O, auto S, auto C) {
         if (lnk)
-            hipLaunchKernelGGL((k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value, 1>),
-                               dim3(total_blocks), dim3(kBlock * S.value), 0, s, jobs, njobs, kdev);
+            go(k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value, 1>, kBlock * S.value);
         else
-            hipLaunchKernelGGL((k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value, 0>),
-                               dim3(total_blocks), dim3(kBlock * S.value), 0, s, jobs, njobs, kdev);
+            go(k_wilson_jobs<R, H.value, P.value, O.value, S.value, C.value, 0>, kBlock * S.value);
     });
 }
-template void launch_wilson_jobs<double>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
-template void launch_wilson_jobs<float>(const JobDesc*, int, const int*, int, int, int, hipStream_t);
+template void launch_wilson_jobs<double>(const JobDesc*, int, const int*, int, int, int, hipStream_t,
+                                         hipEvent_t, hipEvent_t);
+template void launch_wilson_jobs<float>(const JobDesc*, int, const int*, int, int, int, hipStream_t,
+                                        hipEvent_t, hipEvent_t);
 
 template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 void launch_wilson_v(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
