@@ -738,6 +738,11 @@ size_t state_mres_off(int nsrc) {
     return (state_cnt_off(nsrc) + (size_t)2 * nsrc * kMaxSlices * sizeof(int) + 255) & ~(size_t)255;
 }
 size_t state_bytes_for(int nsrc) { return state_mres_off(nsrc) + (size_t)nsrc * kMaxSlices * sizeof(double); }
+// stride of the two pinned host copies of a job's state
+size_t state_slot_bytes(const Work& w) { return (w.state_bytes + 255) & ~(size_t)255; }
+const char* host_slot(const ovl_ctx* c, const Work& w, int slot) {
+    return reinterpret_cast<const char*>(c->host_state) + (size_t)slot * state_slot_bytes(w);
+}
 
 int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     const int J = (int)ctx->z.size();
@@ -857,12 +862,15 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     sh.h_pi = w.h_pi;
     HIPCHK(ctx, ctx->seed.ensure((size_t)nsrc * (w.maxk + 1) * 3 * sizeof(double2)));
     sh.seed = ctx->seed.as<double2>();
-    if ((size_t)ctx->host_state_n < w.state_bytes) {
+    // two pinned copies of the state: the poll reads one while the copy of
+    // the next chunk's state may be in flight into the other
+    if ((size_t)ctx->host_state_n < 2 * state_slot_bytes(w)) {
         if (ctx->host_state) (void)hipHostFree(ctx->host_state);
         ctx->host_state = nullptr;
         ctx->host_state_n = 0;
-        HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, w.state_bytes, hipHostMallocDefault));
-        ctx->host_state_n = (int)w.state_bytes;
+        HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, 2 * state_slot_bytes(w),
+                                  hipHostMallocDefault));
+        ctx->host_state_n = (int)(2 * state_slot_bytes(w));
     }
     return OVL_OK;
 }
@@ -1072,26 +1080,37 @@ struct PollResult {
     int iters = 0, nact = 0;
 };
 
-PollResult poll(Batch& B, int k_host, hipStream_t s, int* rc_out) {
-    PollResult P;
-    *rc_out = OVL_OK;
+// Queues the copy of every job's device state into pinned slot `slot` and
+// records ev after it.
+int post_state(Batch& B, int slot, hipStream_t s, hipEvent_t ev) {
     for (size_t i = 0; i < B.w.size(); ++i) {
         ovl_ctx* c = B.ctx[i];
         Work& w = *B.w[i];
-        if (hipMemcpyAsync(c->host_state, w.st, w.state_bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
-            *rc_out = fail(B.ctx[0], OVL_E_HIP, "state copy failed");
+        char* dst = reinterpret_cast<char*>(c->host_state) + (size_t)slot * state_slot_bytes(w);
+        if (hipMemcpyAsync(dst, w.st, w.state_bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return fail(B.ctx[0], OVL_E_HIP, "state copy failed");
     }
-    if (hipStreamSynchronize(s) != hipSuccess) *rc_out = fail(B.ctx[0], OVL_E_HIP, "stream sync failed");
+    if (hipEventRecord(ev, s) != hipSuccess) return fail(B.ctx[0], OVL_E_HIP, "event record failed");
+    return OVL_OK;
+}
+
+// Waits for ev (posted after the chunk that ends at iteration k_host) and
+// evaluates the state copied into pinned slot `slot`.
+PollResult read_state(Batch& B, int slot, int k_host, hipEvent_t ev, int* rc_out) {
+    PollResult P;
+    *rc_out = OVL_OK;
+    if (hipEventSynchronize(ev) != hipSuccess) *rc_out = fail(B.ctx[0], OVL_E_HIP, "state wait failed");
     prof_collect(B.ctx[0]);
     for (size_t i = 0; i < B.w.size(); ++i) {
         ovl_ctx* c = B.ctx[i];
         Work& w = *B.w[i];
-        const char* hb = reinterpret_cast<const char*>(c->host_state);
+        const char* hb = host_slot(c, w, slot);
+        const SrcState* hs = reinterpret_cast<const SrcState*>(hb);
         const int* hcnt = reinterpret_cast<const int*>(hb + state_cnt_off(w.nsrc)) +
                           (size_t)(std::min(k_host, w.maxk) & 1) * w.nsrc * kMaxSlices;
         const double* hmres = reinterpret_cast<const double*>(hb + state_mres_off(w.nsrc));
         for (int n = 0; n < w.nsrc; ++n) {
-            const SrcState& S = c->host_state[n];
+            const SrcState& S = hs[n];
             if (S.status != OVL_OK && P.status == OVL_OK) P.status = S.status;
             int na = 0;
             for (int q = 0; q < w.sh.nslices; ++q) {
@@ -1165,35 +1184,86 @@ static int solve_batch(Batch& B) {
     HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));  // outside any captured graph
 
     bool low = false;
-    int k_switch = -1, k_host = 0, status = OVL_OK;
+    int k_switch = -1, status = OVL_OK;
+    int k_host = 0;  // iterations whose state the host has read
+    int k_enq = 0;   // iterations queued
     PollResult P;
     P.maxres = 1.0;
     int nact_known = 0;
     for (size_t i = 0; i < B.w.size(); ++i) nact_known += B.w[i]->J * B.w[i]->nsrc;
-    while (k_host < maxk) {
+    hipEvent_t pev[2];
+    HIPCHK(lead, hipEventCreateWithFlags(&pev[0], hipEventDisableTiming));
+    HIPCHK(lead, hipEventCreateWithFlags(&pev[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+    } evg{pev};
+    // one chunk of kChunk iterations, then the copy of its state into pinned
+    // slot (chunk index & 1)
+    auto queue_chunk = [&]() -> int {
         if (form == OVL_FORM_BASIS)
             for (size_t i = 0; i < B.w.size(); ++i) {
-                rc = ensure_slots(B.ctx[i], *B.w[i], k_host + kChunk + 1, s);
-                if (rc) return rc;
+                const int r = ensure_slots(B.ctx[i], *B.w[i], k_enq + kChunk + 1, s);
+                if (r) return r;
             }
-        rc = run_chunk(B, low, graphs, s, nact_known);
-        if (rc) return rc;
+        int r = run_chunk(B, low, graphs, s, nact_known);
+        if (r) return r;
+        k_enq += kChunk;
+        const int slot = (k_enq / kChunk) & 1;
+        return post_state(B, slot, s, pev[slot]);
+    };
+    // Look-ahead: while the largest shifted residual is far above the next
+    // decision point (the precision switch, then the tolerance), the chunk
+    // after the polled one is queued before the host waits, so the device
+    // does not idle through the poll.  Within a factor 10 of that point the
+    // loop polls each chunk before queueing the next, so the switch and the
+    // stop fall on the same iteration as with one chunk in flight.  A chunk
+    // queued past convergence finds no live source and returns at once.
+    // Profiling keeps one chunk in flight (its events are read at each poll).
+    const bool may_look_ahead = !lead->prof_on;
+    while (k_host < maxk) {
+        if (k_enq == k_host) {
+            rc = queue_chunk();
+            if (rc) return rc;
+        }
+        const double next_point = (mixed && !low) ? lead->switch_res : lead->tol;
+        if (may_look_ahead && k_enq == k_host + kChunk && k_enq < maxk &&
+            P.maxres > 10.0 * next_point) {
+            rc = queue_chunk();
+            if (rc) return rc;
+        }
         k_host += kChunk;
         int prc;
-        P = poll(B, k_host, s, &prc);
+        const int slot = (k_host / kChunk) & 1;
+        P = read_state(B, slot, k_host, pev[slot], &prc);
         if (prc) return prc;
         nact_known = P.nact;
         if (P.status != OVL_OK) { status = P.status; break; }
         if (P.all_done) break;
         if (mixed && !low && P.maxres < lead->switch_res && k_host < maxk) {
             // relaxed precision: from here the remaining corrections are small
-            // enough that FP32 vectors perturb the result by ~eps32 * switch_res
+            // enough that FP32 vectors perturb the result by ~eps32 * switch_res.
+            // The conversion follows any chunk still queued.
             low = true;
-            k_switch = k_host;
-            for (size_t i = 0; i < B.w.size(); ++i) convert_job(B.ctx[i], *B.w[i], k_host, s);
+            k_switch = k_enq;
+            for (size_t i = 0; i < B.w.size(); ++i) convert_job(B.ctx[i], *B.w[i], k_enq, s);
             HIPCHK(lead, hipGetLastError());
         }
     }
+    // a chunk queued past the last poll: its state is the final one
+    if (k_enq > k_host) {
+        int prc;
+        const int slot = (k_enq / kChunk) & 1;
+        const PollResult Q = read_state(B, slot, k_enq, pev[slot], &prc);
+        if (prc) return prc;
+        if (status == OVL_OK) status = Q.status;
+        P.all_done = P.all_done || Q.all_done;
+        k_host = k_enq;
+    }
+    // the final state into slot 0, where the code below reads it
+    if (((k_host / kChunk) & 1) != 0)
+        for (size_t i = 0; i < B.w.size(); ++i)
+            memcpy(B.ctx[i]->host_state, host_slot(B.ctx[i], *B.w[i], 1), B.w[i]->state_bytes);
     const int k_run = k_host;
     if (status == OVL_OK && !P.all_done) status = OVL_NOT_CONVERGED;
     for (size_t i = 0; i < B.w.size(); ++i) {
