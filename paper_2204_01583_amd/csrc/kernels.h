@@ -5,15 +5,19 @@
 namespace ovl {
 
 // ---- layout conversion -----------------------------------------------------
-// ext [n][V][12] complex128  <->  internal [n][12][V] (double2 or float2)
-void launch_pack_spinor64(const double2* ext, double2* in, int64_t V, int n, hipStream_t s);
-void launch_pack_spinor32(const double2* ext, float2* in, int64_t V, int n, hipStream_t s);
-void launch_unpack_spinor64(const double2* in, double2* ext, int64_t V, int n, hipStream_t s);
+// ext [n][V][12] complex128  <->  internal tiled [n][Vt/64][12][64] (double2 or
+// float2); the sites from V to Vt are not touched
+void launch_pack_spinor64(const double2* ext, double2* in, int64_t V, int64_t Vt, int n,
+                          hipStream_t s);
+void launch_pack_spinor32(const double2* ext, float2* in, int64_t V, int64_t Vt, int n,
+                          hipStream_t s);
+void launch_unpack_spinor64(const double2* in, double2* ext, int64_t V, int64_t Vt, int n,
+                            hipStream_t s);
 // out_ext = a*b_ext + bm*gamma5*s_int  (D_ov assembly, eq. (1))
 void launch_unpack_dov(const double2* s_int, const double2* b_ext, double2* out_ext, double a,
-                       double bm, int64_t V, int n, hipStream_t s);
-// ext [4][V][9] complex128 -> [4][9][V] FP64 and FP32 and the two-row form
-// [4][6][V], boundary signs (g.bc) folded into the links on the last slice of
+                       double bm, int64_t V, int64_t Vt, int n, hipStream_t s);
+// ext [4][V][9] complex128 -> tiled [4][Vt/64][9][64] FP64 and FP32 and the
+// two-row form [4][Vt/64][6][64], boundary signs (g.bc) folded into the links on the last slice of
 // each direction; defect[4][gauge_blocks] = per-block max of
 // max(|U U^dag - 1|, |det U - 1|) over the input links (NaN propagates).
 int gauge_blocks(const Geom& g);
@@ -38,8 +42,8 @@ void launch_axpy(double2* y, const double2* x, double a, int64_t n, hipStream_t 
 // (bit 1) with 1 or 2 hops per loop step (bit 0).
 constexpr int kShapeVariants = 24;
 constexpr int kStencilVariants = 28;
-// lnk = 1: U holds the first two rows of every link ([mu][6][V]) and the
-// stencil rebuilds the third (SU(3) fields); lnk = 0: full [mu][9][V]
+// lnk = 1: U holds the first two rows of every link ([mu][Vt/64][6][64]) and
+// the stencil rebuilds the third (SU(3) fields); lnk = 0: full [mu][Vt/64][9][64]
 template <typename R>
 void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const Geom& g,
                    double kappa, double2 zs, const C2<R>* r, double4* partial,
@@ -84,9 +88,10 @@ void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_strid
                        double2* sacc, bool accumulate, int64_t n12, int nsrc, hipStream_t s);
 
 // ---- force ------------------------------------------------------------------
-// d = a b + bm gamma5 s, psi = bm gamma5 d, partial[blk] = |d|^2 (one source, SoA)
+// d = a b + bm gamma5 s, psi = bm gamma5 d, partial[blk] = |d|^2 (one source,
+// tiled layout of Vt sites)
 void launch_dov_psi(const double2* b, const double2* s, double2* psi, double a, double bm,
-                    int64_t V, double* partial, int nblk, hipStream_t st);
+                    int64_t Vt, double* partial, int nblk, hipStream_t st);
 // Y[j] (+)= sum over one slot chunk of u_i^{j0+j} r_i, j < jn, for the source
 // whose slot elements start at element eoff (W already offset to that source)
 void launch_materialize(const char* chunk, size_t slot_bytes, int g0, int l1, int ksw,

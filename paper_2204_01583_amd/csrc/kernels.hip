@@ -16,55 +16,57 @@ namespace ovl {
 // ============================================================================
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_pack_spinor(const double2* __restrict__ ext,
-                                                        C2<R>* __restrict__ in, int64_t V) {
+                                                        C2<R>* __restrict__ in, int64_t V,
+                                                        int64_t Vt) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int n = blockIdx.y;
     if (s >= V) return;
     const double2* src = ext + ((int64_t)n * V + s) * 12;
-    C2<R>* dst = in + (int64_t)n * 12 * V + s;
+    C2<R>* dst = in + (int64_t)n * 12 * Vt;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         double2 v = src[c];
         C2<R> w;
         w.x = (R)v.x;
         w.y = (R)v.y;
-        dst[(int64_t)c * V] = w;
+        dst[tix64(c, s, 12)] = w;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_unpack_spinor(const double2* __restrict__ in,
-                                                          double2* __restrict__ ext, int64_t V) {
+                                                          double2* __restrict__ ext, int64_t V,
+                                                          int64_t Vt) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int n = blockIdx.y;
     if (s >= V) return;
-    const double2* src = in + (int64_t)n * 12 * V + s;
+    const double2* src = in + (int64_t)n * 12 * Vt;
     double2* dst = ext + ((int64_t)n * V + s) * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) dst[c] = src[(int64_t)c * V];
+    for (int c = 0; c < 12; ++c) dst[c] = src[tix64(c, s, 12)];
 }
 
 __global__ __launch_bounds__(kBlock) void k_unpack_dov(const double2* __restrict__ sin,
                                                        const double2* __restrict__ bext,
                                                        double2* __restrict__ ext, double a,
-                                                       double bm, int64_t V) {
+                                                       double bm, int64_t V, int64_t Vt) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int n = blockIdx.y;
     if (s >= V) return;
-    const double2* src = sin + (int64_t)n * 12 * V + s;
+    const double2* src = sin + (int64_t)n * 12 * Vt;
     const double2* b = bext + ((int64_t)n * V + s) * 12;
     double2* dst = ext + ((int64_t)n * V + s) * 12;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         const double g5 = (c < 6) ? bm : -bm;  // gamma5 = diag(1,1,-1,-1) on spin
-        double2 sv = src[(int64_t)c * V], bv = b[c], o;
+        double2 sv = src[tix64(c, s, 12)], bv = b[c], o;
         o.x = a * bv.x + g5 * sv.x;
         o.y = a * bv.y + g5 * sv.y;
         dst[c] = o;
     }
 }
 
-// ext [4][V][9] -> [4][9][V] FP64 and FP32, and rows 0 and 1 alone as
-// [4][6][V]; the boundary sign multiplies the links of the last slice of each
+// ext [4][V][9] -> per direction the tiled [Vt/64][9][64] FP64 and FP32, and
+// rows 0 and 1 alone as [Vt/64][6][64]; the boundary sign multiplies the links of the last slice of each
 // direction.  defect[mu][blk] = max over the block's input links of
 // max(|U U^dag - 1|, |det U - 1|) (NaN propagates).
 __global__ __launch_bounds__(kBlock) void k_pack_gauge(const double2* __restrict__ ext,
@@ -86,11 +88,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge(const double2* __restrict
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
             const double2 v = make_double2(u[e].x * sign, u[e].y * sign);
-            U64[((int64_t)mu * 9 + e) * g.V + s] = v;
-            U32[((int64_t)mu * 9 + e) * g.V + s] = make_float2((float)v.x, (float)v.y);
+            U64[(int64_t)mu * 9 * g.Vt + tix64(e, s, 9)] = v;
+            U32[(int64_t)mu * 9 * g.Vt + tix64(e, s, 9)] = make_float2((float)v.x, (float)v.y);
             if (e < 6) {
-                U64c[((int64_t)mu * 6 + e) * g.V + s] = v;
-                U32c[((int64_t)mu * 6 + e) * g.V + s] = make_float2((float)v.x, (float)v.y);
+                U64c[(int64_t)mu * 6 * g.Vt + tix64(e, s, 6)] = v;
+                U32c[(int64_t)mu * 6 * g.Vt + tix64(e, s, 6)] = make_float2((float)v.x, (float)v.y);
             }
         }
         // unitarity: (U U^dag)_ab = sum_c u_ac conj(u_bc)
@@ -140,22 +142,25 @@ __global__ __launch_bounds__(kBlock) void k_convert(const double2* __restrict__ 
     b[i] = make_float2((float)v.x, (float)v.y);
 }
 
-void launch_pack_spinor64(const double2* ext, double2* in, int64_t V, int n, hipStream_t s) {
+void launch_pack_spinor64(const double2* ext, double2* in, int64_t V, int64_t Vt, int n,
+                          hipStream_t s) {
     dim3 grid((unsigned)((V + kBlock - 1) / kBlock), n);
-    hipLaunchKernelGGL(k_pack_spinor<double>, grid, dim3(kBlock), 0, s, ext, in, V);
+    hipLaunchKernelGGL(k_pack_spinor<double>, grid, dim3(kBlock), 0, s, ext, in, V, Vt);
 }
-void launch_pack_spinor32(const double2* ext, float2* in, int64_t V, int n, hipStream_t s) {
+void launch_pack_spinor32(const double2* ext, float2* in, int64_t V, int64_t Vt, int n,
+                          hipStream_t s) {
     dim3 grid((unsigned)((V + kBlock - 1) / kBlock), n);
-    hipLaunchKernelGGL(k_pack_spinor<float>, grid, dim3(kBlock), 0, s, ext, in, V);
+    hipLaunchKernelGGL(k_pack_spinor<float>, grid, dim3(kBlock), 0, s, ext, in, V, Vt);
 }
-void launch_unpack_spinor64(const double2* in, double2* ext, int64_t V, int n, hipStream_t s) {
+void launch_unpack_spinor64(const double2* in, double2* ext, int64_t V, int64_t Vt, int n,
+                            hipStream_t s) {
     dim3 grid((unsigned)((V + kBlock - 1) / kBlock), n);
-    hipLaunchKernelGGL(k_unpack_spinor, grid, dim3(kBlock), 0, s, in, ext, V);
+    hipLaunchKernelGGL(k_unpack_spinor, grid, dim3(kBlock), 0, s, in, ext, V, Vt);
 }
 void launch_unpack_dov(const double2* s_int, const double2* b_ext, double2* out_ext, double a,
-                       double bm, int64_t V, int n, hipStream_t s) {
+                       double bm, int64_t V, int64_t Vt, int n, hipStream_t s) {
     dim3 grid((unsigned)((V + kBlock - 1) / kBlock), n);
-    hipLaunchKernelGGL(k_unpack_dov, grid, dim3(kBlock), 0, s, s_int, b_ext, out_ext, a, bm, V);
+    hipLaunchKernelGGL(k_unpack_dov, grid, dim3(kBlock), 0, s, s_int, b_ext, out_ext, a, bm, V, Vt);
 }
 int gauge_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
 void launch_pack_gauge(const double2* ext, double2* U64, float2* U32, double2* U64c, float2* U32c,
@@ -411,7 +416,7 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
             __syncthreads();
         }
     }
-    const int64_t n12 = 12 * J.g.V;
+    const int64_t n12 = 12 * J.g.Vt;
     const R ar = (R)sc.alpha.x, ai = (R)sc.alpha.y;
     const R br = (R)sc.beta.x, bi = (R)sc.beta.y;
     const C2<R>* ri = job_rk<const C2<R>>(J, k, f) + (size_t)n * n12;
@@ -760,12 +765,13 @@ void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t 
 __global__ __launch_bounds__(kBlock) void k_dov_psi(const double2* __restrict__ b,
                                                     const double2* __restrict__ sv,
                                                     double2* __restrict__ psi, double a, double bm,
-                                                    int64_t V, double* __restrict__ partial) {
-    const int64_t n12 = 12 * V;
+                                                    int64_t Vt, double* __restrict__ partial) {
+    const int64_t n12 = 12 * Vt;
     double acc = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
          e += (int64_t)gridDim.x * kBlock) {
-        const double g5 = (e / V) < 6 ? 1.0 : -1.0;  // component = e / V, spin = comp / 3
+        // tiled layout: component = (e / 64) % 12, spin = component / 3
+        const double g5 = ((e / kTile) % 12) < 6 ? 1.0 : -1.0;
         const double2 bv = b[e], s = sv[e];
         const double2 d = make_double2(a * bv.x + bm * g5 * s.x, a * bv.y + bm * g5 * s.y);
         acc += d.x * d.x + d.y * d.y;
@@ -776,8 +782,8 @@ __global__ __launch_bounds__(kBlock) void k_dov_psi(const double2* __restrict__ 
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 void launch_dov_psi(const double2* b, const double2* s, double2* psi, double a, double bm,
-                    int64_t V, double* partial, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_dov_psi, dim3(nblk), dim3(kBlock), 0, st, b, s, psi, a, bm, V, partial);
+                    int64_t Vt, double* partial, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_dov_psi, dim3(nblk), dim3(kBlock), 0, st, b, s, psi, a, bm, Vt, partial);
 }
 
 // Y[j][e] (+)= sum_{i in one slot chunk} u_i^{j} r_i[e] for shifts j0 .. j0+JG-1
@@ -914,14 +920,14 @@ __global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ X,
                                                   double kappa, double2* __restrict__ acc,
                                                   int first, int last, int kind,
                                                   double2* __restrict__ out) {
-    const int64_t V = g.V;
+    const int64_t V = g.V, Vt = g.Vt;
     const int64_t lk = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (lk >= 4 * V) return;
     const int mu = (int)(lk / V);
     const int64_t x = lk - (int64_t)mu * V;
     const int cm = (int)((x / g.stride[mu]) % g.L[mu]);
     const int64_t xp = (cm == g.L[mu] - 1) ? x - (int64_t)(g.L[mu] - 1) * g.stride[mu] : x + g.stride[mu];
-    const int64_t n12 = 12 * V;
+    const int64_t n12 = 12 * Vt;
     double2 A[3][3], B[3][3];
     double2* ac = acc + (size_t)lk * 18;
 #pragma unroll
@@ -942,8 +948,8 @@ __global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ X,
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                v[sp][cc] = Yj[(size_t)(3 * sp + cc) * V + xp];
-                xs[sp][cc] = Xj[(size_t)(3 * sp + cc) * V + x];
+                v[sp][cc] = Yj[tix64(3 * sp + cc, xp, 12)];
+                xs[sp][cc] = Xj[tix64(3 * sp + cc, x, 12)];
             }
         proj_g5(mu, -1.0, v, m);
 #pragma unroll
@@ -964,8 +970,8 @@ __global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ X,
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                v[sp][cc] = Yj[(size_t)(3 * sp + cc) * V + x];
-                xs[sp][cc] = Xj[(size_t)(3 * sp + cc) * V + xp];
+                v[sp][cc] = Yj[tix64(3 * sp + cc, x, 12)];
+                xs[sp][cc] = Xj[tix64(3 * sp + cc, xp, 12)];
             }
         proj_g5(mu, 1.0, v, m);
 #pragma unroll
@@ -1019,7 +1025,7 @@ __global__ __launch_bounds__(kBlock) void k_force(const double2* __restrict__ X,
             double2 t = make_double2(0, 0);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {  // U[a][q] conj(G[b][q])
-                double2 u = Uint[((size_t)mu * 9 + 3 * a + q) * V + x];
+                double2 u = Uint[(size_t)mu * 9 * Vt + tix64(3 * a + q, x, 9)];
                 u.x *= ph;
                 u.y *= ph;
                 const double2 gg = G[b][q];

@@ -21,7 +21,9 @@ using namespace ovl;
 
 namespace {
 
-// A device allocation that only grows.
+// A device allocation that only grows.  New memory is zeroed before ensure
+// returns, so the padding sites of the tiled layouts start at zero; every
+// kernel keeps them there.
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -31,7 +33,14 @@ struct DBuf {
         p = nullptr;
         bytes = 0;
         hipError_t e = hipMalloc(&p, nb);
-        if (e == hipSuccess) bytes = nb;
+        if (e == hipSuccess) e = hipMemset(p, 0, nb);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) {
+            bytes = nb;
+        } else if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
         return e;
     }
     void release() {
@@ -63,8 +72,8 @@ struct ovl_ctx {
     double switch_res = 1e-4;
     int poll = 8;  // iterations between convergence polls
     // device buffers
-    DBuf U64, U32;    // links [mu][9][V] with the boundary sign folded in
-    DBuf U64c, U32c;  // rows 0 and 1 only, [mu][6][V] (SU(3) fields)
+    DBuf U64, U32;    // links, tiled [mu][Vt/64][9][64], boundary sign folded in
+    DBuf U64c, U32c;  // rows 0 and 1 only, [mu][Vt/64][6][64] (SU(3) fields)
     bool links12 = false;  // the field is SU(3): the stencil rebuilds row 2
     DBuf hw_in, hw_out;
     DBuf b64, r64, p64, q64, r32, p32, q32, s64, pj64, pj32, xj;
@@ -145,7 +154,9 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 double kappa_of(double m0) { return 1.0 / (2.0 * (4.0 - m0)); }
 
-int64_t n12(const ovl_ctx* ctx) { return 12 * ctx->g.V; }
+// elements of one source: internal (tiled, Vt sites) and caller layout (V sites)
+int64_t n12(const ovl_ctx* ctx) { return 12 * ctx->g.Vt; }
+int64_t n12_ext(const ovl_ctx* ctx) { return 12 * ctx->g.V; }
 // A stencil choice is code = variant + kStencilVariants * lnk: the variant
 // (0 .. kStencilVariants-1) and the link format (lnk = 1: the two-row form,
 // only for SU(3) fields).  The links the stencil reads for a format:
@@ -271,6 +282,7 @@ extern "C" int ovl_create(ovl_ctx** out, const int32_t dims[4], const int32_t bc
         ctx->g.bc[i] = ctx->bc[i];
     }
     ctx->g.V = V;
+    ctx->g.Vt = (V + kTile - 1) / kTile * kTile;
     *out = ctx;
     return OVL_OK;
 }
@@ -309,7 +321,7 @@ extern "C" int ovl_set_gauge(ovl_ctx* ctx, const void* U) {
     DeviceGuard dg(ctx->device);
     int rc = check_dev_ptr(ctx, U, "U");
     if (rc) return rc;
-    const size_t nl = (size_t)36 * ctx->g.V;
+    const size_t nl = (size_t)36 * ctx->g.Vt;
     HIPCHK(ctx, ctx->U64.ensure(nl * sizeof(double2)));
     HIPCHK(ctx, ctx->U32.ensure(nl * sizeof(float2)));
     HIPCHK(ctx, ctx->U64c.ensure(nl / 9 * 6 * sizeof(double2)));
@@ -473,7 +485,7 @@ std::string tune_key(const ovl_ctx* ctx, int nrhs, int prec, int mode, int lnk) 
     int rt = 0;
     (void)hipRuntimeGetVersion(&rt);
     char buf[256];
-    snprintf(buf, sizeof(buf), "%s|hip%d|%dx%dx%dx%d|n%d|%s|m%d|%s", arch, rt, ctx->g.L[0],
+    snprintf(buf, sizeof(buf), "%s|hip%d|t%d|%dx%dx%dx%d|n%d|%s|m%d|%s", arch, rt, kTile, ctx->g.L[0],
              ctx->g.L[1], ctx->g.L[2], ctx->g.L[3], nrhs, prec ? "fp32" : "fp64", mode,
              lnk ? "su3" : "gen");
     std::string k(buf);
@@ -676,7 +688,7 @@ static int check_apply_args(ovl_ctx* ctx, const void* in, const void* out, int n
     if (rc) return rc;
     rc = check_dev_ptr(ctx, out, "out");
     if (rc) return rc;
-    const size_t bytes = (size_t)nrhs * n12(ctx) * sizeof(double2);
+    const size_t bytes = (size_t)nrhs * n12_ext(ctx) * sizeof(double2);
     if (overlaps(in, bytes, out, bytes)) return fail(ctx, OVL_E_ARG, "out aliases in");
     return OVL_OK;
 }
@@ -689,7 +701,7 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
     const size_t nb = (size_t)nrhs * n12(ctx) * sizeof(double2);
     HIPCHK(ctx, ctx->hw_in.ensure(nb));
     HIPCHK(ctx, ctx->hw_out.ensure(nb));
-    launch_pack_spinor64(static_cast<const double2*>(in), ctx->hw_in.as<double2>(), ctx->g.V,
+    launch_pack_spinor64(static_cast<const double2*>(in), ctx->hw_in.as<double2>(), ctx->g.V, ctx->g.Vt,
                          nrhs, ctx->stream);
     const int code = stencil_variant(ctx, nrhs, 0, 0);
     const int var = code % kStencilVariants, lnk = code / kStencilVariants;
@@ -697,7 +709,7 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
                           stencil_links<double>(ctx, lnk), ctx->g, kappa_of(ctx->m0),
                           make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs,
                           ctx->stream, var, lnk);
-    launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, nrhs,
+    launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, ctx->g.Vt, nrhs,
                            ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     return OVL_OK;
@@ -1276,6 +1288,7 @@ static int solve_batch(Batch& B) {
             ovl_ctx* c = B.ctx[i];
             Work& w = *B.w[i];
             const int64_t N = w.N;
+            const double Na = 12.0 * (double)c->g.V;  // algorithmic elements per source
             if (form == OVL_FORM_REFERENCE) {
                 launch_sum_ref(w.xj, w.cj, w.s64, w.J, N, w.nsrc, s);
             } else if (form == OVL_FORM_BASIS || form == OVL_FORM_TWOPASS) {
@@ -1291,14 +1304,14 @@ static int solve_batch(Batch& B) {
                     char* base = w.chunks[c0 / kSlotChunk];
                     const int a0 = c0, a1 = std::min(c1, ksw);
                     if (a1 > a0) {
-                        ProfScope ps(lead, s, 6, (double)N * w.nsrc * (16.0 * (a1 - a0) + 32.0));
+                        ProfScope ps(lead, s, 6, Na * w.nsrc * (16.0 * (a1 - a0) + 32.0));
                         launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.maxk, w.st, c0,
                                                   a0 - c0, a1 - c0, w.s64, acc, N, w.nsrc, s);
                         acc = true;
                     }
                     const int f0 = std::max(c0, ksw), f1 = c1;
                     if (f1 > f0) {
-                        ProfScope ps(lead, s, 6, (double)N * w.nsrc * (8.0 * (f1 - f0) + 32.0));
+                        ProfScope ps(lead, s, 6, Na * w.nsrc * (8.0 * (f1 - f0) + 32.0));
                         launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.maxk, w.st,
                                                  c0, f0 - c0, f1 - c0, w.s64, acc, N, w.nsrc, s);
                         acc = true;
@@ -1613,7 +1626,7 @@ static int apply_common(ovl_ctx* ctx, const void* in, void* out, int nrhs, ovl_s
     Work w;
     rc = prepare(ctx, nrhs, w);
     if (rc) return rc;
-    launch_pack_spinor64(static_cast<const double2*>(in), w.b64, ctx->g.V, nrhs, ctx->stream);
+    launch_pack_spinor64(static_cast<const double2*>(in), w.b64, ctx->g.V, ctx->g.Vt, nrhs, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     rc = solve(ctx, w);
     if (rc < 0) return rc;
@@ -1621,10 +1634,10 @@ static int apply_common(ovl_ctx* ctx, const void* in, void* out, int nrhs, ovl_s
     if (rcc < 0) return rcc;
     if (dov)
         launch_unpack_dov(w.s64, static_cast<const double2*>(in), static_cast<double2*>(out),
-                          0.5 * (1.0 + ctx->mq), 0.5 * (1.0 - ctx->mq), ctx->g.V, nrhs,
+                          0.5 * (1.0 + ctx->mq), 0.5 * (1.0 - ctx->mq), ctx->g.V, ctx->g.Vt, nrhs,
                           ctx->stream);
     else
-        launch_unpack_spinor64(w.s64, static_cast<double2*>(out), ctx->g.V, nrhs, ctx->stream);
+        launch_unpack_spinor64(w.s64, static_cast<double2*>(out), ctx->g.V, ctx->g.Vt, nrhs, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (st) *st = ctx->last;
@@ -1690,7 +1703,7 @@ extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind
     Work w;
     rc = prepare(ctx, 1, w);
     if (rc) { restore(); return rc; }
-    launch_pack_spinor64(static_cast<const double2*>(phi), w.b64, ctx->g.V, 1, s);
+    launch_pack_spinor64(static_cast<const double2*>(phi), w.b64, ctx->g.V, ctx->g.Vt, 1, s);
     const int rc1 = solve(ctx, w);
     if (rc1 < 0) { restore(); return rc1; }
     const ovl_stats st1 = ctx->last;
@@ -1709,7 +1722,7 @@ extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind
     // 2. D_ov phi, psi = (1-mq)/2 gamma5 D_ov phi and S = |D_ov phi|^2
     const int npart = 256;
     launch_dov_psi(w.b64, w.s64, ctx->fpsi.as<double2>(), 0.5 * (1.0 + ctx->mq),
-                   0.5 * (1.0 - ctx->mq), ctx->g.V, ctx->fpart.as<double>(), npart, s);
+                   0.5 * (1.0 - ctx->mq), ctx->g.Vt, ctx->fpart.as<double>(), npart, s);
     std::vector<double> part(npart);
     HIPCHK(ctx, hipMemcpyAsync(part.data(), ctx->fpart.p, npart * sizeof(double),
                                hipMemcpyDeviceToHost, s));
@@ -1811,13 +1824,13 @@ extern "C" int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const 
     }
     if (rc != OVL_OK) { restore(); return rc; }
     for (int i = 0; i < nctx; ++i)
-        launch_pack_spinor64(static_cast<const double2*>(in[i]), works[i].b64, ctxs[i]->g.V, nrhs[i],
+        launch_pack_spinor64(static_cast<const double2*>(in[i]), works[i].b64, ctxs[i]->g.V, ctxs[i]->g.Vt, nrhs[i],
                              lead->stream);
     if (hipGetLastError() != hipSuccess) { restore(); return fail(lead, OVL_E_HIP, "pack failed"); }
     rc = solve_batch(B);
     if (rc >= 0) {
         for (int i = 0; i < nctx; ++i)
-            launch_unpack_spinor64(works[i].s64, static_cast<double2*>(out[i]), ctxs[i]->g.V, nrhs[i],
+            launch_unpack_spinor64(works[i].s64, static_cast<double2*>(out[i]), ctxs[i]->g.V, ctxs[i]->g.Vt, nrhs[i],
                                    lead->stream);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(lead->stream) != hipSuccess)
             rc = fail(lead, OVL_E_HIP, "unpack failed");

@@ -65,15 +65,30 @@ template <typename R> __device__ __forceinline__ void fmac_(cx<R>& a, cx<R> b, c
 }
 
 // Lattice geometry of one context.  Sites are numbered
-// s = x + Lx*(y + Ly*(z + Lz*t)); internal fields are structure-of-arrays:
-// spinor [rhs][12][V] (component 3*spin + colour), links [mu][9][V]
-// (element 3*row + col), so consecutive lanes read consecutive sites.
+// s = x + Lx*(y + Ly*(z + Lz*t)).  Internal fields are tiled over 64-site
+// tiles (see tix): a spinor is [rhs][Vt/64][12][64] (component 3*spin +
+// colour), the links of one direction [Vt/64][NE][64] (element 3*row + col),
+// so the 64 lanes of a wave read one contiguous 512 B (FP32) or 1 KiB (FP64)
+// segment per component, and the 12 components of a tile lie in one
+// contiguous block.  Vt = V rounded up to whole tiles; the sites from V to
+// Vt of the last tile are zeros, kept at zero by every kernel.
 struct Geom {
     int L[4];        // Lx, Ly, Lz, Lt
     int64_t stride[4];
-    int64_t V;
+    int64_t V;       // sites
+    int64_t Vt;      // V rounded up to a multiple of kTile
     int bc[4];       // boundary sign per direction (+1 periodic, -1 antiperiodic)
 };
+
+constexpr int kTile = 64;  // sites per tile of the internal layouts
+
+// Offset of component c of site s in one tiled array of nc components per site.
+__host__ __device__ __forceinline__ uint32_t tix(uint32_t c, uint32_t s, uint32_t nc) {
+    return ((s / (uint32_t)kTile) * nc + c) * (uint32_t)kTile + s % (uint32_t)kTile;
+}
+__host__ __device__ __forceinline__ int64_t tix64(int64_t c, int64_t s, int64_t nc) {
+    return ((s / kTile) * nc + c) * kTile + s % kTile;
+}
 
 constexpr int kBlock = 256;           // threads per block of the site kernels
 constexpr int kMaxShifts = 2048;      // shifted systems per apply

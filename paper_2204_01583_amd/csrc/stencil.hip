@@ -62,16 +62,17 @@ __device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
 // element indices from uniform base pointers.  With an LDS tile (TIL = 1:
 // the block's 256 sites [s0, s0 + 256) of every rhs, component-major), a
 // neighbour inside the tile is read from LDS instead of memory.  With LNK = 1
-// the links are stored as their first two rows ([6][V] per direction) and the
+// the links are stored as their first two rows (6 elements per link) and the
 // third is rebuilt as lsgn * conj(row0 x row1), exact for SU(3); lsgn is the
 // boundary sign folded into the stored rows of that link.
 template <typename R, int RPT, int TIL, int LNK, int LT = 0>
 __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
                                     const C2<R>* const (&psi)[RPT],
-                                    const C2<R>* __restrict__ Um, uint32_t V, uint32_t nb,
+                                    const C2<R>* __restrict__ Um, uint32_t nb,
                                     uint32_t lsite, const C2<R>* tile, uint32_t s0, R lsgn,
                                     const C2<R>* lut = nullptr) {
     const R sg = fwd ? R(-1) : R(1);
+    constexpr uint32_t NE = LNK ? 6 : 9;  // stored elements per link
     // link element e of this hop's link: from the LDS link tile (LT = 1: the
     // forward links of the block's sites, [NE][256] for this mu) when the
     // link's site lies in the tile, else from memory
@@ -82,7 +83,7 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
             const C2<R> v = lut[e * (uint32_t)kBlock + llo];
             return mk<R>(v.x, v.y);
         }
-        return ld<R>(Um, e * V + lsite);
+        return ld<R>(Um, tix(e, lsite, NE));
     };
     cx<R> pv[RPT][4][3];
     const uint32_t lo = nb - s0;
@@ -102,7 +103,7 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pv[r][a][c] = ld<R>(psi[r], (uint32_t)(3 * a + c) * V + nb);
+                for (int c = 0; c < 3; ++c) pv[r][a][c] = ld<R>(psi[r], tix((uint32_t)(3 * a + c), nb, 12));
     }
     cx<R> h[RPT][2][3];
 #pragma unroll
@@ -196,7 +197,7 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
                                             uint32_t s, const int (&coord)[4], int h,
                                             const C2<R>* tile, uint32_t s0,
                                             const C2<R>* lu = nullptr) {
-    const uint32_t V = (uint32_t)g.V;
+    const uint32_t Vt = (uint32_t)g.Vt;
     constexpr uint32_t NE = LNK ? 6 : 9;  // stored elements per link
     // boundary sign of the link a hop uses: U_mu(x) forward (last slice when
     // x_mu = L-1), U_mu(x - mu) backward (last slice when x_mu = 0)
@@ -210,14 +211,14 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 #pragma unroll 1
             for (int mu = 0; mu < 4; ++mu) {
                 const uint32_t nb = nbr(g, s, coord, mu, fwd);
-                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
+                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
             }
         } else {
 #pragma unroll 1
             for (int mu = 0; mu < 4; mu += 2) {
                 const uint32_t n0 = nbr(g, s, coord, mu, fwd), n1 = nbr(g, s, coord, mu + 1, fwd);
-                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
-                hop<R, RPT, TIL, LNK, LT>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * V, V, n1,
+                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
+                hop<R, RPT, TIL, LNK, LT>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * Vt, n1,
                                  fwd ? s : n1, tile, s0, lsg(mu + 1, fwd), lu + (size_t)(mu + 1) * NE * kBlock);
             }
         }
@@ -227,14 +228,14 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
             const int mu = d >> 1;
             const bool fwd = (d & 1) == 0;
             const uint32_t nb = nbr(g, s, coord, mu, fwd);
-            hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * V, V, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
+            hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
         }
     } else {
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
-            hop<R, RPT, TIL, LNK, LT>(mu, true, acc, psi, U + (size_t)mu * NE * V, V, fw, s, tile, s0, lsg(mu, true), lu + (size_t)(mu) * NE * kBlock);
-            hop<R, RPT, TIL, LNK, LT>(mu, false, acc, psi, U + (size_t)mu * NE * V, V, bw, bw, tile, s0, lsg(mu, false), lu + (size_t)(mu) * NE * kBlock);
+            hop<R, RPT, TIL, LNK, LT>(mu, true, acc, psi, U + (size_t)mu * NE * Vt, fw, s, tile, s0, lsg(mu, true), lu + (size_t)(mu) * NE * kBlock);
+            hop<R, RPT, TIL, LNK, LT>(mu, false, acc, psi, U + (size_t)mu * NE * Vt, bw, bw, tile, s0, lsg(mu, false), lu + (size_t)(mu) * NE * kBlock);
         }
     }
 }
@@ -268,7 +269,7 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
     }
     if (!any) return;
     constexpr int NT = kBlock * SPL;
-    const uint32_t V = (uint32_t)g.V;
+    const uint32_t V = (uint32_t)g.V, Vt = (uint32_t)g.Vt;
     const int h = SPL == 2 ? (int)(threadIdx.x & 1u) : 0;
     const uint32_t s = (uint32_t)sb * kBlock + (SPL == 2 ? threadIdx.x >> 1 : threadIdx.x);
     const bool valid = s < V;
@@ -278,7 +279,7 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
     for (int r = 0; r < RPT; ++r) dre[r] = dim[r] = dqq[r] = drr[r] = 0.0;
     const C2<R>* psi[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) psi[r] = in + (size_t)(n0 + (on[r] ? r : 0)) * 12 * V;
+    for (int r = 0; r < RPT; ++r) psi[r] = in + (size_t)(n0 + (on[r] ? r : 0)) * 12 * Vt;
     cx<R> acc[RPT][4][3];
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
@@ -297,7 +298,7 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
             for (int r = 0; r < RPT; ++r)
 #pragma unroll
                 for (int comp = 0; comp < 12; ++comp) {
-                    const cx<R> v = ld<R>(psi[r], (uint32_t)comp * V + s);
+                    const cx<R> v = ld<R>(psi[r], tix((uint32_t)comp, s, 12));
                     C2<R> w;
                     w.x = v.re;
                     w.y = v.im;
@@ -335,8 +336,8 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (!on[r]) continue;
-            C2<R>* o = out + (size_t)(n0 + r) * 12 * V;
-            const C2<R>* rd = (MODE == 1) ? rdot + (size_t)(n0 + r) * 12 * V : nullptr;
+            C2<R>* o = out + (size_t)(n0 + r) * 12 * Vt;
+            const C2<R>* rd = (MODE == 1) ? rdot + (size_t)(n0 + r) * 12 * Vt : nullptr;
 #pragma unroll
             for (int ai = 0; ai < NA; ++ai) {
                 const int a = SPL == 2 ? 2 * h + ai : ai;
@@ -348,19 +349,19 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
                         const C2<R> w = lt[(r * 12 + (int)comp) * kBlock + threadIdx.x];
                         p = mk<R>(w.x, w.y);
                     } else {
-                        p = ld<R>(psi[r], comp * V + s);
+                        p = ld<R>(psi[r], tix(comp, s, 12));
                     }
                     // D psi = psi - kappa acc ; H = gamma5 D
                     cx<R> hv = p - kappa * acc[r][ai][c];
                     if (a >= 2) hv = -hv;
                     if constexpr (MODE == 0) {
-                        stc<R>(o, comp * V + s, hv);
+                        stc<R>(o, tix(comp, s, 12), hv);
                     } else {
                         // q = zs p - H p
                         const R zr = (R)zsr, zi = (R)zsi;
                         cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
-                        stc<R>(o, comp * V + s, q);
-                        const cx<R> rv = ld<R>(rd, comp * V + s);
+                        stc<R>(o, tix(comp, s, 12), q);
+                        const cx<R> rv = ld<R>(rd, tix(comp, s, 12));
                         // <r, q> = sum conj(r) q, accumulated in FP64
                         dre[r] += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
                         dim[r] += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
@@ -421,19 +422,19 @@ __device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2
     for (int r = 0; r < RB; ++r)
         if (r == w) on = onr[r];
     const int n = grp * RB + w;
-    const uint32_t V = (uint32_t)g.V;
+    const uint32_t V = (uint32_t)g.V, Vt = (uint32_t)g.Vt;
     const uint32_t s0 = (uint32_t)sb * kBlock;
     const uint32_t s = s0 + t;
     const bool valid = s < V;
     __shared__ C2<R> lu[4 * NE * kBlock];
     for (uint32_t q = threadIdx.x; q < 4 * NE * (uint32_t)kBlock; q += NT) {
         const uint32_t me = q / (uint32_t)kBlock, tt = q % (uint32_t)kBlock;
-        if (s0 + tt < V) lu[q] = U[(size_t)me * V + s0 + tt];
+        if (s0 + tt < V) lu[q] = U[(size_t)(me / NE) * NE * Vt + tix(me % NE, s0 + tt, NE)];
     }
     __syncthreads();
     double dre = 0.0, dim = 0.0, dqq = 0.0, drr = 0.0;
     if (valid && on) {
-        const C2<R>* psi[1] = {in + (size_t)n * 12 * V};
+        const C2<R>* psi[1] = {in + (size_t)n * 12 * Vt};
         cx<R> acc[1][4][3];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -446,23 +447,23 @@ __device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2
         coord[2] = (int)(rem % (uint32_t)g.L[2]);
         coord[3] = (int)(rem / (uint32_t)g.L[2]);
         dslash_site<R, HPI, 1, 1, 0, LNK, 1>(acc, psi, U, g, s, coord, 0, nullptr, s0, lu);
-        C2<R>* o = out + (size_t)n * 12 * V;
-        const C2<R>* rd = (MODE == 1) ? rdot + (size_t)n * 12 * V : nullptr;
+        C2<R>* o = out + (size_t)n * 12 * Vt;
+        const C2<R>* rd = (MODE == 1) ? rdot + (size_t)n * 12 * Vt : nullptr;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const uint32_t comp = (uint32_t)(3 * a + c);
-                const cx<R> p = ld<R>(psi[0], comp * V + s);
+                const cx<R> p = ld<R>(psi[0], tix(comp, s, 12));
                 cx<R> hv = p - kappa * acc[0][a][c];
                 if (a >= 2) hv = -hv;
                 if constexpr (MODE == 0) {
-                    stc<R>(o, comp * V + s, hv);
+                    stc<R>(o, tix(comp, s, 12), hv);
                 } else {
                     const R zr = (R)zsr, zi = (R)zsi;
                     cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
-                    stc<R>(o, comp * V + s, q);
-                    const cx<R> rv = ld<R>(rd, comp * V + s);
+                    stc<R>(o, tix(comp, s, 12), q);
+                    const cx<R> rv = ld<R>(rd, tix(comp, s, 12));
                     dre += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
                     dim += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
                     dqq += (double)q.re * (double)q.re + (double)q.im * (double)q.im;
