@@ -224,7 +224,9 @@ int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
  *   4 r update with the shift sweep FP64           5 the same in FP32
  *   6 basis sum s = sum h_k r_k                    7 scalar kernels
  * Algorithmic bytes count every array element the kernel must read or write
- * once (links once per launch, neighbour spinors once). */
+ * once (links once per launch, neighbour spinors once); for classes 0-3 they
+ * count the sources still iterating in each launch (a launch in which every
+ * source has finished returns at once: it adds its time, and no bytes). */
 int ovl_set_profiling(ovl_ctx* ctx, int32_t enable);
 int ovl_get_profile(const ovl_ctx* ctx, int32_t kclass, double* total_ms, int64_t* launches,
                     double* bytes);

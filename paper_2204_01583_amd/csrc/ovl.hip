@@ -983,11 +983,10 @@ void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
     ovl_ctx* lead = B.ctx[0];
     const int c32 = sizeof(R) == 4 ? 1 : 0;
     const double es = sizeof(C2<R>);
-    double sten_b = 0, vec_b = 0, sweep_b = 0;
+    double vec_b = 0, sweep_b = 0;
     if (prof) {
         for (size_t i = 0; i < B.w.size(); ++i) {
             const double V = (double)B.ctx[i]->g.V, n = B.w[i]->nsrc, N = 12 * V;
-            sten_b += V * es * ((B.lnk[c32] ? 24.0 : 36.0) + 36.0 * n);
             vec_b += 3.0 * es * N * n;
             const bool ref = B.form == OVL_FORM_REFERENCE;
             sweep_b += N * (n * (2.0 * es + (ref ? 0.0 : 32.0)));
@@ -999,7 +998,8 @@ void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
     const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
     for (int i = 0; i < count; ++i) {
         {
-            ProfScope ps(lead, s, prof ? 0 + c32 : -1, sten_b, true);
+            // bytes credited after the solve from the sources' live iterations
+            ProfScope ps(lead, s, prof ? 0 + c32 : -1, 0.0, true);
             launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
                                   B.sten_total[c32], var, B.lnk[c32], s, ps.start(), ps.stop());
         }
@@ -1007,7 +1007,7 @@ void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
             // K2: r update (r, q read, r written) plus p update (p read and
             // written) or the sweep
             ProfScope ps(lead, s, prof ? (sweep ? 4 + c32 : 2 + c32) : -1,
-                         sweep ? vec_b + sweep_b : 5.0 / 3.0 * vec_b, true);
+                         sweep ? vec_b + sweep_b : 0.0, true);
             launch_iteration_update<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
                                        B.kdev + ((i + 1) & 1), B.vec_total, B.form, B.maxJ, s,
                                        ps.start(), ps.stop());
@@ -1138,6 +1138,38 @@ PollResult read_state(Batch& B, int slot, int k_host, hipEvent_t ev, int* rc_out
 }
 
 }  // namespace
+
+// Profiling: algorithmic bytes of the stencil classes and of the r/p update
+// of the basis and two-pass forms, from the sources' live iterations (the
+// per-launch records cannot know them: a launch in which every source has
+// finished returns at once and moves nothing).  A source live for iterations
+// 0 .. iter-1 ran min(iter, k_switch) of them in FP64 and the rest in FP32;
+// a job's links are read once per launch in which any of its sources is live.
+void credit_live_bytes(const Batch& B, int k_switch) {
+    ovl_ctx* lead = B.ctx[0];
+    if (!lead->prof_on) return;
+    const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
+    for (size_t i = 0; i < B.w.size(); ++i) {
+        const ovl_ctx* c = B.ctx[i];
+        const Work& w = *B.w[i];
+        const double V = (double)c->g.V;
+        const SrcState* hs = reinterpret_cast<const SrcState*>(c->host_state);
+        for (int f = 0; f < 2; ++f) {
+            const double es = f ? (double)sizeof(float2) : (double)sizeof(double2);
+            double sum = 0.0;
+            int mx = 0;
+            for (int n = 0; n < w.nsrc; ++n) {
+                const int it = std::min(hs[n].iter, w.maxk);
+                const int n64 = k_switch < 0 ? it : std::min(it, k_switch);
+                const int itf = f ? it - n64 : n64;
+                sum += itf;
+                mx = std::max(mx, itf);
+            }
+            lead->prof_bytes[0 + f] += V * es * (36.0 * sum + (B.lnk[f] ? 24.0 : 36.0) * mx);
+            if (!sweep) lead->prof_bytes[2 + f] += 5.0 * 12.0 * V * es * sum;
+        }
+    }
+}
 
 // Runs the shifted solver for every job of a batch (their sources packed in
 // w->b64) and leaves s = sum_j c_j y_j in each w->s64.  Work is enqueued on
@@ -1276,6 +1308,7 @@ static int solve_batch(Batch& B) {
     if (((k_host / kChunk) & 1) != 0)
         for (size_t i = 0; i < B.w.size(); ++i)
             memcpy(B.ctx[i]->host_state, host_slot(B.ctx[i], *B.w[i], 1), B.w[i]->state_bytes);
+    credit_live_bytes(B, k_switch);
     const int k_run = k_host;
     if (status == OVL_OK && !P.all_done) status = OVL_NOT_CONVERGED;
     for (size_t i = 0; i < B.w.size(); ++i) {
@@ -1342,6 +1375,7 @@ static int solve_batch(Batch& B) {
                 rc = run_chunk(B, low2, graphs, s, nact_known);
                 if (rc) return rc;
             }
+            credit_live_bytes(B, k_switch);  // the second pass repeats the same iterations
             HIPCHK(lead, hipGetLastError());
         }
     }
