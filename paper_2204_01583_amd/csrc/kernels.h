@@ -67,6 +67,10 @@ template <typename R>
 void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
                              int vec_blocks_total, int form, int maxJ, hipStream_t s,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// state block of every job into its pinned host slot (k / chunk) & 1, with k
+// read from kdev (the iteration counter after a chunk)
+void launch_export_state(const JobDesc* jobs, int njobs, const int* kdev, int chunk,
+                         hipStream_t s);
 // two-pass form, second pass: s = h_0 b
 void launch_s_init(const double2* b, const double2* h, int maxk, double2* s, int64_t n12, int nsrc,
                    hipStream_t st);

@@ -187,6 +187,22 @@ void launch_axpy(double2* y, const double2* x, double a, int64_t n, hipStream_t 
                        x, a, n);
 }
 
+// One block per job: copy the job's state block into pinned host slot
+// (k / chunk) & 1, k the iteration counter after the chunk.
+__global__ __launch_bounds__(kBlock) void k_export_state(const JobDesc* __restrict__ jobs,
+                                                         const int* __restrict__ kdev, int chunk) {
+    const JobDesc& J = jobs[blockIdx.x];
+    if (J.state_host == nullptr) return;
+    const int slot = (*kdev / chunk) & 1;
+    const uint2* src = reinterpret_cast<const uint2*>(J.state_dev);
+    uint2* dst = reinterpret_cast<uint2*>(J.state_host + (size_t)slot * J.state_stride);
+    for (int e = threadIdx.x; e < J.state_bytes / 8; e += kBlock) dst[e] = src[e];
+}
+void launch_export_state(const JobDesc* jobs, int njobs, const int* kdev, int chunk,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_export_state, dim3(njobs), dim3(kBlock), 0, s, jobs, kdev, chunk);
+}
+
 void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, a, b, n);
@@ -613,12 +629,32 @@ __global__ __launch_bounds__(kBlock) void k_coef(const double2* __restrict__ h_a
     if (j >= J) return;
     const int K = st[n].iter;
     const int64_t hb = (int64_t)n * (maxk + 1) * J;
+    // The loads of a group of U steps do not depend on the recurrence: issue
+    // them together, then run the U steps, so a step costs arithmetic rather
+    // than a memory latency.  Same operations in the same order as one step
+    // at a time.
+    constexpr int U = 8;
     double2 P = make_double2(0, 0);
-    for (int i = K - 1; i >= 0; --i) {
-        const double2 a = h_a[hb + (int64_t)i * J + j], b = h_b[hb + (int64_t)i * J + j];
-        P = cadd(a, cmul(b, P));
-        const double2 pi = (i == 0) ? make_double2(1, 0) : h_pi[hb + (int64_t)i * J + j];
-        W[hb + (int64_t)i * J + j] = cdiv(P, pi);
+    for (int i0 = K - 1; i0 >= 0; i0 -= U) {
+        double2 a[U], b[U], pi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 - u;
+            if (i >= 0) {
+                const int64_t o = hb + (int64_t)i * J + j;
+                a[u] = h_a[o];
+                b[u] = h_b[o];
+                pi[u] = (i == 0) ? make_double2(1, 0) : h_pi[o];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 - u;
+            if (i >= 0) {
+                P = cadd(a[u], cmul(b[u], P));
+                W[hb + (int64_t)i * J + j] = cdiv(P, pi[u]);
+            }
+        }
     }
 }
 // h[src][i] = sum_j c_j W[src][i][j] (fixed order)

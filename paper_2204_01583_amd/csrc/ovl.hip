@@ -1013,6 +1013,9 @@ void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
                                        ps.start(), ps.stop());
         }
     }
+    // the chunk's final state to the pinned host slots (the counter after an
+    // even number of iterations is in slot 0)
+    launch_export_state(B.desc_dev, (int)B.desc.size(), B.kdev + (count & 1), kChunk, s);
 }
 
 // Capture (once per key) and replay a graph of kChunk iterations in precision R.
@@ -1092,16 +1095,9 @@ struct PollResult {
     int iters = 0, nact = 0;
 };
 
-// Queues the copy of every job's device state into pinned slot `slot` and
-// records ev after it.
-int post_state(Batch& B, int slot, hipStream_t s, hipEvent_t ev) {
-    for (size_t i = 0; i < B.w.size(); ++i) {
-        ovl_ctx* c = B.ctx[i];
-        Work& w = *B.w[i];
-        char* dst = reinterpret_cast<char*>(c->host_state) + (size_t)slot * state_slot_bytes(w);
-        if (hipMemcpyAsync(dst, w.st, w.state_bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
-            return fail(B.ctx[0], OVL_E_HIP, "state copy failed");
-    }
+// Records ev after a chunk, whose last kernel has exported every job's state
+// into pinned slot (chunk index & 1).
+int post_state(Batch& B, hipStream_t s, hipEvent_t ev) {
     if (hipEventRecord(ev, s) != hipSuccess) return fail(B.ctx[0], OVL_E_HIP, "event record failed");
     return OVL_OK;
 }
@@ -1211,6 +1207,14 @@ static int solve_batch(Batch& B) {
     for (size_t i = 0; i < B.w.size(); ++i) {
         fill_desc(B.ctx[i], *B.w[i], B.desc[i], vars, B.lnk, sb, vb);
         B.maxJ = std::max(B.maxJ, B.w[i]->J);
+        // the chunk kernels export the state into the pinned slots
+        JobDesc& d = B.desc[i];
+        void* hdev = nullptr;
+        HIPCHK(lead, hipHostGetDevicePointer(&hdev, B.ctx[i]->host_state, 0));
+        d.state_dev = reinterpret_cast<const char*>(B.w[i]->st);
+        d.state_host = static_cast<char*>(hdev);
+        d.state_bytes = (int)B.w[i]->state_bytes;
+        d.state_stride = (int)state_slot_bytes(*B.w[i]);
     }
     B.sten_total[0] = sb[0];
     B.sten_total[1] = sb[1];
@@ -1254,7 +1258,7 @@ static int solve_batch(Batch& B) {
         if (r) return r;
         k_enq += kChunk;
         const int slot = (k_enq / kChunk) & 1;
-        return post_state(B, slot, s, pev[slot]);
+        return post_state(B, s, pev[slot]);
     };
     // Look-ahead: while the largest shifted residual is far above the next
     // decision point (the precision switch, then the tolerance), the chunk
@@ -1362,6 +1366,7 @@ static int solve_batch(Batch& B) {
                 if (rc) return rc;
                 launch_s_init(w.b64, w.h, w.maxk, w.s64, w.N, w.nsrc, s);
                 B.desc[i].h = w.h;
+                B.desc[i].state_host = nullptr;  // the host keeps the first pass's final state
             }
             HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(), B.desc.size() * sizeof(JobDesc),
                                         hipMemcpyHostToDevice, s));

@@ -161,6 +161,13 @@ struct JobDesc {
     const double2* h;           // two-pass, second pass: h[src][i] weights of r_i
     int ksw;                    // first FP32 iteration (slots from it hold FP32), or large
     int form;                   // OVL_FORM_* of this solve
+    // state export at the end of each chunk: the state block (SrcState array,
+    // active counts, residual maxima; state_bytes, a multiple of 8) goes to
+    // pinned host slot (k / chunk) & 1, state_stride bytes apart; none if
+    // state_host is null
+    const char* state_dev;
+    char* state_host;           // device address of the pinned slots
+    int state_bytes, state_stride;
 };
 
 // r_k and r_{k+1} of a job (element pointers of source 0; sources are 12V apart)
