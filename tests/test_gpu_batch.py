@@ -38,6 +38,30 @@ def test_graph_replay_equals_eager(precision, form, monkeypatch):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision,form", [(1, 2), (1, 3), (0, 1), (0, 2)])
+def test_lookahead_equals_chunk_by_chunk(precision, form):
+    """Normally the solver keeps one chunk queued ahead of the state poll
+    (away from the precision switch and convergence), and each chunk graph
+    ends by exporting the state to pinned host memory; with profiling on it
+    polls every chunk before queueing the next.  Results, iteration counts
+    and the FP64/FP32 split must agree bit for bit, with a tolerance that
+    ends the solve several chunks in."""
+    dims = (4, 4, 4, 6)
+    U = gauge(dims, 0.3, 3)
+    b = to_dev(si.gaussian_sources(dims, 2, first_seed=21))
+    ctx = make_ctx(dims, U, nq=16, precision=precision, form=form)
+    a, sa = ctx.apply_sign(b)
+    ctx.set_profiling(True)
+    p, sp = ctx.apply_sign(b)
+    ctx.set_profiling(False)
+    a2, _ = ctx.apply_sign(b)
+    print(f"prec {precision} form {form}: iterations {sa.iterations} ({sa.fp32_iterations} FP32)")
+    assert sa.iterations > 128           # many chunks, look-ahead on for most
+    assert (sa.iterations, sa.fp32_iterations) == (sp.iterations, sp.fp32_iterations)
+    assert bool((a == p).all()) and bool((a2 == p).all())
+    ctx.close()
+
+
 def test_twopass_equals_basis():
     dims = (8, 8, 8, 8)
     U = gauge(dims, 0.3, 0)
