@@ -1,8 +1,9 @@
 // HIP kernels for gfx950: layout conversion, the seed iteration's vector
 // kernels with their deterministic reductions and shifted-system scalars, the
 // shift sweeps and the basis-form sum.  Everything here is bandwidth bound (no
-// dense contraction), so the kernels stream structure-of-arrays vectors with
-// one lane per complex component.  The stencil is in stencil.hip.
+// dense contraction), so the kernels stream the vectors (tiled, 12 Vt complex
+// elements per source) with one lane per element or pair of elements.  The
+// stencil is in stencil.hip.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -441,7 +442,7 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
     C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
     if constexpr (!SWEEP && sizeof(R) == 4) {
         // FP32: two components per lane in one 16-byte access of each array
-        // (every vector starts 16-byte aligned and 12V is even)
+        // (every vector starts 16-byte aligned and 12 Vt is even)
         const bool acc2 = J.h != nullptr;
         const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
         double2* sacc = J.s64 + (size_t)n * n12;

@@ -147,17 +147,17 @@ struct JobDesc {
     SrcState* st;
     ShiftDev sh;
     double4* part_w;            // [nsrc][nsb]: <r_k, q> (re, im), ||q||^2, ||r_k||^2 per block
-    // working vectors [nsrc][12V], index [0] FP64, [1] FP32
+    // working vectors [nsrc][12 Vt], index [0] FP64, [1] FP32
     void* p[2];
     void* q[2];
     void* r[2];                 // fused/reference: r in place; two-pass: r_k at r[..] + (k&1) * rpp
     size_t rpp;                 // two-pass: element offset of the second r buffer
     double2* b64;               // packed source
     double2* s64;               // quadrature sum
-    void* pj[2];                // sweep forms: [nsrc][J][12V]
+    void* pj[2];                // sweep forms: [nsrc][J][12 Vt]
     double2* xj;                // reference form
     char* const* slots;         // basis form: device table of slot-chunk bases
-    size_t slot_bytes;          // bytes of one slot (nsrc * 12V FP64 complex)
+    size_t slot_bytes;          // bytes of one slot (nsrc * 12 Vt FP64 complex)
     const double2* h;           // two-pass, second pass: h[src][i] weights of r_i
     int ksw;                    // first FP32 iteration (slots from it hold FP32), or large
     int form;                   // OVL_FORM_* of this solve
@@ -170,7 +170,7 @@ struct JobDesc {
     int state_bytes, state_stride;
 };
 
-// r_k and r_{k+1} of a job (element pointers of source 0; sources are 12V apart)
+// r_k and r_{k+1} of a job (element pointers of source 0; sources are 12 Vt apart)
 template <typename T>
 __device__ __forceinline__ T* job_rk(const JobDesc& J, int k, int fp32) {
     if (J.form == 2) {  // basis: slot k (FP32 slots packed at the slot base)

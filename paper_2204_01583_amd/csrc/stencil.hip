@@ -1,9 +1,10 @@
 // The hermitian Wilson stencil H_W = gamma5 D_W(-m0) for gfx950 (HIP).
 // Bandwidth bound (at most ~3.6 flop per algorithmic byte in FP64), so no
-// matrix cores: one or two lanes per site (and rhs), structure-of-arrays
-// spinors and links, 32-bit offsets from uniform bases, an XCD-aware block
-// order, an optional LDS tile of the block's sites, and 24
-// register/latency/locality trade-off variants chosen by the autotuner.
+// matrix cores: one or two lanes per site (and rhs), tiled spinors and links
+// (64-site tiles, components contiguous within a tile), 32-bit offsets from
+// uniform bases, an XCD-aware block order, optional LDS tiles of the block's
+// sites or links, and 28 register/latency/locality trade-off variants chosen
+// by the autotuner.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
