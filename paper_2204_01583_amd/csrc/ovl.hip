@@ -33,8 +33,8 @@ struct DBuf {
         p = nullptr;
         bytes = 0;
         hipError_t e = hipMalloc(&p, nb);
-        if (e == hipSuccess) e = hipMemset(p, 0, nb);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemsetAsync(p, 0, nb, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);  // the fill, not other streams' work
         if (e == hipSuccess) {
             bytes = nb;
         } else if (p) {
