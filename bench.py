@@ -236,8 +236,8 @@ def main():
                          "size for scaling the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the path shards over contour nodes with one "
-              "final reduction, which this build does not run; use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: sharding over contour nodes with one final "
+              "reduction is designed but not implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
