@@ -34,6 +34,27 @@ def test_force_matches_oracle(dims, chunk):
     ctx.close()
 
 
+@pytest.mark.parametrize("dims,bc", [((3, 2, 2, 4), (1, 1, 1, -1)), ((2, 3, 2, 4), (1, -1, 1, 1))])
+def test_force_partial_tile_and_boundaries(dims, bc):
+    """48 sites: the internal layouts hold one 64-site tile with 16 padding
+    sites, which the force's site loops must leave out; the second case moves
+    the antiperiodic direction to y."""
+    m0, mq, nq = 1.4, 0.1, 16
+    U = gauge(dims, 0.3, 4)
+    phi = si.gaussian_sources(dims, 1, first_seed=17)[0]
+    z, c = nodes(nq, *CIRCLE)
+    G_ref, F_ref, S_ref = oracle_force(U, phi, m0, mq, z, c, bc=bc, method="dense")
+    ctx = make_ctx(dims, U, m0, mq, nq, form=2, tol=1e-13, bc=bc)
+    G, S, st = ctx.force(to_dev(phi), kind=1, shift_chunk=3)
+    F, _, _ = ctx.force(to_dev(phi), kind=0)
+    eG = relerr(G.cpu().numpy(), G_ref)
+    eF = relerr(F.cpu().numpy(), F_ref)
+    print(f"{dims} bc {bc}: S {S:.12e} vs {S_ref:.12e}, G err {eG:.2e}, F err {eF:.2e}")
+    assert abs(S - S_ref) / S_ref < 1e-11
+    assert eG < 1e-10 and eF < 1e-10
+    ctx.close()
+
+
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 16)])
 def test_force_finite_differences(dims):
     """Central differences (h = 1e-6) of S(U) = |D_ov phi|^2 through the

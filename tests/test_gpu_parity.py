@@ -394,6 +394,29 @@ def test_sign_ragged_lattice_below_one_tile():
             ctx.close()
 
 
+def test_sign_partial_layout_tile_two_sources():
+    """Volumes that are not a multiple of the 64-site layout tile (360 and 180
+    sites: 24 and 12 padding sites in the last tile), two sources (so the
+    second one starts 12 Vt elements in), basis, two-pass and fused forms in
+    FP64 and mixed precision, against the oracle."""
+    from oracle.sign import sign_by_solves
+    from oracle.contour import nodes
+    for dims in ((3, 5, 4, 6), (5, 3, 3, 4)):
+        U = gauge(dims, 0.3, 5)
+        H = oracle_H(dims, 0.3, 5, 1.4)
+        b = si.gaussian_sources(dims, 2, first_seed=81)
+        z, c = nodes(16, *CIRCLE)
+        refs = [sign_by_solves(H, b[n].ravel(), z, c, method="gmres", processes=NPROC)
+                for n in range(2)]
+        for precision, form, tol in ((0, 2, 1e-11), (1, 2, 1e-10), (1, 3, 1e-10), (0, 1, 1e-11)):
+            ctx = make_ctx(dims, U, nq=16, precision=precision, form=form)
+            s, _ = ctx.apply_sign(to_dev(b))
+            for n in range(2):
+                err = relerr(s[n].cpu().numpy(), refs[n])
+                assert err < tol, (dims, precision, form, n, err)
+            ctx.close()
+
+
 def test_sign_invariants_16x16x16x16_bench_configuration():
     """At the benchmark's size and launch configuration (16^4, roughness 0.3,
     4 sources, 2 x 128 circle nodes, mixed precision, basis form), properties
