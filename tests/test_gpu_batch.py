@@ -84,7 +84,7 @@ def test_batched_uneven_lattices(precision, form):
     job carrying the stored 8^4 workload matches the oracle."""
     from paper_2204_01583_amd import ovl
     specs = [((8, 8, 8, 8), 0.3, 0), ((4, 4, 6, 6), 0.2, 1), ((6, 6, 6, 8), 0.4, 2),
-             ((4, 4, 4, 4), 0.3, 3)]
+             ((4, 4, 4, 4), 0.3, 3), ((3, 5, 4, 6), 0.3, 4)]    # the last with a partial layout tile
     nq = 64
     ctxs, ins = [], []
     for dims, r, seed in specs:

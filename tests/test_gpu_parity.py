@@ -408,12 +408,19 @@ def test_sign_partial_layout_tile_two_sources():
         z, c = nodes(16, *CIRCLE)
         refs = [sign_by_solves(H, b[n].ravel(), z, c, method="gmres", processes=NPROC)
                 for n in range(2)]
+        mq = 0.1
         for precision, form, tol in ((0, 2, 1e-11), (1, 2, 1e-10), (1, 3, 1e-10), (0, 1, 1e-11)):
-            ctx = make_ctx(dims, U, nq=16, precision=precision, form=form)
+            ctx = make_ctx(dims, U, mq=mq, nq=16, precision=precision, form=form)
             s, _ = ctx.apply_sign(to_dev(b))
+            d, _ = ctx.apply_dov(to_dev(b))
             for n in range(2):
                 err = relerr(s[n].cpu().numpy(), refs[n])
                 assert err < tol, (dims, precision, form, n, err)
+                # D_ov b = (1 + mq)/2 b + (1 - mq)/2 gamma5 sgn b, gamma5 = diag(1, 1, -1, -1)
+                g5s = refs[n].reshape(-1, 4, 3) * np.array([1, 1, -1, -1])[None, :, None]
+                dref = 0.5 * (1 + mq) * b[n].ravel() + 0.5 * (1 - mq) * g5s.ravel()
+                errd = relerr(d[n].cpu().numpy(), dref)
+                assert errd < tol, (dims, precision, form, n, errd)
             ctx.close()
 
 
