@@ -715,10 +715,54 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const C2<R>* __restrict__ slots
     }
     sacc[n * n12 + e] = o;
 }
+
+// FP32 slots, two elements per lane: the same sums in the same order as k_gemv
+__global__ __launch_bounds__(kBlock) void k_gemv2(const float4* __restrict__ slots,
+                                                  int64_t slot_stride2, int64_t src_stride2,
+                                                  const double2* __restrict__ h, int maxk,
+                                                  const SrcState* __restrict__ st, int g0, int l0,
+                                                  int l1, double2* __restrict__ sacc,
+                                                  int accumulate, int64_t n12) {
+    const int n = blockIdx.y;
+    const int64_t e2 = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // element pair
+    if (2 * e2 >= n12) return;
+    const int K = st[n].iter + 1;  // r_0 .. r_K exist; h is zero beyond K-1
+    const int lend = (K - g0) < l1 ? (K - g0) : l1;
+    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+    const double2* hh = h + (int64_t)n * (maxk + 1) + g0;
+    const float4* base = slots + n * src_stride2 + e2;
+    for (int l = l0; l < lend; ++l) {
+        const double2 c = hh[l];
+        const float4 v = base[(int64_t)l * slot_stride2];
+        re0 += c.x * (double)v.x - c.y * (double)v.y;
+        im0 += c.x * (double)v.y + c.y * (double)v.x;
+        re1 += c.x * (double)v.z - c.y * (double)v.w;
+        im1 += c.x * (double)v.w + c.y * (double)v.z;
+    }
+    double2 o0 = make_double2(re0, im0), o1 = make_double2(re1, im1);
+    double2* out = sacc + n * n12 + 2 * e2;
+    if (accumulate) {
+        const double2 p0 = out[0], p1 = out[1];
+        o0.x += p0.x;
+        o0.y += p0.y;
+        o1.x += p1.x;
+        o1.y += p1.y;
+    }
+    out[0] = o0;
+    out[1] = o1;
+}
 template <typename R>
 void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_stride,
                        const double2* h, int maxk, const SrcState* st, int g0, int l0, int l1,
                        double2* sacc, bool accumulate, int64_t n12, int nsrc, hipStream_t s) {
+    if constexpr (sizeof(R) == 4) {
+        // two elements per lane in one 16-byte access per slot (12 Vt and the
+        // element strides are even, the slot bases 16-byte aligned)
+        dim3 grid((unsigned)((n12 / 2 + kBlock - 1) / kBlock), nsrc);
+        hipLaunchKernelGGL(k_gemv2, grid, dim3(kBlock), 0, s, (const float4*)slots, slot_stride / 2,
+                           src_stride / 2, h, maxk, st, g0, l0, l1, sacc, (int)accumulate, n12);
+        return;
+    }
     dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock), nsrc);
     hipLaunchKernelGGL(k_gemv<R>, grid, dim3(kBlock), 0, s, (const C2<R>*)slots, slot_stride,
                        src_stride, h, maxk, st, g0, l0, l1, sacc, (int)accumulate, n12);
