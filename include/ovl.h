@@ -31,7 +31,16 @@
  *
  * Streams: every call enqueues on the context's HIP stream (ovl_set_stream).
  * Calls that take an ovl_stats* synchronise that stream once at the end and
- * fill it; they return only after the result is complete in `out`.
+ * fill it; they return only after the result is complete in `out`.  The
+ * solves run on an internal stream of the context (default priority) that
+ * waits for the caller's stream on entry and is waited for on exit; the
+ * host reads the solver state once per 16 iterations, with the next 16
+ * already queued while the residuals are far from the precision switch and
+ * the tolerance.
+ *
+ * Memory: work buffers (internal vectors, the stored basis, job tables) are
+ * allocated on the context's device on first use, zero-filled, grown when a
+ * later call needs more, and freed by ovl_destroy.
  *
  * Errors: every call returns an int status.  It never aborts or throws.
  * On an error the output buffers are unspecified and ovl_last_error(ctx)
@@ -95,8 +104,10 @@ int ovl_set_stream(ovl_ctx* ctx, void* hip_stream);
 
 /* Copy the gauge field (complex128 [4][Lt][Lz][Ly][Lx][3][3], device) into
  * the context's internal layout; the caller may free U afterwards.  The
- * links are used as given (no unitarity check), so H_W stays hermitian for
- * any complex 3x3 links. */
+ * links are used as given, so H_W stays hermitian for any complex 3x3
+ * links.  When every link is SU(3) to rounding (|U U^dag - 1| and
+ * |det U - 1| below 1e-12) the stencil may also store two rows per link and
+ * rebuild the third; other fields keep the full matrices. */
 int ovl_set_gauge(ovl_ctx* ctx, const void* U_dev);
 
 /* m0 > 0 is the negative Wilson mass of H_W = gamma5 D_W(-m0) (paper: after
