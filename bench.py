@@ -140,6 +140,48 @@ def batched_uneven(torch, ovl):
             "err_vs_own_fp64_solve": errs}
 
 
+def force_workload(torch, ovl):
+    """The derivative of S = |D_ov phi|^2 with respect to every link (ovl_force,
+    the traceless hermitian force) at 8^4 and 16^4: roughness 0.3, seed 0,
+    m0 = 1.4, m_q = 0.1, 2 x 64 circle nodes, one Gaussian phi, basis form, FP64
+    and mixed.  Median wall time of three evaluations after a warm-up; mixed
+    against FP64 as the relative 2-norm difference of F."""
+    import numpy as np
+    import seeded_inputs as si
+    out = {}
+    for dims in ((8, 8, 8, 8), (16, 16, 16, 16)):
+        U = torch.from_numpy(si.gauge_field(dims, 0.3, 0)).to("cuda:0")
+        phi = torch.from_numpy(np.ascontiguousarray(
+            si.gaussian_sources(dims, 1, first_seed=2000))).to("cuda:0")
+        c = ovl.Context(dims, device=0)
+        c.set_gauge(U)
+        c.set_masses(M0, MQ)
+        c.set_contour(64, *CIRCLE)
+        row, F64 = {}, None
+        for name, prec in (("fp64", ovl.PREC_FP64), ("mixed", ovl.PREC_MIXED)):
+            c.set_solver(prec, ovl.FORM_BASIS, tol=TOL, maxiter=4000, switch_res=SWITCH)
+            c.force(phi, kind=0)                          # warm-up (tuning, graphs, buffers)
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F, S, st = c.force(phi, kind=0)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[name] = {"seconds": round(float(np.median(ts)), 4), "action": S,
+                         "iterations_per_solve": st.iterations}
+            if F64 is None:
+                F64 = F.clone()
+            else:
+                row[name]["rel_diff_vs_fp64"] = float((F - F64).norm() / F64.norm())
+        c.close()
+        out["x".join(map(str, dims))] = row
+    out["note"] = ("one force = two shifted solves (phi and psi = (1-m_q)/2 gamma5 D_ov phi), "
+                   "the per-shift solutions rebuilt from the stored basis, and the per-link "
+                   "contraction over all 128 shifts")
+    return out
+
+
 def paper_workload(torch, ovl):
     """The workload of the paper's Table I and Fig. 4 on seeded stand-in fields:
     8^4, m0 = 1, the paper's ellipse (alpha 0.1, rho 1.1999, gamma +-1.2),
@@ -225,6 +267,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-lattice run")
+    ap.add_argument("--no-force", action="store_true", help="skip the force timing")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the paper's 8^4 sigma / timing workload")
     ap.add_argument("--only-steps", action="store_true",
@@ -374,6 +417,14 @@ def main():
         log("batched uneven lattices")
         rec["batched"] = batched_uneven(torch, ovl)
         log(f"batched: {rec['batched']['seconds']}s, {rec['batched']['applies_per_s']} applies/s")
+    if not args.no_force:
+        log("force")
+        try:
+            rec["force"] = force_workload(torch, ovl)
+            log(f"force: {json.dumps(rec['force']['16x16x16x16'])}")
+        except Exception as e:  # a secondary row must not cost the bench line
+            rec["force"] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"force failed: {e}")
     del Ud, Bd
     torch.cuda.empty_cache()
 
