@@ -96,11 +96,13 @@ void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_strid
 // tiled layout of Vt sites)
 void launch_dov_psi(const double2* b, const double2* s, double2* psi, double a, double bm,
                     int64_t Vt, double* partial, int nblk, hipStream_t st);
-// Y[j] (+)= sum over one slot chunk of u_i^{j0+j} r_i, j < jn, for the source
-// whose slot elements start at element eoff (W already offset to that source)
-void launch_materialize(const char* chunk, size_t slot_bytes, int g0, int l1, int ksw,
-                        const double2* W, int J, int j0, int jn, int K, double2* Y, int64_t n12,
-                        int64_t eoff, bool accumulate, hipStream_t s);
+// Y[j] = sum_{i < K} u_i^{j0+j} r_i, j < jn, for the source whose slot
+// elements start at element eoff (W already offset to that source); chunks is
+// the device table of slot-chunk bases (slot i in chunk i / kSlotChunk),
+// slots below ksw hold FP64, from ksw on FP32
+void launch_materialize(char* const* chunks, size_t slot_bytes, int K, int ksw, const double2* W,
+                        int J, int j0, int jn, double2* Y, int64_t n12, int64_t eoff,
+                        hipStream_t s);
 // partial[blk] = (|b - (z x - H x)|^2, |b|^2) per block over one source
 void launch_true_res(const double2* b, const double2* x, const double2* hx, double2 z,
                      double2* partial, int nblk, int64_t n12, hipStream_t s);

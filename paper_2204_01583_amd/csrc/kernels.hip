@@ -867,24 +867,23 @@ void launch_dov_psi(const double2* b, const double2* s, double2* psi, double a, 
     hipLaunchKernelGGL(k_dov_psi, dim3(nblk), dim3(kBlock), 0, st, b, s, psi, a, bm, Vt, partial);
 }
 
-// Y[j][e] (+)= sum_{i in one slot chunk} u_i^{j} r_i[e] for shifts j0 .. j0+JG-1
-// of one source; slots below ksw hold FP64, from ksw on FP32 (at the slot base).
+// Y[j][e] = sum_{i < K} u_i^{j} r_i[e] for shifts j0 .. j0+jn-1 (jn <= JG) of
+// one source: every stored slot in turn (FP64 below ksw, FP32 from it, at
+// the slot base), through the device table of slot chunks, each output
+// written once.  The basis is read once per group of JG shifts.
 template <int JG>
-__global__ __launch_bounds__(kBlock) void k_materialize(const char* __restrict__ chunk,
-                                                        size_t slot_bytes, int g0, int l1,
-                                                        int ksw, const double2* __restrict__ W,
-                                                        int J, int j0, int jn, int K,
-                                                        double2* __restrict__ Y, int64_t n12,
-                                                        int64_t eoff, int accumulate) {
+__global__ __launch_bounds__(kBlock) void k_materialize(char* const* __restrict__ chunks,
+                                                        size_t slot_bytes, int K, int ksw,
+                                                        const double2* __restrict__ W, int J,
+                                                        int j0, int jn, double2* __restrict__ Y,
+                                                        int64_t n12, int64_t eoff) {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n12) return;
     double re[JG], im[JG];
 #pragma unroll
     for (int q = 0; q < JG; ++q) re[q] = im[q] = 0.0;
-    const int lend = (K - g0) < l1 ? (K - g0) : l1;
-    for (int l = 0; l < lend; ++l) {
-        const int i = g0 + l;
-        const char* slot = chunk + (size_t)l * slot_bytes;
+    for (int i = 0; i < K; ++i) {
+        const char* slot = chunks[i / kSlotChunk] + (size_t)(i % kSlotChunk) * slot_bytes;
         double vr, vi;
         if (i < ksw) {
             const double2 v = reinterpret_cast<const double2*>(slot)[eoff + e];
@@ -906,29 +905,18 @@ __global__ __launch_bounds__(kBlock) void k_materialize(const char* __restrict__
         }
     }
 #pragma unroll
-    for (int q = 0; q < JG; ++q) {
-        if (q < jn) {
-            double2* y = Y + (size_t)q * n12 + e;
-            double2 o = make_double2(re[q], im[q]);
-            if (accumulate) {
-                const double2 prev = *y;
-                o.x += prev.x;
-                o.y += prev.y;
-            }
-            *y = o;
-        }
-    }
+    for (int q = 0; q < JG; ++q)
+        if (q < jn) Y[(size_t)q * n12 + e] = make_double2(re[q], im[q]);
 }
-constexpr int kMatGroup = 8;
-void launch_materialize(const char* chunk, size_t slot_bytes, int g0, int l1, int ksw,
-                        const double2* W, int J, int j0, int jn, int K, double2* Y, int64_t n12,
-                        int64_t eoff, bool accumulate, hipStream_t s) {
+constexpr int kMatGroup = 16;
+void launch_materialize(char* const* chunks, size_t slot_bytes, int K, int ksw, const double2* W,
+                        int J, int j0, int jn, double2* Y, int64_t n12, int64_t eoff,
+                        hipStream_t s) {
     dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock));
     for (int q0 = 0; q0 < jn; q0 += kMatGroup) {
         const int m = jn - q0 < kMatGroup ? jn - q0 : kMatGroup;
-        hipLaunchKernelGGL(k_materialize<kMatGroup>, grid, dim3(kBlock), 0, s, chunk, slot_bytes,
-                           g0, l1, ksw, W, J, j0 + q0, m, K, Y + (size_t)q0 * n12, n12, eoff,
-                           (int)accumulate);
+        hipLaunchKernelGGL(k_materialize<kMatGroup>, grid, dim3(kBlock), 0, s, chunks, slot_bytes,
+                           K, ksw, W, J, j0 + q0, m, Y + (size_t)q0 * n12, n12, eoff);
     }
 }
 

@@ -1700,14 +1700,10 @@ static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y, 
     if (K < 0) K = w.K;
     const int ksw = w.k_switch < 0 ? K + 1 : w.k_switch;
     const double2* Wn = w.W + (size_t)n * (w.maxk + 1) * w.J;
-    bool acc = false;
-    for (int c0 = 0; c0 < K; c0 += kSlotChunk) {
-        launch_materialize(w.chunks[c0 / kSlotChunk], w.slot_bytes, c0, kSlotChunk, ksw, Wn, w.J,
-                           j0, jn, K, Y, w.N, (int64_t)n * w.N, acc,
-                           ctx->stream);  // after solve's handoff
-        acc = true;
-    }
-    if (!acc) HIPCHK(ctx, hipMemsetAsync(Y, 0, (size_t)jn * w.N * sizeof(double2), ctx->stream));
+    // on the caller's stream, after the solve's handoff; the slot table on the
+    // device lists every chunk of this solve
+    launch_materialize(w.slot_tab, w.slot_bytes, K, ksw, Wn, w.J, j0, jn, Y, w.N,
+                       (int64_t)n * w.N, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     return OVL_OK;
 }
