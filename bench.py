@@ -231,7 +231,9 @@ def paper_workload(torch, ovl):
 
 def cpu_baseline(U, B, nsample):
     """The FP64 oracle (independent GMRES solve per node) on a stratified sample
-    of the 256 shifted systems of source 0, one node per host core."""
+    of the 256 shifted systems of source 0, one node per host core.  Returns
+    the baseline record, the sampled node indices and the oracle's sum
+    sum_{j in sample} c_j (z_j - H_W)^-1 b_0 over them."""
     import numpy as np
     from oracle.contour import nodes
     from oracle.sign import sign_by_solves
@@ -244,13 +246,13 @@ def cpu_baseline(U, B, nsample):
     step = len(z) // nsample
     pick = np.arange(step // 2, len(z), step)[:nsample]
     t0 = time.time()
-    sign_by_solves(H, B[0].ravel(), z[pick], c[pick], method="gmres", rtol=1e-14,
-                   processes=min(cores, nsample))
+    s_ref = sign_by_solves(H, B[0].ravel(), z[pick], c[pick], method="gmres", rtol=1e-14,
+                           processes=min(cores, nsample))
     wall = time.time() - t0
     used = min(cores, nsample)
     # sample throughput extrapolated linearly to the 256 systems of one application
     per_apply_s = wall * len(z) / nsample
-    return {
+    rec = {
         "value": 1.0 / per_apply_s, "unit": "sgn(H_W)b applies/s", "cores": used,
         "kind": "oracle",
         "sample": (f"{nsample} of the {len(z)} shifted systems of source 0 (every {step}th node), "
@@ -258,6 +260,36 @@ def cpu_baseline(U, B, nsample):
                    f"{used} in parallel; {wall:.1f}s wall, extrapolated linearly to all "
                    f"{len(z)} systems; H_W CSR build ({t_build:.1f}s) not included"),
     }
+    return rec, pick, s_ref
+
+
+def oracle_sample_accuracy(torch, ovl, Ud, B, pick, s_ref):
+    """The GPU path in the benchmark's configuration restricted to the oracle's
+    sampled nodes (ovl_set_nodes with the same z_j, c_j), FP64 and mixed, on
+    source 0: relative 2-norm and element-wise errors against the oracle's
+    sum over the same nodes."""
+    import numpy as np
+    from oracle.contour import nodes
+    z, c = nodes(NQ, *CIRCLE)
+    b0 = torch.from_numpy(np.ascontiguousarray(B[:1])).to("cuda:0")
+    ctx = ovl.Context(DIMS, device=0)
+    ctx.set_gauge(Ud)
+    ctx.set_masses(M0, MQ)
+    ctx.set_nodes(z[pick], c[pick])
+    out = {"nodes": [int(i) for i in pick], "source": 0,
+           "targets": {"fp64": 1e-11, "mixed": 1e-10}}
+    for label, prec in (("fp64", ovl.PREC_FP64), ("mixed", ovl.PREC_MIXED)):
+        ctx.set_solver(prec, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=SWITCH)
+        s, st = ctx.apply_sign(b0)
+        g = s.cpu().numpy().ravel()
+        out[label] = {
+            "rel_err": float(np.linalg.norm(g - s_ref) / np.linalg.norm(s_ref)),
+            "elementwise_rel_err": float(np.abs(g - s_ref).max() / np.abs(s_ref).max()),
+            "iterations": st.iterations, "fp32_iterations": st.fp32_iterations}
+        log(f"oracle sample, {label}: rel err {out[label]['rel_err']:.2e}, "
+            f"element-wise {out[label]['elementwise_rel_err']:.2e}")
+    ctx.close()
+    return out
 
 
 def main():
@@ -425,13 +457,15 @@ def main():
         except Exception as e:  # a secondary row must not cost the bench line
             rec["force"] = {"error": f"{type(e).__name__}: {e}"}
             log(f"force failed: {e}")
-    del Ud, Bd
+    del Bd
     torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("cpu baseline (oracle sample)")
-        rec["cpu_baseline"] = cpu_baseline(U, B, args.cpu_nodes)
+        rec["cpu_baseline"], pick, s_ref = cpu_baseline(U, B, args.cpu_nodes)
         log(f"cpu baseline {rec['cpu_baseline']['value']:.3e} applies/s")
+        # the same sampled nodes on the GPU, against the oracle's sum over them
+        rec["accuracy"]["oracle_sample"] = oracle_sample_accuracy(torch, ovl, Ud, B, pick, s_ref)
     print(json.dumps(rec), flush=True)
 
 

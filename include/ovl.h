@@ -102,12 +102,16 @@ int ovl_create(ovl_ctx** ctx, const int32_t dims[4], const int32_t bc[4],
 int ovl_destroy(ovl_ctx* ctx);
 int ovl_set_stream(ovl_ctx* ctx, void* hip_stream);
 
-/* Copy the gauge field (complex128 [4][Lt][Lz][Ly][Lx][3][3], device) into
- * the context's internal layout; the caller may free U afterwards.  The
- * links are used as given, so H_W stays hermitian for any complex 3x3
- * links.  When every link is SU(3) to rounding (|U U^dag - 1| and
- * |det U - 1| below 1e-12) the stencil may also store two rows per link and
- * rebuild the third; other fields keep the full matrices. */
+/* Copy the gauge field U_mu(x) of the Wilson-Dirac operator (paper: the
+ * links of D_W in eq. (1); the Numerical experiments section uses quenched
+ * SU(3) configurations) from complex128 [4][Lt][Lz][Ly][Lx][3][3] device
+ * memory into the context's internal layout; the caller may free U
+ * afterwards.  The links are used as given, so H_W stays hermitian for any
+ * complex 3x3 links.  When every link is SU(3) to rounding (|U U^dag - 1|
+ * and |det U - 1| below 1e-12) the stencil may also store two rows per link
+ * and rebuild the third; other fields keep the full matrices.
+ * OVL_E_NONFINITE if any entry is NaN or infinite: the context then has no
+ * gauge field (operators return OVL_E_STATE) until a valid one is set. */
 int ovl_set_gauge(ovl_ctx* ctx, const void* U_dev);
 
 /* m0 > 0 is the negative Wilson mass of H_W = gamma5 D_W(-m0) (paper: after
@@ -133,15 +137,21 @@ int ovl_set_contour(ovl_ctx* ctx, int32_t nq, double gamma, double rho, double a
  * the two-contour form give 0.  nq even, 2 <= nq <= 2048. */
 int ovl_set_contour_single(ovl_ctx* ctx, int32_t nq, double gamma, double rho, double alpha);
 
-/* General rational function s = sum_j c_j (z_j - H_W)^-1 b: n nodes given as
- * interleaved host arrays z_reim[2n], c_reim[2n], 1 <= n <= 2048.  Every
- * Im z_j must be nonzero.  Replaces any contour set before. */
+/* General rational function s = sum_j c_j (z_j - H_W)^-1 b (the resolvent
+ * sum of eqs. (5)-(6) with caller-chosen nodes and weights, e.g. a subset of
+ * the eq. (7) nodes): n nodes given as interleaved host arrays z_reim[2n],
+ * c_reim[2n], 1 <= n <= 2048.  Every Im z_j must be nonzero.  Replaces any
+ * contour set before. */
 int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* z_reim, const double* c_reim);
 
 /* precision: OVL_PREC_*; form: OVL_FORM_*; tol: shift j stops when its
  * residual estimate ||r_j|| <= tol*||b||; maxiter: seed iterations;
- * (zseed_re, zseed_im): seed shift, zseed_im != 0; switch_res: the MIXED
- * switch point (ignored for FP64; <= 0 picks 1e-4). */
+ * (zseed_re, zseed_im): seed shift of the shifted BiCG, zseed_im != 0 (the
+ * Supplemental Material's numerical setup uses z_seed = 1 + 0.05i);
+ * switch_res: the MIXED switch point (ignored for FP64; <= 0 picks 1e-4).
+ * precision, form and switch_res go beyond the paper's statement of the
+ * problem (which is FP64 with per-shift directions): they select the
+ * library's extensions. */
 int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, int32_t maxiter,
                    double zseed_re, double zseed_im, double switch_res);
 
@@ -160,6 +170,13 @@ int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample);
 /* out = H_W in for nrhs spinors (eq. (1): H_W = gamma5 D_W(-m0)).  out must
  * not alias in. */
 int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs);
+
+/* The same operator through the FP32 stencil that OVL_PREC_MIXED uses after
+ * its switch: `in` is rounded to complex64, the links are the context's FP32
+ * copy, the arithmetic is FP32, and the result is widened to complex128 in
+ * `out` (same layouts and argument rules as ovl_apply_hw).  For checking the
+ * FP32 kernels; expect relative errors of order 1e-7. */
+int ovl_apply_hw_fp32(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs);
 
 /* out = sum_j c_j (z_j - H_W)^-1 in  (eqs. (5)-(7)) for nrhs spinors.
  * Returns OVL_NOT_CONVERGED (out = last iterate) if maxiter is reached.
@@ -180,7 +197,9 @@ int ovl_apply_dov(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs, ovl_sta
 int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind, int32_t shift_chunk,
               double* action, ovl_stats* st);
 
-/* ovl_apply_sign for several contexts (different lattices allowed) at once:
+/* ovl_apply_sign for several contexts (different lattices allowed) at once
+ * (eqs. (5)-(7) for every context, the independent (field, source) problems
+ * of the Numerical experiments gathered into one solve):
  * out[i] = sum_j c_j (z_j - H_W[ctx i])^-1 in[i] with nrhs[i] spinors; every
  * context must have its gauge field and masses set.  The node set and solver
  * settings of ctxs[0] are used for every context during the call (each

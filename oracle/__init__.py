@@ -17,8 +17,9 @@ What it computes (plain numpy/scipy, complex128 throughout):
   rho w_j / N_q on the ellipses Gamma_+ and Gamma_- (eq. (7)); the weights of
   Gamma_- carry the minus sign of eq. (3).
 * ``sign.sign_by_solves`` -- sum_j c_j y_j with every shifted system
-  (z_j I - H_W) y_j = b (eq. (6)) solved on its own by a sparse direct or an
-  unrestarted GMRES solve (eqs. (5)-(7)).
+  (z_j I - H_W) y_j = b (eq. (6)) solved on its own by a dense or sparse LU
+  solve, or by restarted GMRES(100) accepted only when its true residual is
+  below 10 rtol (eqs. (5)-(7)).
 * ``sign.sign_by_eigh`` -- the same rational filter, and the exact sign, from a
   dense eigendecomposition (eq. (2)); small lattices only.
 * ``sign.overlap`` -- D_ov(m_q) b = (1+m_q)/2 b + (1-m_q)/2 gamma5 s (eq. (1)).

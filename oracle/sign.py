@@ -27,7 +27,6 @@ def _solve_one(H, zj, b, method, rtol):
     elif method == "splu":
         y = spla.splu(A).solve(b)
     elif method == "gmres":
-        # unrestarted GMRES; the stopping test is re-checked on the true residual
         # GMRES(m), m = min(n, 100): scipy preallocates the m-vector basis, and
         # these shifted systems converge without stagnation under restarts.
         # The Arnoldi residual estimate can stall a little above rtol near

@@ -98,9 +98,3 @@ def hermitian_wilson(U, m0, bc=(1, 1, 1, -1)):
     H = sp.coo_matrix((vals[keep], (rows[keep], cols[keep])), shape=(12 * V, 12 * V))
     return H.tocsr()
 
-
-def apply_gamma5(v):
-    """gamma5 applied to spinors whose last two axes are [4][3]."""
-    out = np.array(v, dtype=np.complex128, copy=True)
-    out[..., 2:, :] *= -1
-    return out

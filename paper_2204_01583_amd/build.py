@@ -1,34 +1,50 @@
-"""Build libovl.so (the HIP library behind include/ovl.h) in-tree for gfx950."""
+"""Build libovl.so (the HIP library behind include/ovl.h) in-tree for gfx950.
+
+Each source is compiled to an object on its own (in parallel; no device code
+crosses translation units), then the objects are linked into the library."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libovl.so")
 SOURCES = ["kernels.hip", "stencil.hip", "ovl.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
 
 
-def build(verbose=False):
-    """Compile every HIP source into libovl.so; raises on a compiler error."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
+def _run(cmd):
     res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
     msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
                      if "packed-fp32-ops" not in l and l.strip())
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + msgs)
-    if verbose and msgs:
-        print(msgs, file=sys.stderr)
+    return msgs
+
+
+def build(verbose=False):
+    """Compile every HIP source and link libovl.so; raises on a compiler error."""
+    os.makedirs(OBJ, exist_ok=True)
+    objs = [os.path.join(OBJ, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    cmds = [[HIPCC] + FLAGS + ["-c", os.path.join(CSRC, s), "-o", o]
+            for s, o in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(len(cmds)) as ex:
+        msgs = list(ex.map(_run, cmds))
+    tmp = LIB + ".tmp"
+    msgs.append(_run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]))
+    if verbose:
+        for m in msgs:
+            if m:
+                print(m, file=sys.stderr)
     os.replace(tmp, LIB)
     return LIB
 

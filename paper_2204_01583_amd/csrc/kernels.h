@@ -13,6 +13,8 @@ void launch_pack_spinor32(const double2* ext, float2* in, int64_t V, int64_t Vt,
                           hipStream_t s);
 void launch_unpack_spinor64(const double2* in, double2* ext, int64_t V, int64_t Vt, int n,
                             hipStream_t s);
+void launch_unpack_spinor32(const float2* in, double2* ext, int64_t V, int64_t Vt, int n,
+                            hipStream_t s);
 // out_ext = a*b_ext + bm*gamma5*s_int  (D_ov assembly, eq. (1))
 void launch_unpack_dov(const double2* s_int, const double2* b_ext, double2* out_ext, double a,
                        double bm, int64_t V, int64_t Vt, int n, hipStream_t s);

@@ -34,16 +34,20 @@ __global__ __launch_bounds__(kBlock) void k_pack_spinor(const double2* __restric
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_unpack_spinor(const double2* __restrict__ in,
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_unpack_spinor(const C2<R>* __restrict__ in,
                                                           double2* __restrict__ ext, int64_t V,
                                                           int64_t Vt) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int n = blockIdx.y;
     if (s >= V) return;
-    const double2* src = in + (int64_t)n * 12 * Vt;
+    const C2<R>* src = in + (int64_t)n * 12 * Vt;
     double2* dst = ext + ((int64_t)n * V + s) * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) dst[c] = src[tix64(c, s, 12)];
+    for (int c = 0; c < 12; ++c) {
+        const C2<R> v = src[tix64(c, s, 12)];
+        dst[c] = make_double2((double)v.x, (double)v.y);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_unpack_dov(const double2* __restrict__ sin,
@@ -69,7 +73,8 @@ __global__ __launch_bounds__(kBlock) void k_unpack_dov(const double2* __restrict
 // ext [4][V][9] -> per direction the tiled [Vt/64][9][64] FP64 and FP32, and
 // rows 0 and 1 alone as [Vt/64][6][64]; the boundary sign multiplies the links of the last slice of each
 // direction.  defect[mu][blk] = max over the block's input links of
-// max(|U U^dag - 1|, |det U - 1|) (NaN propagates).
+// max(|U U^dag - 1|, |det U - 1|), or NaN if any input element of the block is
+// NaN or infinite (NaN propagates through the max).
 __global__ __launch_bounds__(kBlock) void k_pack_gauge(const double2* __restrict__ ext,
                                                        double2* __restrict__ U64,
                                                        float2* __restrict__ U32,
@@ -84,8 +89,12 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge(const double2* __restrict
         const double sign = (coord == g.L[mu] - 1) ? (double)g.bc[mu] : 1.0;
         const double2* src = ext + ((int64_t)mu * g.V + s) * 9;
         double2 u[9];
+        bool fin = true;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) u[e] = src[e];
+        for (int e = 0; e < 9; ++e) {
+            u[e] = src[e];
+            fin = fin && isfinite(u[e].x) && isfinite(u[e].y);
+        }
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
             const double2 v = make_double2(u[e].x * sign, u[e].y * sign);
@@ -116,6 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge(const double2* __restrict
         const double2 det = cadd(csub(cmul(u[0], m0), cmul(u[1], m1)), cmul(u[2], m2));
         const double dd = sqrt((det.x - 1.0) * (det.x - 1.0) + det.y * det.y);
         dev = (dev != dev || dd != dd) ? dd + dev : fmax(dev, dd);
+        // a non-finite entry marks the block whatever the products gave
+        // (Inf - Inf is NaN, but Inf alone would only read as "not SU(3)")
+        if (!fin) dev = __builtin_nan("");
     }
     __shared__ double sh[kBlock / 64];
     // max over the block; a NaN anywhere makes the result NaN
@@ -156,7 +168,12 @@ void launch_pack_spinor32(const double2* ext, float2* in, int64_t V, int64_t Vt,
 void launch_unpack_spinor64(const double2* in, double2* ext, int64_t V, int64_t Vt, int n,
                             hipStream_t s) {
     dim3 grid((unsigned)((V + kBlock - 1) / kBlock), n);
-    hipLaunchKernelGGL(k_unpack_spinor, grid, dim3(kBlock), 0, s, in, ext, V, Vt);
+    hipLaunchKernelGGL(k_unpack_spinor<double>, grid, dim3(kBlock), 0, s, in, ext, V, Vt);
+}
+void launch_unpack_spinor32(const float2* in, double2* ext, int64_t V, int64_t Vt, int n,
+                            hipStream_t s) {
+    dim3 grid((unsigned)((V + kBlock - 1) / kBlock), n);
+    hipLaunchKernelGGL(k_unpack_spinor<float>, grid, dim3(kBlock), 0, s, in, ext, V, Vt);
 }
 void launch_unpack_dov(const double2* s_int, const double2* b_ext, double2* out_ext, double a,
                        double bm, int64_t V, int64_t Vt, int n, hipStream_t s) {

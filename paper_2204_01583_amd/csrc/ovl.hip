@@ -338,8 +338,20 @@ extern "C" int ovl_set_gauge(ovl_ctx* ctx, const void* U) {
     HIPCHK(ctx, hipMemcpyAsync(defect.data(), ctx->chk.p, defect.size() * sizeof(double),
                                hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    // the kernel marks a block holding a NaN or infinite entry with NaN; keep
+    // any NaN (std::max would drop it: max(x, NaN) returns x)
     double dmax = 0.0;
-    for (double d : defect) dmax = std::max(dmax, d);  // NaN-safe: NaN fails the test below
+    bool nonfinite = false;
+    for (double d : defect) {
+        if (std::isnan(d)) nonfinite = true;
+        else if (d > dmax) dmax = d;
+    }
+    if (nonfinite) {
+        // the internal links now hold the bad field: no operator may use them
+        ctx->gauge_set = false;
+        ctx->links12 = false;
+        return fail(ctx, OVL_E_NONFINITE, "the gauge field has a NaN or infinite entry");
+    }
     const char* lf = getenv("OVL_LINKS");
     ctx->links12 = dmax < 1e-12 && !(lf && std::strcmp(lf, "full") == 0);
     ctx->gauge_set = true;
@@ -710,6 +722,28 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
                           make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs,
                           ctx->stream, var, lnk);
     launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, ctx->g.Vt, nrhs,
+                           ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    return OVL_OK;
+}
+
+extern "C" int ovl_apply_hw_fp32(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs) {
+    if (!ctx) return OVL_E_ARG;
+    DeviceGuard dg(ctx->device);
+    int rc = check_apply_args(ctx, in, out, nrhs, false);
+    if (rc) return rc;
+    const size_t nb = (size_t)nrhs * n12(ctx) * sizeof(float2);
+    HIPCHK(ctx, ctx->hw_in.ensure(nb));
+    HIPCHK(ctx, ctx->hw_out.ensure(nb));
+    launch_pack_spinor32(static_cast<const double2*>(in), ctx->hw_in.as<float2>(), ctx->g.V, ctx->g.Vt,
+                         nrhs, ctx->stream);
+    const int code = stencil_variant(ctx, nrhs, 1, 0);
+    const int var = code % kStencilVariants, lnk = code / kStencilVariants;
+    launch_wilson<float>(0, ctx->hw_in.as<float2>(), ctx->hw_out.as<float2>(),
+                         stencil_links<float>(ctx, lnk), ctx->g, kappa_of(ctx->m0),
+                         make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs,
+                         ctx->stream, var, lnk);
+    launch_unpack_spinor32(ctx->hw_out.as<float2>(), static_cast<double2*>(out), ctx->g.V, ctx->g.Vt, nrhs,
                            ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     return OVL_OK;
@@ -1178,13 +1212,30 @@ static int solve_batch(Batch& B) {
     if (rc) return rc;
     HIPCHK(lead, hipEventRecord(lead->ev_in, lead->stream));
     HIPCHK(lead, hipStreamWaitEvent(s, lead->ev_in, 0));
+    // On every return from here on, whether the solve succeeded or not, the
+    // caller's stream waits for everything queued on the solve stream (so a
+    // caller never reads buffers the solve may still write), and the timing
+    // events are released.
+    struct SolveScope {
+        ovl_ctx* lead;
+        hipStream_t s;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~SolveScope() {
+            if (hipEventRecord(lead->ev_out, s) == hipSuccess)
+                (void)hipStreamWaitEvent(lead->stream, lead->ev_out, 0);
+            else
+                (void)hipStreamSynchronize(s);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } scope{lead, s};
     const bool mixed = lead->precision == OVL_PREC_MIXED;
     const int form = lead->form;
     const bool graphs = graphs_enabled(lead);
     const int maxk = lead->maxiter;
-    hipEvent_t e0, e1;
-    HIPCHK(lead, hipEventCreate(&e0));
-    HIPCHK(lead, hipEventCreate(&e1));
+    HIPCHK(lead, hipEventCreate(&scope.e0));
+    HIPCHK(lead, hipEventCreate(&scope.e1));
+    hipEvent_t e0 = scope.e0, e1 = scope.e1;
     HIPCHK(lead, hipEventRecord(e0, s));
     // stencil variants: those tuned for the largest job
     size_t big = 0;
@@ -1393,11 +1444,7 @@ static int solve_batch(Batch& B) {
     prof_collect(lead);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    // hand the results back to the caller's stream
-    HIPCHK(lead, hipEventRecord(lead->ev_out, s));
-    HIPCHK(lead, hipStreamWaitEvent(lead->stream, lead->ev_out, 0));
+    // (the results go back to the caller's stream when `scope` ends)
     for (size_t i = 0; i < B.w.size(); ++i) {
         ovl_ctx* c = B.ctx[i];
         Work& w = *B.w[i];

@@ -29,7 +29,7 @@ EXPORTS = [
     "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
     "ovl_set_contour", "ovl_set_contour_single", "ovl_set_nodes", "ovl_set_solver",
     "ovl_set_residual_check", "ovl_spectral_bounds", "ovl_suggest_contour",
-    "ovl_apply_hw", "ovl_apply_sign",
+    "ovl_apply_hw", "ovl_apply_hw_fp32", "ovl_apply_sign",
     "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
     "ovl_bench_kernel", "ovl_set_profiling", "ovl_get_profile", "ovl_status_string",
     "ovl_last_error",
@@ -89,6 +89,7 @@ def load():
         "ovl_spectral_bounds": ([P, I, P], I),
         "ovl_suggest_contour": ([D, D, D, P, P, P], I),
         "ovl_apply_hw": ([P, P, P, I], I),
+        "ovl_apply_hw_fp32": ([P, P, P, I], I),
         "ovl_apply_sign": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "ovl_apply_dov": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "ovl_force": ([P, P, P, I, I, ctypes.POINTER(D), ctypes.POINTER(Stats)], I),
@@ -231,6 +232,17 @@ class Context:
         self._sync_stream()
         self._rc(self.lib.ovl_apply_hw(self._h, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), x.shape[0]), "ovl_apply_hw")
+        return out[0] if squeeze else out
+
+    def apply_hw_fp32(self, x):
+        """H_W x through the FP32 stencil (x rounded to complex64, result widened)."""
+        squeeze = x.dim() == len(self.site_shape) + 2
+        x = self._spinor_in(x)
+        out = torch.empty_like(x)
+        self._sync_stream()
+        self._rc(self.lib.ovl_apply_hw_fp32(self._h, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), x.shape[0]),
+                 "ovl_apply_hw_fp32")
         return out[0] if squeeze else out
 
     def _apply(self, fn, x, allow_not_converged):

@@ -15,9 +15,27 @@ NPROC = min(16, len(os.sched_getaffinity(0)))
 
 
 def relerr(a, b):
+    """Relative 2-norm error ||a - b|| / ||b|| over the whole array."""
     a = np.asarray(a).ravel()
     b = np.asarray(b).ravel()
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def maxerr(a, b):
+    """Element-wise relative error max_i |a_i - b_i| / max_i |b_i|: an error
+    confined to a few elements (a padded tile, a boundary wrap, one block) is
+    not diluted by the size of the array, as it is in relerr."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def assert_close(a, b, tol, what=""):
+    """Both the relative 2-norm error and the element-wise error below tol."""
+    e2, em = relerr(a, b), maxerr(a, b)
+    print(f"{what}: rel 2-norm {e2:.2e}, element-wise {em:.2e} (tol {tol:.0e})")
+    assert e2 < tol and em < tol, (what, e2, em, tol)
+    return e2, em
 
 
 def make_ctx(dims, U, m0=1.4, mq=0.1, nq=None, contour=CIRCLE, precision=0, form=1,
