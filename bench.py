@@ -74,22 +74,27 @@ def roofline_from_profile(prof):
     }
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_stencil32_insolver_16x16x16x16_n4.json")
+def counters_path(kclass):
+    """Committed rocprofv3 counter summary of a kernel class in the benchmark's
+    configuration (16^4, 4 sources, in the solver)."""
+    return os.path.join(ROOT, "profiles", f"hbm_counters_{kclass}_insolver_16x16x16x16_n4.json")
 
 
-def measured_traffic(variant32):
-    """HBM bytes per launch of the in-solver FP32 stencil from the committed
-    rocprofv3 counter summary, or None if that kernel (source or variant) has
-    changed since the counters were taken."""
+def measured_traffic(kclass, variant):
+    """HBM bytes per launch of kernel class `kclass` from its committed
+    rocprofv3 counter summary (scaled FETCH_SIZE + WRITE_SIZE), or None if no
+    summary exists or that kernel (its source file or variant) has changed
+    since the counters were taken."""
     import hashlib
     try:
-        rec = json.load(open(COUNTERS))
-        src = open(os.path.join(ROOT, "paper_2204_01583_amd", "csrc", "stencil.hip"), "rb").read()
-    except OSError:
+        rec = json.load(open(counters_path(kclass)))
+        src = open(os.path.join(ROOT, "paper_2204_01583_amd", "csrc", rec["kernel_source"]),
+                   "rb").read()
+    except (OSError, KeyError, ValueError):
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
         return None
-    if rec.get("variant") != variant32:
+    if rec.get("variant") != variant:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -115,21 +120,32 @@ def batched_uneven(torch, ovl):
             ctxs.append(c)
             ins.append(torch.from_numpy(np.ascontiguousarray(
                 si.gaussian_sources(dims, 8, first_seed=1000))).to("cuda:0"))
-    ovl.apply_sign_batched(ctxs, ins)                 # warm-up (graphs, tuning)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs, st = ovl.apply_sign_batched(ctxs, ins)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    # accuracy of two jobs against their own FP64 solves: the smoothest 12^4
-    # field converges before the batch switches to FP32 (so it is bitwise the
-    # FP64 result), the roughest 16^3x32 field runs most iterations in FP32
-    errs = {}
-    for i, name in ((4, "12x12x12x12_r0.2"), (11, "16x16x16x32_r0.4")):
-        c = ctxs[i]
-        c.set_solver(ovl.PREC_FP64, ovl.FORM_TWOPASS, tol=TOL, maxiter=4000)
-        ref, _ = c.apply_sign(ins[i])
-        errs[name] = float((outs[i] - ref).norm() / ref.norm())
+    def timed(fn):
+        fn()                                          # warm-up (graphs, tuning, buffers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    def set_all(prec):
+        for c in ctxs:
+            c.set_solver(prec, ovl.FORM_TWOPASS, tol=TOL, maxiter=4000, switch_res=SWITCH)
+
+    dt, (outs, st) = timed(lambda: ovl.apply_sign_batched(ctxs, ins))
+    # the same 12 jobs one context at a time (same settings, same kernels)
+    dt_seq, seq = timed(lambda: [c.apply_sign(x)[0] for c, x in zip(ctxs, ins)])
+    # the batch in FP64
+    set_all(ovl.PREC_FP64)
+    dt64, (outs64, st64) = timed(lambda: ovl.apply_sign_batched(ctxs, ins))
+    set_all(ovl.PREC_MIXED)
+    # every job's batched result against its own single solve (the same
+    # iterations in one launch per stage) and against the FP64 batch
+    err_single = max(float((o - r).norm() / r.norm()) for o, r in zip(outs, seq))
+    err_fp64 = {}
+    for i, name in ((0, "8x8x8x8_r0.2"), (4, "12x12x12x12_r0.2"), (11, "16x16x16x32_r0.4")):
+        err_fp64[name] = float((outs[i] - outs64[i]).norm() / outs64[i].norm())
+    err_fp64["max_over_jobs"] = max(float((o - r).norm() / r.norm()) for o, r in zip(outs, outs64))
     for c in ctxs:
         c.close()
     nsrc = 8 * len(ctxs)
@@ -137,7 +153,12 @@ def batched_uneven(torch, ovl):
                         "each, 2x64 nodes, mixed, two-pass form, one batched solve",
             "seconds": round(dt, 4), "applies_per_s": round(nsrc / dt, 3),
             "iterations": st.iterations, "fp32_iterations": st.fp32_iterations,
-            "err_vs_own_fp64_solve": errs}
+            "sequential_seconds": round(dt_seq, 4),
+            "speedup_vs_sequential": round(dt_seq / dt, 3),
+            "fp64_seconds": round(dt64, 4), "fp64_iterations": st64.iterations,
+            "speedup_vs_fp64_batch": round(dt64 / dt, 3),
+            "max_err_vs_single_solves": err_single,
+            "err_vs_fp64_batch": err_fp64}
 
 
 def force_workload(torch, ovl):
@@ -153,32 +174,42 @@ def force_workload(torch, ovl):
         U = torch.from_numpy(si.gauge_field(dims, 0.3, 0)).to("cuda:0")
         phi = torch.from_numpy(np.ascontiguousarray(
             si.gaussian_sources(dims, 1, first_seed=2000))).to("cuda:0")
-        c = ovl.Context(dims, device=0)
-        c.set_gauge(U)
-        c.set_masses(M0, MQ)
-        c.set_contour(64, *CIRCLE)
         row, F64 = {}, None
-        for name, prec in (("fp64", ovl.PREC_FP64), ("mixed", ovl.PREC_MIXED)):
+        for name, prec, chunk in (("fp64", ovl.PREC_FP64, 128), ("mixed", ovl.PREC_MIXED, 128),
+                                  ("mixed_chunk16", ovl.PREC_MIXED, 16)):
+            # a fresh context per row: the drop in free device memory across
+            # it is the context's footprint (links, two bases, work vectors)
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            c = ovl.Context(dims, device=0)
+            c.set_gauge(U)
+            c.set_masses(M0, MQ)
+            c.set_contour(64, *CIRCLE)
             c.set_solver(prec, ovl.FORM_BASIS, tol=TOL, maxiter=4000, switch_res=SWITCH)
-            c.force(phi, kind=0)                          # warm-up (tuning, graphs, buffers)
+            c.force(phi, kind=0, shift_chunk=chunk)     # warm-up (tuning, graphs, buffers)
             ts = []
             for _ in range(3):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                F, S, st = c.force(phi, kind=0)
+                F, S, st = c.force(phi, kind=0, shift_chunk=chunk)
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
+            used = free0 - torch.cuda.mem_get_info()[0] - F.numel() * 16
             row[name] = {"seconds": round(float(np.median(ts)), 4), "action": S,
-                         "iterations_per_solve": st.iterations}
+                         "iterations_per_solve": st.iterations, "shift_chunk": chunk,
+                         "context_device_bytes": int(used)}
             if F64 is None:
                 F64 = F.clone()
             else:
                 row[name]["rel_diff_vs_fp64"] = float((F - F64).norm() / F64.norm())
-        c.close()
+            c.close()
+            del F
         out["x".join(map(str, dims))] = row
-    out["note"] = ("one force = two shifted solves (phi and psi = (1-m_q)/2 gamma5 D_ov phi), "
-                   "the per-shift solutions rebuilt from the stored basis, and the per-link "
-                   "contraction over all 128 shifts")
+    out["note"] = ("one force = two basis-form solves (phi, then psi = (1-m_q)/2 gamma5 D_ov phi at "
+                   "the conjugate nodes) whose bases are kept side by side; the 128 shifted "
+                   "solutions of each are rebuilt shift_chunk at a time and contracted per link; "
+                   "context_device_bytes is the drop in free device memory across the context's "
+                   "life (links, both bases, work vectors)")
     return out
 
 
@@ -278,8 +309,10 @@ def oracle_sample_accuracy(torch, ovl, Ud, B, pick, s_ref):
     ctx.set_nodes(z[pick], c[pick])
     out = {"nodes": [int(i) for i in pick], "source": 0,
            "targets": {"fp64": 1e-11, "mixed": 1e-10}}
-    for label, prec in (("fp64", ovl.PREC_FP64), ("mixed", ovl.PREC_MIXED)):
-        ctx.set_solver(prec, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=SWITCH)
+    for label, prec, theta in (("fp64", ovl.PREC_FP64, SWITCH), ("mixed", ovl.PREC_MIXED, SWITCH),
+                               ("mixed_switch_1e-03", ovl.PREC_MIXED, 1e-3),
+                               ("mixed_switch_1e-02", ovl.PREC_MIXED, 1e-2)):
+        ctx.set_solver(prec, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=theta)
         s, st = ctx.apply_sign(b0)
         g = s.cpu().numpy().ravel()
         out[label] = {
@@ -367,9 +400,9 @@ def main():
     prof = ctx.profile()
     ctx.set_profiling(False)
     name, roof = roofline_from_profile(prof)
-    if name == "stencil32":
-        roof["traffic"] = measured_traffic(st.stencil_variant32)
-    roof["stencil_variant"] = st.stencil_variant32 if name.endswith("32") else st.stencil_variant64
+    variant = st.stencil_variant32 if name.endswith("32") else st.stencil_variant64
+    roof["traffic"] = measured_traffic(name, variant)
+    roof["stencil_variant"] = variant
     rec["roofline"] = roof
     rec["kernel_profile"] = {k: {"ms": round(v[0], 3), "launches": v[1],
                                  "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
@@ -400,6 +433,26 @@ def main():
         rec["accuracy"][f"{label}_true_rel_res_worst_shifts"] = stc.max_true_rel_res
         rec["accuracy"][f"{label}_est_rel_res"] = stc.max_est_rel_res
         log(f"{label}: true residual {stc.max_true_rel_res:.2e} (estimate {stc.max_est_rel_res:.2e})")
+    ctx.set_solver(ovl.PREC_FP64, ovl.FORM_BASIS, tol=TOL, maxiter=3000)
+
+    # ---- the mixed switch point: time and error against the FP64 path
+    sweep = {}
+    for theta in (1e-2, 1e-3, 1e-4):
+        ctx.set_solver(ovl.PREC_MIXED, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=theta)
+        ctx.apply_sign(Bd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sm, stm = ctx.apply_sign(Bd)
+        torch.cuda.synchronize()
+        sweep[f"{theta:.0e}"] = {"seconds": round(time.perf_counter() - t0, 5),
+                                 "err_vs_fp64": max(relerrs(sm, s64)),
+                                 "iterations": stm.iterations,
+                                 "fp32_iterations": stm.fp32_iterations,
+                                 "true_rel_res_worst_shift": stm.max_true_rel_res,
+                                 "fp64_repeat": stm.fp64_repeat}
+        log(f"switch {theta:.0e}: {sweep[f'{theta:.0e}']}")
+        del sm
+    rec["mixed_switch_sweep"] = sweep
     ctx.set_solver(ovl.PREC_FP64, ovl.FORM_BASIS, tol=TOL, maxiter=3000)
 
     # ---- the other solver forms (one application each), FP64 and mixed

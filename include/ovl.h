@@ -86,11 +86,16 @@ typedef struct {
     int32_t n_active_end;      /* shifts still above tolerance at the end (0 if converged)   */
     double  max_est_rel_res;   /* max_j ||r_j|| / ||b|| from the recurrence, at the end      */
     double  seconds;           /* wall time of the apply on the stream                       */
-    int32_t stencil_variant64; /* stencil choice used in FP64 (autotuned; see ovl_bench_kernel) */
+    int32_t stencil_variant64; /* stencil choice used in FP64 (autotuned; see ovl_bench_kernel);
+                                  1000 + v + 8 f for the fused iteration's variant v and link
+                                  format f (basis forms)                                    */
     int32_t stencil_variant32; /* ... in FP32, or -1                                        */
     double  max_true_rel_res;  /* max ||b - (z_j - H) x_j|| / ||b|| over the checked shifts, or
                                   -1 when not checked (see ovl_set_residual_check)           */
-    double  reserved[2];
+    int32_t fp64_repeat;       /* 1 if an OVL_PREC_MIXED apply failed its in-band check and was
+                                  solved again in FP64 (the result is the FP64 one), else 0   */
+    int32_t reserved;
+    double  mixed_true_rel_res;/* with fp64_repeat: the mixed attempt's max_true_rel_res, else -1 */
 } ovl_stats;
 
 /* Create a context for a Lx*Ly*Lz*Lt lattice on HIP device `device`.
@@ -155,16 +160,25 @@ int ovl_set_nodes(ovl_ctx* ctx, int32_t n, const double* z_reim, const double* c
 int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, int32_t maxiter,
                    double zseed_re, double zseed_im, double switch_res);
 
-/* Opt-in check of the recurrence's residual estimates (shift j stops on the
- * estimate ||r_k|| / |pi_k^j|, not on its true residual).  After each
- * ovl_apply_sign / ovl_apply_dov, for the `nsample` shifts of each rhs with
- * the largest final estimate, x_j is formed (stored by OVL_FORM_REFERENCE,
- * rebuilt from the stored basis by OVL_FORM_BASIS) and
- * ||b - (z_j - H_W) x_j|| / ||b|| is computed with one more stencil; the
- * maximum goes to ovl_stats.max_true_rel_res.  The fused and two-pass forms
- * keep no x_j and report -1.  The check synchronises the stream and costs one
- * basis sum per checked shift.  nsample in [0, 64]; 0 (default) turns it off.
- * Returns OVL_E_ARG for an out-of-range nsample. */
+/* True-residual checks of the recurrence's residual estimates (shift j stops
+ * on the estimate ||r_k|| / |pi_k^j|, not on its true residual).
+ * In-band check (OVL_FORM_BASIS, on by default): after every solve, the
+ * shift of each rhs with the largest final estimate has its solution
+ * x_j = sum_i u_i^j r_i rebuilt in the same pass over the stored basis that
+ * forms the sum s (one more output vector), and its true residual
+ * ||b - (z_j - H_W) x_j|| / ||b|| is computed in FP64 with one more FP64
+ * stencil; the maximum over the rhs goes to ovl_stats.max_true_rel_res.  In
+ * OVL_PREC_MIXED, when every shift met tol by its estimate but this true
+ * residual exceeds 10 tol (the FP32 phase drifted), the apply is solved again
+ * in FP64 (ovl_stats.fp64_repeat = 1); if that also misses, the call returns
+ * OVL_NOT_CONVERGED.  The other forms report -1 for the in-band check.
+ * nsample >= 1 adds a synchronous diagnostic after each ovl_apply_sign /
+ * ovl_apply_dov: for the nsample shifts of each rhs with the largest final
+ * estimate, x_j is formed (stored by OVL_FORM_REFERENCE, rebuilt from the
+ * stored basis by OVL_FORM_BASIS) and its true residual computed with one
+ * more stencil; max_true_rel_res becomes the maximum of both checks.
+ * nsample = 0 (default) keeps the in-band check only; nsample = -1 turns the
+ * in-band check off as well.  nsample in [-1, 64], else OVL_E_ARG. */
 int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample);
 
 /* out = H_W in for nrhs spinors (eq. (1): H_W = gamma5 D_W(-m0)).  out must
@@ -187,13 +201,19 @@ int ovl_apply_sign(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs, ovl_st
 int ovl_apply_dov(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs, ovl_stats* st);
 
 /* Derivative of S = phi^dag D_ov^dag D_ov phi (one phi) with respect to the
- * links, through adjoint shifted solves (dS = 2 Re sum_j c_j X_j^dag dH Y_j,
- * Y_j = (z_j-H)^-1 phi, X_j = (conj z_j - H)^-1 psi, psi = (1-m_q)/2 gamma5 D_ov phi).
+ * links (eq. (1) with the resolvent form of the sign under eq. (4); the
+ * paper gives no force), through adjoint shifted solves:
+ * dS = 2 Re sum_j c_j X_j^dag dH Y_j, Y_j = (z_j-H)^-1 phi,
+ * X_j = (conj z_j - H)^-1 psi, psi = (1-m_q)/2 gamma5 D_ov phi.
  * kind 0: the traceless hermitian force F with dS/dh = sum tr(Omega F) for
  *         U -> exp(i h Omega) U;  kind 1: the complex gradient G with
- *         dS = Re sum conj(G) dU (PyTorch's convention).
- * *action (host, may be NULL) receives S.  shift_chunk bounds how many
- * shifted solutions are held at once (<= 0: all). */
+ *         dS = Re sum conj(G) dU (PyTorch's convention);  kind 2: S only
+ *         (one solve; grad is not touched and may be NULL).
+ * *action (host, may be NULL) receives S.  Two basis-form solves (phi, then
+ * psi at the conjugate nodes) keep their stored bases side by side; the
+ * shifted solutions Y_j and X_j are never all held: they are rebuilt from the
+ * bases shift_chunk shifts at a time (<= 0: all at once) and contracted per
+ * link, so the work space is the two bases plus 2 shift_chunk vectors. */
 int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind, int32_t shift_chunk,
               double* action, ovl_stats* st);
 
@@ -253,10 +273,14 @@ int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
  *   2 r and p update FP64 (one kernel)             3 the same in FP32
  *   4 r update with the shift sweep FP64           5 the same in FP32
  *   6 basis sum s = sum h_k r_k                    7 scalar kernels
+ *   8 fused iteration FP64 (basis forms: r_k and   9 the same in FP32
+ *     q_k = A r_k + beta q_{k-1} in one kernel)
  * Algorithmic bytes count every array element the kernel must read or write
- * once (links once per launch, neighbour spinors once); for classes 0-3 they
- * count the sources still iterating in each launch (a launch in which every
- * source has finished returns at once: it adds its time, and no bytes). */
+ * once (links once per launch, neighbour spinors once); for classes 0-3, 8
+ * and 9 they count the sources still iterating in each launch (a launch in
+ * which every source has finished returns at once: it adds its time, and no
+ * bytes).  Class 8/9 moves per live source r_{k-1} and q_{k-1} (read) and r_k
+ * and q_k (written), plus the links once per launch. */
 int ovl_set_profiling(ovl_ctx* ctx, int32_t enable);
 int ovl_get_profile(const ovl_ctx* ctx, int32_t kclass, double* total_ms, int64_t* launches,
                     double* bytes);

@@ -69,6 +69,17 @@ template <typename R>
 void launch_iteration_update(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
                              int vec_blocks_total, int form, int maxJ, hipStream_t s,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// The fused one-kernel seed iteration of the basis forms (stencil.hip): kernel
+// k forms r_k and q_k = A r_k + beta q_{k-1} without the direction p, and
+// advances the shifts by iteration k-1; reads k from kread, writes k + 1 to
+// kwrite.  Variants 0 .. kIterVariants-1: hops per loop step (bit 0), block
+// order (bit 1), LDS tile of the block's r_k (bit 2).
+constexpr int kIterVariants = 8;
+int iter_grid_blocks(const Geom& g, int nrhs);
+template <typename R>
+void launch_iter_jobs(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
+                      int total_blocks, int variant, int lnk, hipStream_t s,
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // state block of every job into its pinned host slot (k / chunk) & 1, with k
 // read from kdev (the iteration counter after a chunk)
 void launch_export_state(const JobDesc* jobs, int njobs, const int* kdev, int chunk,
@@ -87,11 +98,17 @@ void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t 
 void launch_basis_coef(const double2* h_a, const double2* h_b, const double2* h_pi,
                        const double2* c, const SrcState* st, double2* W, double2* h, int J,
                        int maxk, int nsrc, hipStream_t s);
-// s[src] (+)= sum_{l in [l0,l1)} h[src][g0+l] * slot_l[src] over one chunk of slots of type R
+// s[src] (+)= sum_{l in [l0,l1)} h[src][g0+l] * slot_l[src] over one chunk of slots of type R;
+// with hx non-null also xc[src] (+)= sum_l hx[src][g0+l] * slot_l[src] in the same pass
 template <typename R>
 void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_stride,
-                       const double2* h, int maxk, const SrcState* st, int g0, int l0, int l1,
-                       double2* sacc, bool accumulate, int64_t n12, int nsrc, hipStream_t s);
+                       const double2* h, const double2* hx, int maxk, const SrcState* st, int g0,
+                       int l0, int l1, double2* sacc, double2* xc, bool accumulate, int64_t n12,
+                       int nsrc, hipStream_t s);
+// per source, the shift with the largest final residual estimate: its basis
+// coefficients W[src][i][j] into hx[src][i] and its node z[j] into zc[src]
+void launch_pick_check(const double* res, const double2* W, const double2* z, const SrcState* st,
+                       int J, int maxk, int nsrc, double2* hx, double2* zc, hipStream_t s);
 
 // ---- force ------------------------------------------------------------------
 // d = a b + bm gamma5 s, psi = bm gamma5 d, partial[blk] = |d|^2 (one source,
@@ -108,6 +125,10 @@ void launch_materialize(char* const* chunks, size_t slot_bytes, int K, int ksw, 
 // partial[blk] = (|b - (z x - H x)|^2, |b|^2) per block over one source
 void launch_true_res(const double2* b, const double2* x, const double2* hx, double2 z,
                      double2* partial, int nblk, int64_t n12, hipStream_t s);
+// the same for nsrc sources (source n against node zc[n]); partial[n][blk]
+void launch_true_res_multi(const double2* b, const double2* x, const double2* hx,
+                           const double2* zc, double2* partial, int nblk, int64_t n12, int nsrc,
+                           hipStream_t s);
 // per-link accumulation of sum_j c_j X_j^dag dH Y_j; on the last chunk writes
 // the complex gradient (kind 1) or the traceless hermitian force (kind 0)
 void launch_force(const double2* X, const double2* Y, const double2* c, int jn, const Geom& g,

@@ -9,6 +9,7 @@
 
 #include "device_util.h"
 #include "kernels.h"
+#include "seed_iter.h"
 
 namespace ovl {
 
@@ -270,75 +271,9 @@ __device__ __forceinline__ VecBlock vec_block(const JobDesc* jobs, int njobs) {
     return VecBlock{j, local / jobs[j].nbe, local % jobs[j].nbe};
 }
 
-// Seed scalars of iteration k from the stencil's per-block partials:
-//   alpha_k = ||r_k||^2 / <r_k, q_k>,   q_k = A_s p_k,
-//   ||r_{k+1}||^2 = ||r_k - alpha q||^2 = |alpha|^2 ||q||^2 - ||r_k||^2
-//     (alpha <r,q> = ||r||^2 is real), clamped at 0,
-//   beta_k = (alpha / conj(alpha)) ||r_{k+1}||^2 / ||r_k||^2.
-// The next stencil pass measures ||r_{k+1}||^2 from the vector itself, so
-// alpha_{k+1} is always taken from the true residual.
-struct SeedScalars {
-    double2 alpha, beta;
-    double rr, rrn;
-    int status;
-};
+// seed scalars of iteration k from the stencil's partials of source n
 __device__ __forceinline__ SeedScalars seed_scalars(const JobDesc& J, int n, double* shm) {
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    const double4* pw = J.part_w + (size_t)n * J.nsb;
-    for (int b = threadIdx.x; b < J.nsb; b += kBlock) {
-        const double4 v = pw[b];
-        a0 += v.x;
-        a1 += v.y;
-        a2 += v.z;
-        a3 += v.w;
-    }
-    a0 = block_sum<kBlock>(a0, shm);
-    a1 = block_sum<kBlock>(a1, shm);
-    a2 = block_sum<kBlock>(a2, shm);
-    a3 = block_sum<kBlock>(a3, shm);
-    SeedScalars r;
-    const double2 rq = make_double2(a0, a1);
-    r.rr = a3;
-    r.status = 0;
-    if (!finite2(rq) || !isfinite(a2) || !isfinite(a3)) r.status = OVL_E_NONFINITE;
-    else if (cabs2(rq) <= 1e-300 * a3) r.status = OVL_E_BREAKDOWN;
-    if (r.status) {
-        r.alpha = r.beta = make_double2(0, 0);
-        r.rrn = 0;
-        return r;
-    }
-    r.alpha = cdiv(make_double2(a3, 0.0), rq);
-    r.rrn = fmax(cabs2(r.alpha) * a2 - a3, 0.0);
-    const double2 ph = cdiv(r.alpha, make_double2(r.alpha.x, -r.alpha.y));
-    const double ratio = r.rrn / a3;
-    r.beta = make_double2(ph.x * ratio, ph.y * ratio);
-    return r;
-}
-
-// Per-shift scalars of iteration k for shift j (active at the start of k):
-//   pi_{k+1} = (1 + alpha Dz_j) pi_k + (alpha beta_{k-1}/alpha_{k-1}) (pi_k - pi_{k-1})
-//   alpha^j = alpha pi_k / pi_{k+1},  beta^j = (pi_k / pi_{k+1})^2 beta,
-//   shifted residual estimate ||r_{k+1}|| / |pi_{k+1}| / ||b||.
-struct ShiftScalars {
-    double2 pn, aj, bj, ipi;
-    double res;
-};
-__device__ __forceinline__ ShiftScalars shift_scalars(const ShiftDev& sh, size_t o, int j, int k,
-                                                      const SeedScalars& sc, double2 c1, double bb) {
-    const size_t stride3 = (size_t)sh.nsrc * sh.J;
-    const double2 p = sh.pi[(size_t)(k % 3) * stride3 + o];
-    const double2 pp = sh.pi[(size_t)((k + 2) % 3) * stride3 + o];
-    const double2 dz = sh.dz[j];
-    const double2 al = sc.alpha;
-    const double2 one_ad = make_double2(1.0 + (al.x * dz.x - al.y * dz.y), al.x * dz.y + al.y * dz.x);
-    ShiftScalars t;
-    t.pn = cadd(cmul(one_ad, p), cmul(c1, csub(p, pp)));
-    const double2 rt = cdiv(p, t.pn);
-    t.aj = cmul(al, rt);
-    t.bj = cmul(cmul(rt, rt), sc.beta);
-    t.ipi = cdiv(make_double2(1.0, 0.0), t.pn);
-    t.res = sqrt(sc.rrn / cabs2(t.pn) / bb);
-    return t;
+    return seed_scalars_from(J.part_w + (size_t)n * J.nsb, J.nsb, shm);
 }
 
 // The seed iteration's second kernel (after the stencil), for every form:
@@ -702,27 +637,38 @@ void launch_basis_coef(const double2* h_a, const double2* h_b, const double2* h_
 
 // s[src] = (s[src] +) sum_l h[src][g0 + l] * slot_l[src] over local slots
 // l0 <= l < l1 of one contiguous chunk whose slot 0 is global slot g0;
-// slots at or beyond K_src + 1 are skipped (they were never written).
+// slots at or beyond K_src + 1 are skipped (they were never written).  With
+// hx != null the same pass also forms xc[src] (+)= sum_l hx[src][g0 + l] *
+// slot_l[src]: one shifted solution, rebuilt for its true-residual check at
+// the cost of one more output stream.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_gemv(const C2<R>* __restrict__ slots,
                                                  int64_t slot_stride, int64_t src_stride,
-                                                 const double2* __restrict__ h, int maxk,
+                                                 const double2* __restrict__ h,
+                                                 const double2* __restrict__ hx, int maxk,
                                                  const SrcState* __restrict__ st, int g0, int l0,
                                                  int l1, double2* __restrict__ sacc,
-                                                 int accumulate, int64_t n12) {
+                                                 double2* __restrict__ xc, int accumulate,
+                                                 int64_t n12) {
     const int n = blockIdx.y;
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n12) return;
     const int K = st[n].iter + 1;  // r_0 .. r_K exist; h is zero beyond K-1
     const int lend = (K - g0) < l1 ? (K - g0) : l1;
-    double re = 0.0, im = 0.0;
+    double re = 0.0, im = 0.0, xr = 0.0, xi = 0.0;
     const double2* hh = h + (int64_t)n * (maxk + 1) + g0;
+    const double2* hc = hx ? hx + (int64_t)n * (maxk + 1) + g0 : nullptr;
     const C2<R>* base = slots + n * src_stride + e;
     for (int l = l0; l < lend; ++l) {
         const double2 c = hh[l];
         const C2<R> v = base[(int64_t)l * slot_stride];
         re += c.x * (double)v.x - c.y * (double)v.y;
         im += c.x * (double)v.y + c.y * (double)v.x;
+        if (hc) {
+            const double2 u = hc[l];
+            xr += u.x * (double)v.x - u.y * (double)v.y;
+            xi += u.x * (double)v.y + u.y * (double)v.x;
+        }
     }
     double2 o = make_double2(re, im);
     if (accumulate) {
@@ -731,22 +677,35 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const C2<R>* __restrict__ slots
         o.y += prev.y;
     }
     sacc[n * n12 + e] = o;
+    if (hc) {
+        double2 ox = make_double2(xr, xi);
+        if (accumulate) {
+            const double2 prev = xc[n * n12 + e];
+            ox.x += prev.x;
+            ox.y += prev.y;
+        }
+        xc[n * n12 + e] = ox;
+    }
 }
 
 // FP32 slots, two elements per lane: the same sums in the same order as k_gemv
 __global__ __launch_bounds__(kBlock) void k_gemv2(const float4* __restrict__ slots,
                                                   int64_t slot_stride2, int64_t src_stride2,
-                                                  const double2* __restrict__ h, int maxk,
+                                                  const double2* __restrict__ h,
+                                                  const double2* __restrict__ hx, int maxk,
                                                   const SrcState* __restrict__ st, int g0, int l0,
                                                   int l1, double2* __restrict__ sacc,
-                                                  int accumulate, int64_t n12) {
+                                                  double2* __restrict__ xc, int accumulate,
+                                                  int64_t n12) {
     const int n = blockIdx.y;
     const int64_t e2 = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // element pair
     if (2 * e2 >= n12) return;
     const int K = st[n].iter + 1;  // r_0 .. r_K exist; h is zero beyond K-1
     const int lend = (K - g0) < l1 ? (K - g0) : l1;
     double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+    double xr0 = 0.0, xi0 = 0.0, xr1 = 0.0, xi1 = 0.0;
     const double2* hh = h + (int64_t)n * (maxk + 1) + g0;
+    const double2* hc = hx ? hx + (int64_t)n * (maxk + 1) + g0 : nullptr;
     const float4* base = slots + n * src_stride2 + e2;
     for (int l = l0; l < lend; ++l) {
         const double2 c = hh[l];
@@ -755,6 +714,13 @@ __global__ __launch_bounds__(kBlock) void k_gemv2(const float4* __restrict__ slo
         im0 += c.x * (double)v.y + c.y * (double)v.x;
         re1 += c.x * (double)v.z - c.y * (double)v.w;
         im1 += c.x * (double)v.w + c.y * (double)v.z;
+        if (hc) {
+            const double2 u = hc[l];
+            xr0 += u.x * (double)v.x - u.y * (double)v.y;
+            xi0 += u.x * (double)v.y + u.y * (double)v.x;
+            xr1 += u.x * (double)v.z - u.y * (double)v.w;
+            xi1 += u.x * (double)v.w + u.y * (double)v.z;
+        }
     }
     double2 o0 = make_double2(re0, im0), o1 = make_double2(re1, im1);
     double2* out = sacc + n * n12 + 2 * e2;
@@ -767,29 +733,93 @@ __global__ __launch_bounds__(kBlock) void k_gemv2(const float4* __restrict__ slo
     }
     out[0] = o0;
     out[1] = o1;
+    if (hc) {
+        double2 x0 = make_double2(xr0, xi0), x1 = make_double2(xr1, xi1);
+        double2* xo = xc + n * n12 + 2 * e2;
+        if (accumulate) {
+            const double2 p0 = xo[0], p1 = xo[1];
+            x0.x += p0.x;
+            x0.y += p0.y;
+            x1.x += p1.x;
+            x1.y += p1.y;
+        }
+        xo[0] = x0;
+        xo[1] = x1;
+    }
 }
 template <typename R>
 void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_stride,
-                       const double2* h, int maxk, const SrcState* st, int g0, int l0, int l1,
-                       double2* sacc, bool accumulate, int64_t n12, int nsrc, hipStream_t s) {
+                       const double2* h, const double2* hx, int maxk, const SrcState* st, int g0,
+                       int l0, int l1, double2* sacc, double2* xc, bool accumulate, int64_t n12,
+                       int nsrc, hipStream_t s) {
     if constexpr (sizeof(R) == 4) {
         // two elements per lane in one 16-byte access per slot (12 Vt and the
         // element strides are even, the slot bases 16-byte aligned)
         dim3 grid((unsigned)((n12 / 2 + kBlock - 1) / kBlock), nsrc);
         hipLaunchKernelGGL(k_gemv2, grid, dim3(kBlock), 0, s, (const float4*)slots, slot_stride / 2,
-                           src_stride / 2, h, maxk, st, g0, l0, l1, sacc, (int)accumulate, n12);
+                           src_stride / 2, h, hx, maxk, st, g0, l0, l1, sacc, xc, (int)accumulate,
+                           n12);
         return;
     }
     dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock), nsrc);
     hipLaunchKernelGGL(k_gemv<R>, grid, dim3(kBlock), 0, s, (const C2<R>*)slots, slot_stride,
-                       src_stride, h, maxk, st, g0, l0, l1, sacc, (int)accumulate, n12);
+                       src_stride, h, hx, maxk, st, g0, l0, l1, sacc, xc, (int)accumulate, n12);
 }
-template void launch_basis_gemv<double>(const void*, int64_t, int64_t, const double2*, int,
-                                        const SrcState*, int, int, int, double2*, bool, int64_t,
-                                        int, hipStream_t);
-template void launch_basis_gemv<float>(const void*, int64_t, int64_t, const double2*, int,
-                                       const SrcState*, int, int, int, double2*, bool, int64_t,
-                                       int, hipStream_t);
+template void launch_basis_gemv<double>(const void*, int64_t, int64_t, const double2*,
+                                        const double2*, int, const SrcState*, int, int, int,
+                                        double2*, double2*, bool, int64_t, int, hipStream_t);
+template void launch_basis_gemv<float>(const void*, int64_t, int64_t, const double2*,
+                                       const double2*, int, const SrcState*, int, int, int,
+                                       double2*, double2*, bool, int64_t, int, hipStream_t);
+
+// The in-band residual check: for every source pick the shift with the
+// largest final residual estimate res[src][j] (ties: the lower j), and copy
+// its basis coefficients u_i^j = W[src][i][j] into hx[src][i] (zero beyond
+// the source's iteration count) and its node into zc[src].  One block per source.
+__global__ __launch_bounds__(kBlock) void k_pick_check(const double* __restrict__ res,
+                                                       const double2* __restrict__ W,
+                                                       const double2* __restrict__ z,
+                                                       const SrcState* __restrict__ st, int J,
+                                                       int maxk, double2* __restrict__ hx,
+                                                       double2* __restrict__ zc) {
+    const int n = blockIdx.x;
+    double best = -1.0;
+    int bj = 0;
+    for (int j = threadIdx.x; j < J; j += kBlock) {
+        const double v = res[(size_t)n * J + j];
+        if (v > best) {  // strided scan: j increases, so ties keep the lower j
+            best = v;
+            bj = j;
+        }
+    }
+    // block argmax, ties to the lower index
+    __shared__ double sv[kBlock];
+    __shared__ int sj[kBlock];
+    sv[threadIdx.x] = best;
+    sj[threadIdx.x] = bj;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double a = sv[threadIdx.x], b = sv[threadIdx.x + o];
+            const int ja = sj[threadIdx.x], jb = sj[threadIdx.x + o];
+            if (b > a || (b == a && jb < ja)) {
+                sv[threadIdx.x] = b;
+                sj[threadIdx.x] = jb;
+            }
+        }
+        __syncthreads();
+    }
+    const int j = sj[0];
+    const int K = st[n].iter;
+    for (int i = threadIdx.x; i <= maxk; i += kBlock)
+        hx[(size_t)n * (maxk + 1) + i] =
+            i < K ? W[((size_t)n * (maxk + 1) + i) * J + j] : make_double2(0, 0);
+    if (threadIdx.x == 0) zc[n] = z[j];
+}
+void launch_pick_check(const double* res, const double2* W, const double2* z, const SrcState* st,
+                       int J, int maxk, int nsrc, double2* hx, double2* zc, hipStream_t s) {
+    hipLaunchKernelGGL(k_pick_check, dim3(nsrc), dim3(kBlock), 0, s, res, W, z, st, J, maxk, hx, zc);
+}
 
 // ============================================================================
 // solver initialisation
@@ -830,7 +860,10 @@ __global__ __launch_bounds__(kBlock) void k_init_state(SrcState* __restrict__ st
     if (threadIdx.x == 0) {
         int c = sh.J - blockIdx.x * kBlock;
         c = c > kBlock ? kBlock : c;
+        // both parities: the two-kernel iteration k reads counts [k&1], the
+        // fused kernel k reads [(k-1)&1]
         sh.cnt[(size_t)n * kMaxSlices + blockIdx.x] = ok ? c : 0;
+        sh.cnt[((size_t)sh.nsrc + n) * kMaxSlices + blockIdx.x] = ok ? c : 0;
         sh.mres[(size_t)n * kMaxSlices + blockIdx.x] = ok ? 1.0 : 0.0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -959,6 +992,37 @@ __global__ __launch_bounds__(kBlock) void k_true_res(const double2* __restrict__
 void launch_true_res(const double2* b, const double2* x, const double2* hx, double2 z,
                      double2* partial, int nblk, int64_t n12, hipStream_t s) {
     hipLaunchKernelGGL(k_true_res, dim3(nblk), dim3(kBlock), 0, s, b, x, hx, z, partial, n12);
+}
+// The same for nsrc sources at once, source n with its own node zc[n]:
+// partial[n][blk] = (|b_n - (zc_n x_n - H x_n)|^2, |b_n|^2) of the block
+__global__ __launch_bounds__(kBlock) void k_true_res_multi(const double2* __restrict__ b,
+                                                           const double2* __restrict__ x,
+                                                           const double2* __restrict__ hx,
+                                                           const double2* __restrict__ zc,
+                                                           double2* __restrict__ partial,
+                                                           int64_t n12) {
+    const int n = blockIdx.y;
+    const double2 z = zc[n];
+    const size_t o = (size_t)n * n12;
+    double tt = 0.0, bb = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n12;
+         e += (int64_t)gridDim.x * kBlock) {
+        const double2 bv = b[o + e], xv = x[o + e], hv = hx[o + e];
+        const double tr = bv.x - (z.x * xv.x - z.y * xv.y - hv.x);
+        const double ti = bv.y - (z.x * xv.y + z.y * xv.x - hv.y);
+        tt += tr * tr + ti * ti;
+        bb += bv.x * bv.x + bv.y * bv.y;
+    }
+    __shared__ double sh[kBlock / 64];
+    tt = block_sum<kBlock>(tt, sh);
+    bb = block_sum<kBlock>(bb, sh);
+    if (threadIdx.x == 0) partial[(size_t)n * gridDim.x + blockIdx.x] = make_double2(tt, bb);
+}
+void launch_true_res_multi(const double2* b, const double2* x, const double2* hx,
+                           const double2* zc, double2* partial, int nblk, int64_t n12, int nsrc,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_true_res_multi, dim3(nblk, nsrc), dim3(kBlock), 0, s, b, x, hx, zc,
+                       partial, n12);
 }
 
 // (M v) for M = gamma5 (1 -+ gamma_mu) (sg = -1: 1 - gamma, +1: 1 + gamma):

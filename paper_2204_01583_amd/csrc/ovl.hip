@@ -21,6 +21,7 @@ using namespace ovl;
 
 namespace {
 
+
 // A device allocation that only grows.  New memory is zeroed before ensure
 // returns, so the padding sites of the tiled layouts start at zero; every
 // kernel keeps them there.
@@ -71,6 +72,9 @@ struct ovl_ctx {
     double2 zseed = make_double2(1.0, 0.05);
     double switch_res = 1e-4;
     int poll = 8;  // iterations between convergence polls
+    // the basis forms run the fused one-kernel iteration (OVL_FUSED=0: the
+    // two-kernel iteration with the seed direction p)
+    bool fused_iter = true;
     // device buffers
     DBuf U64, U32;    // links, tiled [mu][Vt/64][9][64], boundary sign folded in
     DBuf U64c, U32c;  // rows 0 and 1 only, [mu][Vt/64][6][64] (SU(3) fields)
@@ -88,7 +92,17 @@ struct ovl_ctx {
     int host_state_n = 0;
     DBuf bench_a, bench_b, bench_c, tune_state, tune_flush, chk;
     int check_n = 0;  // shifts per source whose true residual is checked after a solve
+    // in-band check (basis form): the true residual of every source's worst
+    // shift, fused into the final basis sum; off when false
+    bool inband_check = true;
+    DBuf chkdev;                   // hx [nsrc][maxk+1] | zc [nsrc] | partials [nsrc][kChkBlocks]
+    double2* chk_host = nullptr;   // pinned copy of the partials
+    size_t chk_host_bytes = 0;
     DBuf fY, fX, fpsi, facc, fc, fpart;  // force work space
+    // the force keeps the first solve's basis (slot chunks, their device
+    // table) and coefficients here while the second solve runs
+    std::vector<DBuf> fslot_chunks;
+    DBuf fslot_table, fW;
     DBuf slot_table;                       // basis form: device table of slot-chunk bases
     // solve stream (graphs cannot be captured on the legacy null stream) and handoff events
     hipStream_t ws = nullptr;
@@ -96,7 +110,7 @@ struct ovl_ctx {
     DBuf jobs_dev;                         // batch lead: JobDesc table + iteration counter
     struct GraphCache { std::string key; hipGraphExec_t exec = nullptr; } graphs[2];
     // per-kernel-class event timing (ovl_set_profiling)
-    static constexpr int kClasses = 8;
+    static constexpr int kClasses = 10;
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
     struct ProfRec { int cls; int ev; double bytes; };
@@ -283,6 +297,8 @@ extern "C" int ovl_create(ovl_ctx** out, const int32_t dims[4], const int32_t bc
     }
     ctx->g.V = V;
     ctx->g.Vt = (V + kTile - 1) / kTile * kTile;
+    const char* fz = getenv("OVL_FUSED");
+    ctx->fused_iter = !(fz && fz[0] == '0');
     *out = ctx;
     return OVL_OK;
 }
@@ -291,6 +307,9 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
     if (!ctx) return OVL_OK;
     DeviceGuard dg(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (DBuf& b : ctx->fslot_chunks) b.release();
+    ctx->fslot_table.release();
+    ctx->fW.release();
     DBuf* bufs[] = {&ctx->U64,  &ctx->U32, &ctx->U64c, &ctx->U32c,   &ctx->hw_in,  &ctx->hw_out, &ctx->b64,   &ctx->r64,
                     &ctx->p64,  &ctx->q64,   &ctx->r32,    &ctx->p32,    &ctx->q32,   &ctx->s64,
                     &ctx->pj64, &ctx->pj32,  &ctx->xj,     &ctx->part_w, &ctx->part_b,
@@ -306,6 +325,8 @@ extern "C" int ovl_destroy(ovl_ctx* ctx) {
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->ws) (void)hipStreamDestroy(ctx->ws);
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+    if (ctx->chk_host) (void)hipHostFree(ctx->chk_host);
+    ctx->chkdev.release();
     delete ctx;
     return OVL_OK;
 }
@@ -686,6 +707,146 @@ static int stencil_variant(ovl_ctx* ctx, int nrhs, int prec, int mode) {
     return best;
 }
 
+// Variant of the fused iteration kernel (code v + kIterVariants * links) for
+// nrhs right-hand sides in precision prec, tuned like the stencil: every
+// variant in every allowed link format is timed on a one-job table whose
+// buffers are scratch (kernel 1 with every source live, no shifts), each
+// launch after 512 MB of writes, median of 9.  OVL_ITER_VARIANT=v forces
+// variant v (two-row links for SU(3) fields unless OVL_LINKS=full).
+static int iter_variant(ovl_ctx* ctx, int nrhs, int prec) {
+    const int nfmt = ctx->links12 ? 2 : 1;
+    const char* force = getenv("OVL_ITER_VARIANT");
+    if (force && *force) {
+        const int v = atoi(force);
+        if (v >= 0 && v < kIterVariants) return v + kIterVariants * (nfmt - 1);
+    }
+    const auto key = std::make_pair(nrhs, prec + 4);
+    auto it = ctx->stencil_variant.find(key);
+    if (it != ctx->stencil_variant.end()) return it->second;
+    const char* at = getenv("OVL_AUTOTUNE");
+    if (at && at[0] == '0') return ctx->stencil_variant[key] = kIterVariants * (nfmt - 1);
+    const char* path = getenv("OVL_AUTOTUNE_CACHE");
+    const std::string k = tune_key(ctx, nrhs, prec, 2, nfmt == 2);
+    if (path && *path) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto m = read_cache(path);
+        auto f = m.find(k);
+        if (f != m.end() && f->second >= 0 && f->second < kIterVariants * nfmt)
+            return ctx->stencil_variant[key] = f->second;
+    }
+    const size_t es = prec ? sizeof(float2) : sizeof(double2);
+    const size_t vec = (size_t)nrhs * n12(ctx) * es;
+    const int nsb = wilson_blocks(ctx->g);
+    const size_t part = (size_t)nrhs * nsb;
+    // layout of tune_state: JobDesc | kdev[2] | slot table | SrcState[nrhs] |
+    // cnt [2][nrhs][kMaxSlices] | mres [nrhs][kMaxSlices] | partials [2][part]
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_k = al(sizeof(JobDesc)), o_tab = o_k + 256, o_st = o_tab + 256;
+    const size_t o_cnt = o_st + al((size_t)nrhs * sizeof(SrcState));
+    const size_t o_mres = o_cnt + al((size_t)2 * nrhs * kMaxSlices * sizeof(int));
+    const size_t o_part = o_mres + al((size_t)nrhs * kMaxSlices * sizeof(double));
+    const size_t total = o_part + 2 * part * sizeof(double4);
+    int best = kIterVariants * (nfmt - 1);
+    bool ok = ctx->bench_a.ensure(2 * vec) == hipSuccess && ctx->bench_b.ensure(2 * vec) == hipSuccess &&
+              ctx->tune_state.ensure(total) == hipSuccess &&
+              hipMemsetAsync(ctx->bench_a.p, 0, 2 * vec, ctx->stream) == hipSuccess &&
+              hipMemsetAsync(ctx->bench_b.p, 0, 2 * vec, ctx->stream) == hipSuccess &&
+              hipMemsetAsync(ctx->tune_state.p, 0, total, ctx->stream) == hipSuccess;
+    char* base = ctx->tune_state.as<char>();
+    JobDesc* jd = reinterpret_cast<JobDesc*>(base);
+    int* kdev = reinterpret_cast<int*>(base + o_k);
+    const char* vb = getenv("OVL_AUTOTUNE_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
+    if (ok) {
+        // host images: every source live at kernel 1 (counts [0][n][0] = 1),
+        // kernel 0's partials (1, 0, 1, 1) per block give alpha = 1, beta = 0
+        std::vector<int> cnt((size_t)2 * nrhs * kMaxSlices, 0);
+        for (int n = 0; n < nrhs; ++n) cnt[(size_t)n * kMaxSlices] = 1;
+        std::vector<double4> p0(part, make_double4(1.0, 0.0, 1.0, 1.0));
+        char* tab[1] = {ctx->bench_a.as<char>()};
+        const int kk[2] = {1, 2};
+        ok = hipMemcpyAsync(base + o_cnt, cnt.data(), cnt.size() * sizeof(int),
+                            hipMemcpyHostToDevice, ctx->stream) == hipSuccess &&
+             hipMemcpyAsync(base + o_part, p0.data(), part * sizeof(double4), hipMemcpyHostToDevice,
+                            ctx->stream) == hipSuccess &&
+             hipMemcpyAsync(base + o_tab, tab, sizeof(tab), hipMemcpyHostToDevice, ctx->stream) ==
+                 hipSuccess &&
+             hipMemcpyAsync(kdev, kk, sizeof(kk), hipMemcpyHostToDevice, ctx->stream) == hipSuccess &&
+             hipStreamSynchronize(ctx->stream) == hipSuccess;
+    }
+    const bool flush = ok && ctx->tune_flush.ensure((size_t)512 << 20) == hipSuccess;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    double tbest = 1e30;
+    for (int code = 0; ok && code < kIterVariants * nfmt; ++code) {
+        const int v = code % kIterVariants, lnk = code / kIterVariants;
+        JobDesc d{};
+        d.g = ctx->g;
+        d.kappa = kappa_of(ctx->m0);
+        d.zs = ctx->zseed;
+        d.U[0] = lnk ? ctx->U64c.p : ctx->U64.p;
+        d.U[1] = lnk ? ctx->U32c.p : ctx->U32.p;
+        d.nsrc = nrhs;
+        d.nsb = nsb;
+        d.sten_nb[0] = d.sten_nb[1] = iter_grid_blocks(ctx->g, nrhs);
+        d.st = reinterpret_cast<SrcState*>(base + o_st);
+        d.sh.cnt = reinterpret_cast<int*>(base + o_cnt);
+        d.sh.mres = reinterpret_cast<double*>(base + o_mres);
+        d.sh.nsrc = nrhs;
+        d.sh.nslices = 1;
+        d.sh.maxk = 4;
+        d.part_w = reinterpret_cast<double4*>(base + o_part);
+        d.part_stride = part;
+        d.q[0] = d.q[1] = ctx->bench_b.p;
+        d.qpp = (size_t)nrhs * n12(ctx);
+        d.slots = reinterpret_cast<char* const*>(base + o_tab);
+        d.slot_bytes = vec;
+        d.ksw = 1 << 30;
+        d.form = OVL_FORM_BASIS;
+        if (hipMemcpyAsync(jd, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream) != hipSuccess) break;
+        auto run = [&]() {
+            // kread = kwrite: every timed launch is kernel 1
+            if (prec)
+                launch_iter_jobs<float>(jd, 1, kdev, kdev + 1, d.sten_nb[1], v, lnk, ctx->stream);
+            else
+                launch_iter_jobs<double>(jd, 1, kdev, kdev + 1, d.sten_nb[0], v, lnk, ctx->stream);
+        };
+        run();
+        std::vector<float> t;
+        for (int i = 0; i < 9; ++i) {
+            if (flush) (void)hipMemsetAsync(ctx->tune_flush.p, i & 0xff, (size_t)512 << 20, ctx->stream);
+            (void)hipEventRecord(e0, ctx->stream);
+            run();
+            (void)hipEventRecord(e1, ctx->stream);
+            float ms = 1e30f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                ms = 1e30f;
+            t.push_back(ms);
+        }
+        std::nth_element(t.begin(), t.begin() + 4, t.end());
+        if (verbose)
+            fprintf(stderr, "ovl autotune %s: fused choice %d (variant %d, %s links) %.2f us\n",
+                    k.c_str(), code, v, lnk ? "two-row" : "full", t[4] * 1e3);
+        if (t[4] < tbest) {
+            tbest = t[4];
+            best = code;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->tune_flush.release();
+    (void)hipGetLastError();
+    ctx->stencil_variant[key] = best;
+    if (path && *path) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto m = read_cache(path);
+        m[k] = best;
+        write_cache(path, m);
+    }
+    return best;
+}
+
 // ============================================================================
 // H_W
 // ============================================================================
@@ -769,14 +930,21 @@ struct Work {
     size_t state_bytes;
     ShiftDev sh;
     int var64, var32;      // stencil variants (autotuned)
-    int k_switch;          // first FP32 iteration (mixed), or -1
+    bool fused;            // one-kernel iteration (basis forms): q and the partials double-buffered
+    size_t qpp;            // fused: elements between q[0] and q[1]
+    int k_switch;          // first basis slot (or iteration) held in FP32 (mixed), or -1
     int K;                 // seed iterations of the last solve (max over sources)
     size_t rpp;            // two-pass: elements between the two r buffers
     char** slot_tab;       // basis: device table of slot-chunk bases
     int n_tab;             // chunks published in slot_tab
-    double2 *dz, *cj;
+    double2 *dz, *cj, *zj;
     double2 *h_a, *h_b, *h_pi, *W, *h;
+    // in-band residual check (basis form), or null: coefficients of the
+    // checked shift per source, its node, per-block partials, pinned copy
+    double2 *hx, *zc, *cpart, *chost;
 };
+
+constexpr int kChkBlocks = 256;  // blocks per source of the in-band residual reduction
 
 // layout of the state block shared by the device and its pinned host mirror
 size_t state_cnt_off(int nsrc) { return ((size_t)nsrc * sizeof(SrcState) + 255) & ~(size_t)255; }
@@ -805,10 +973,13 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     const size_t vec64 = (size_t)nsrc * N * sizeof(double2);
     const size_t vec32 = (size_t)nsrc * N * sizeof(float2);
     const bool twopass = form == OVL_FORM_TWOPASS;
+    w.fused = ctx->fused_iter && (form == OVL_FORM_BASIS || twopass);
+    const size_t nq = w.fused ? 2 : 1;  // q buffers
+    w.qpp = (size_t)nsrc * N;
     HIPCHK(ctx, ctx->b64.ensure(vec64));
     HIPCHK(ctx, ctx->r64.ensure(twopass ? 2 * vec64 : vec64));
     HIPCHK(ctx, ctx->p64.ensure(vec64));
-    HIPCHK(ctx, ctx->q64.ensure(vec64));
+    HIPCHK(ctx, ctx->q64.ensure(nq * vec64));
     HIPCHK(ctx, ctx->s64.ensure(vec64));
     w.b64 = ctx->b64.as<double2>();
     w.r64 = ctx->r64.as<double2>();
@@ -825,7 +996,7 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     if (mixed) {
         HIPCHK(ctx, ctx->r32.ensure(twopass ? 2 * vec32 : vec32));
         HIPCHK(ctx, ctx->p32.ensure(vec32));
-        HIPCHK(ctx, ctx->q32.ensure(vec32));
+        HIPCHK(ctx, ctx->q32.ensure(nq * vec32));
         w.r32 = ctx->r32.as<float2>();
         w.p32 = ctx->p32.as<float2>();
         w.q32 = ctx->q32.as<float2>();
@@ -857,7 +1028,7 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     const int nslices = (J + 255) / 256;
     w.nbw = wilson_blocks(ctx->g);
     w.nbe = vec_blocks(N, nslices);
-    HIPCHK(ctx, ctx->part_w.ensure((size_t)nsrc * w.nbw * sizeof(double4)));
+    HIPCHK(ctx, ctx->part_w.ensure(nq * (size_t)nsrc * w.nbw * sizeof(double4)));
     HIPCHK(ctx, ctx->part_b.ensure((size_t)nsrc * w.nbe * sizeof(double)));
     w.state_bytes = state_bytes_for(nsrc);
     HIPCHK(ctx, ctx->state.ensure(w.state_bytes));
@@ -878,15 +1049,17 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     sh.nslices = nslices;
     sh.tol = ctx->tol;
     sh.maxk = w.maxk;
-    HIPCHK(ctx, ctx->nodes_dev.ensure((size_t)2 * J * sizeof(double2)));
+    HIPCHK(ctx, ctx->nodes_dev.ensure((size_t)3 * J * sizeof(double2)));
     w.dz = ctx->nodes_dev.as<double2>();
     w.cj = w.dz + J;
+    w.zj = w.dz + 2 * J;
     sh.dz = w.dz;
     sh.c = w.cj;
-    std::vector<double2> tab(2 * J);
+    std::vector<double2> tab(3 * J);
     for (int j = 0; j < J; ++j) {
         tab[j] = make_double2(ctx->z[j].x - ctx->zseed.x, ctx->z[j].y - ctx->zseed.y);
         tab[J + j] = ctx->c[j];
+        tab[2 * J + j] = ctx->z[j];
     }
     HIPCHK(ctx, hipMemcpyAsync(w.dz, tab.data(), tab.size() * sizeof(double2),
                                hipMemcpyHostToDevice, ctx->stream));
@@ -906,6 +1079,23 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     sh.h_a = w.h_a;
     sh.h_b = w.h_b;
     sh.h_pi = w.h_pi;
+    w.hx = w.zc = w.cpart = w.chost = nullptr;
+    if (basis && ctx->inband_check) {
+        const size_t nhx = (size_t)nsrc * (w.maxk + 1), npart = (size_t)nsrc * kChkBlocks;
+        HIPCHK(ctx, ctx->chkdev.ensure((nhx + nsrc + npart) * sizeof(double2)));
+        w.hx = ctx->chkdev.as<double2>();
+        w.zc = w.hx + nhx;
+        w.cpart = w.zc + nsrc;
+        if (ctx->chk_host_bytes < npart * sizeof(double2)) {
+            if (ctx->chk_host) (void)hipHostFree(ctx->chk_host);
+            ctx->chk_host = nullptr;
+            ctx->chk_host_bytes = 0;
+            HIPCHK(ctx, hipHostMalloc((void**)&ctx->chk_host, npart * sizeof(double2),
+                                      hipHostMallocDefault));
+            ctx->chk_host_bytes = npart * sizeof(double2);
+        }
+        w.chost = ctx->chk_host;
+    }
     HIPCHK(ctx, ctx->seed.ensure((size_t)nsrc * (w.maxk + 1) * 3 * sizeof(double2)));
     sh.seed = ctx->seed.as<double2>();
     // two pinned copies of the state: the poll reads one while the copy of
@@ -971,6 +1161,8 @@ struct Batch {
     int sten_total[2] = {0, 0};  // stencil grid of the FP64 and of the FP32 variant
     int vec_total = 0, variant64 = 0, variant32 = 0, form = 0, maxJ = 0;
     int lnk[2] = {0, 0};  // link format of the FP64 and of the FP32 stencil
+    bool fused = false;   // one-kernel iteration: variant64/32 are fused-kernel variants
+    int check_variant = 0, check_lnk = 0;  // H_W stencil of the in-band check
     JobDesc* desc_dev = nullptr;
     int* kdev = nullptr;
 };
@@ -986,7 +1178,8 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], const i
     d.nsb = wilson_blocks(c->g);
     for (int f = 0; f < 2; ++f) {
         d.sten_b0[f] = sten_b0[f];
-        d.sten_nb[f] = wilson_grid_blocks(c->g, w.nsrc, variant[f]);
+        d.sten_nb[f] = w.fused ? iter_grid_blocks(c->g, w.nsrc)
+                               : wilson_grid_blocks(c->g, w.nsrc, variant[f]);
         sten_b0[f] += d.sten_nb[f];
     }
     d.vec_b0 = vec_b0;
@@ -995,6 +1188,8 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], const i
     d.st = w.st;
     d.sh = w.sh;
     d.part_w = w.part_w;
+    d.part_stride = w.fused ? (size_t)w.nsrc * d.nsb : 0;
+    d.qpp = w.fused ? w.qpp : 0;
     d.p[0] = w.p64; d.p[1] = w.p32;
     d.q[0] = w.q64; d.q[1] = w.q32;
     d.r[0] = w.r64; d.r[1] = w.r32;
@@ -1030,6 +1225,17 @@ void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
     }
     const int var = c32 ? B.variant32 : B.variant64;
     const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
+    if (B.fused) {
+        for (int i = 0; i < count; ++i) {
+            // bytes credited after the solve from the sources' live iterations
+            ProfScope ps(lead, s, prof ? 8 + c32 : -1, 0.0, true);
+            launch_iter_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
+                                B.kdev + ((i + 1) & 1), B.sten_total[c32], var, B.lnk[c32], s,
+                                ps.start(), ps.stop());
+        }
+        launch_export_state(B.desc_dev, (int)B.desc.size(), B.kdev + (count & 1), kChunk, s);
+        return;
+    }
     for (int i = 0; i < count; ++i) {
         {
             // bytes credited after the solve from the sources' live iterations
@@ -1058,9 +1264,9 @@ int replay_chunk(Batch& B, hipStream_t s) {
     ovl_ctx* lead = B.ctx[0];
     const int ph = sizeof(R) == 4 ? 1 : 0;
     char kb[256];
-    snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d|%d", (void*)B.desc_dev, (void*)B.kdev,
+    snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d|%d|%d", (void*)B.desc_dev, (void*)B.kdev,
              B.desc.size(), B.sten_total[ph], B.vec_total, ph ? B.variant32 : B.variant64, B.form,
-             B.maxJ, B.lnk[ph]);
+             B.maxJ, B.lnk[ph], (int)B.fused);
     auto& gc = lead->graphs[ph];
     if (!gc.exec || gc.key != kb) {
         if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
@@ -1098,7 +1304,8 @@ int init_job(ovl_ctx* c, Work& w, hipStream_t s) {
     } else {
         HIPCHK(c, hipMemcpyAsync(w.r64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
     }
-    HIPCHK(c, hipMemcpyAsync(w.p64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
+    // the fused iteration has no direction p (kernel 0 applies A to r_0 = b)
+    if (!w.fused) HIPCHK(c, hipMemcpyAsync(w.p64, w.b64, vec64, hipMemcpyDeviceToDevice, s));
     if (form == OVL_FORM_FUSED) HIPCHK(c, hipMemsetAsync(w.s64, 0, vec64, s));
     if (form == OVL_FORM_REFERENCE) HIPCHK(c, hipMemsetAsync(w.xj, 0, vec64 * w.J, s));
     launch_init_state(w.st, w.b64, w.part_b, w.N, w.sh, s);
@@ -1109,6 +1316,22 @@ int init_job(ovl_ctx* c, Work& w, hipStream_t s) {
 // FP64 -> FP32 switch of one job at iteration k
 void convert_job(ovl_ctx* c, Work& w, int k, hipStream_t s) {
     const int64_t n = (int64_t)w.nsrc * w.N;
+    if (w.fused) {
+        // the first FP32 kernel k reads r_{k-1} and q_{k-1}: slot k-1 (FP32
+        // packed at its base from here on) or two-pass buffer (k-1)&1, and q[(k-1)&1]
+        const int km = k - 1;
+        launch_convert_64_to_32(w.q64 + (size_t)(km & 1) * w.qpp, w.q32 + (size_t)(km & 1) * w.qpp,
+                                n, s);
+        if (c->form == OVL_FORM_BASIS) {
+            launch_convert_64_to_32(slot_ptr<double2>(w, km), w.r32, n, s);
+            (void)hipMemcpyAsync(slot_ptr<float2>(w, km), w.r32, (size_t)n * sizeof(float2),
+                                 hipMemcpyDeviceToDevice, s);
+        } else {
+            launch_convert_64_to_32(w.r64 + (size_t)(km & 1) * w.rpp, w.r32 + (size_t)(km & 1) * w.rpp,
+                                    n, s);
+        }
+        return;
+    }
     launch_convert_64_to_32(w.p64, w.p32, n, s);
     if (c->form == OVL_FORM_BASIS) {
         launch_convert_64_to_32(slot_ptr<double2>(w, k), w.r32, n, s);
@@ -1120,6 +1343,13 @@ void convert_job(ovl_ctx* c, Work& w, int k, hipStream_t s) {
         launch_convert_64_to_32(w.r64, w.r32, n, s);
         launch_convert_64_to_32(w.pj64, w.pj32, n * w.J, s);
     }
+}
+
+// Parity of the newest active counts after `done` launches of the iteration:
+// the two-kernel iteration k writes counts [(k+1)&1], the fused kernel k
+// writes [k&1]; at the iteration limit the counts of the last live launch stay.
+int count_parity(const Work& w, int done) {
+    return w.fused ? std::min(done - 1, w.maxk) : std::min(done, w.maxk);
 }
 
 struct PollResult {
@@ -1149,7 +1379,7 @@ PollResult read_state(Batch& B, int slot, int k_host, hipEvent_t ev, int* rc_out
         const char* hb = host_slot(c, w, slot);
         const SrcState* hs = reinterpret_cast<const SrcState*>(hb);
         const int* hcnt = reinterpret_cast<const int*>(hb + state_cnt_off(w.nsrc)) +
-                          (size_t)(std::min(k_host, w.maxk) & 1) * w.nsrc * kMaxSlices;
+                          (size_t)(count_parity(w, k_host) & 1) * w.nsrc * kMaxSlices;
         const double* hmres = reinterpret_cast<const double*>(hb + state_mres_off(w.nsrc));
         for (int n = 0; n < w.nsrc; ++n) {
             const SrcState& S = hs[n];
@@ -1184,6 +1414,27 @@ void credit_live_bytes(const Batch& B, int k_switch) {
         const Work& w = *B.w[i];
         const double V = (double)c->g.V;
         const SrcState* hs = reinterpret_cast<const SrcState*>(c->host_state);
+        if (B.fused) {
+            // kernel k is live for a source through k = iter (its last live
+            // kernel records iter = k); FP64 below the first FP32 kernel
+            // k_switch.  Per live source r_{k-1}, q_{k-1} read and r_k, q_k
+            // written (kernel 0: b read, q_0 written), links once per launch.
+            for (int f = 0; f < 2; ++f) {
+                const double es = f ? (double)sizeof(float2) : (double)sizeof(double2);
+                double vec = 0.0;
+                int mx = 0;
+                for (int n = 0; n < w.nsrc; ++n) {
+                    const int last = std::min(hs[n].iter, w.maxk);  // kernels 0 .. last
+                    const int ksw = k_switch < 0 ? last + 1 : std::min(k_switch, last + 1);
+                    const int k0 = f ? ksw : 0, k1 = f ? last + 1 : ksw;  // [k0, k1)
+                    if (k1 <= k0) continue;
+                    vec += 48.0 * (k1 - k0) - (k0 == 0 ? 24.0 : 0.0);
+                    mx = std::max(mx, k1 - k0);
+                }
+                lead->prof_bytes[8 + f] += V * es * (vec + (B.lnk[f] ? 24.0 : 36.0) * mx);
+            }
+            continue;
+        }
         for (int f = 0; f < 2; ++f) {
             const double es = f ? (double)sizeof(float2) : (double)sizeof(double2);
             double sum = 0.0;
@@ -1205,7 +1456,7 @@ void credit_live_bytes(const Batch& B, int k_switch) {
 // w->b64) and leaves s = sum_j c_j y_j in each w->s64.  Work is enqueued on
 // the lead context's solve stream after its caller stream.  Returns a status
 // and fills ctx->last of every context.
-static int solve_batch(Batch& B) {
+static int solve_batch_once(Batch& B) {
     ovl_ctx* lead = B.ctx[0];
     hipStream_t s;
     int rc = solve_stream(lead, &s);
@@ -1244,12 +1495,30 @@ static int solve_batch(Batch& B) {
     // the two-row link form only where every job's field is SU(3)
     bool all12 = true;
     for (ovl_ctx* c : B.ctx) all12 = all12 && c->links12;
-    const int c64 = stencil_variant(B.ctx[big], B.w[big]->nsrc, 0, 1);
-    const int c32 = mixed ? stencil_variant(B.ctx[big], B.w[big]->nsrc, 1, 1) : 0;
-    B.variant64 = c64 % kStencilVariants;
-    B.variant32 = c32 % kStencilVariants;
-    B.lnk[0] = all12 ? c64 / kStencilVariants : 0;
-    B.lnk[1] = all12 ? c32 / kStencilVariants : 0;
+    B.fused = B.w[0]->fused;
+    for (Work* w : B.w)
+        if (w->fused != B.fused) return fail(lead, OVL_E_ARG, "mixed iteration kinds in one batch");
+    if (B.fused) {
+        // fused iteration: its own variants (hops per step, block order, LDS tile)
+        const int c64 = iter_variant(B.ctx[big], B.w[big]->nsrc, 0);
+        const int c32 = mixed ? iter_variant(B.ctx[big], B.w[big]->nsrc, 1) : 0;
+        B.variant64 = c64 % kIterVariants;
+        B.variant32 = c32 % kIterVariants;
+        B.lnk[0] = all12 ? c64 / kIterVariants : 0;
+        B.lnk[1] = all12 ? c32 / kIterVariants : 0;
+        // the H_W stencil with the same hops per step, order and tile
+        const int v = B.variant64;
+        B.check_variant = (v & 1) + 4 * ((v >> 1) & 1) + 16 * ((v >> 2) & 1);
+    } else {
+        const int c64 = stencil_variant(B.ctx[big], B.w[big]->nsrc, 0, 1);
+        const int c32 = mixed ? stencil_variant(B.ctx[big], B.w[big]->nsrc, 1, 1) : 0;
+        B.variant64 = c64 % kStencilVariants;
+        B.variant32 = c32 % kStencilVariants;
+        B.lnk[0] = all12 ? c64 / kStencilVariants : 0;
+        B.lnk[1] = all12 ? c32 / kStencilVariants : 0;
+        B.check_variant = B.variant64;
+    }
+    B.check_lnk = B.lnk[0];
     B.form = form;
     B.maxJ = 0;
     B.desc.resize(B.w.size());
@@ -1320,13 +1589,16 @@ static int solve_batch(Batch& B) {
     // queued past convergence finds no live source and returns at once.
     // Profiling keeps one chunk in flight (its events are read at each poll).
     const bool may_look_ahead = !lead->prof_on;
-    while (k_host < maxk) {
+    // launches the iteration may take: the two-kernel iteration k < maxk; the
+    // fused kernel k <= maxk (kernel k advances the shifts by iteration k-1)
+    const int klim = B.fused ? maxk + 1 : maxk;
+    while (k_host < klim) {
         if (k_enq == k_host) {
             rc = queue_chunk();
             if (rc) return rc;
         }
         const double next_point = (mixed && !low) ? lead->switch_res : lead->tol;
-        if (may_look_ahead && k_enq == k_host + kChunk && k_enq < maxk &&
+        if (may_look_ahead && k_enq == k_host + kChunk && k_enq < klim &&
             P.maxres > 10.0 * next_point) {
             rc = queue_chunk();
             if (rc) return rc;
@@ -1339,7 +1611,7 @@ static int solve_batch(Batch& B) {
         nact_known = P.nact;
         if (P.status != OVL_OK) { status = P.status; break; }
         if (P.all_done) break;
-        if (mixed && !low && P.maxres < lead->switch_res && k_host < maxk) {
+        if (mixed && !low && P.maxres < lead->switch_res && k_host < klim) {
             // relaxed precision: from here the remaining corrections are small
             // enough that FP32 vectors perturb the result by ~eps32 * switch_res.
             // The conversion follows any chunk still queued.
@@ -1367,7 +1639,9 @@ static int solve_batch(Batch& B) {
     const int k_run = k_host;
     if (status == OVL_OK && !P.all_done) status = OVL_NOT_CONVERGED;
     for (size_t i = 0; i < B.w.size(); ++i) {
-        B.w[i]->k_switch = k_switch;
+        // first slot holding FP32 (the fused kernel k reads slot k-1, which the
+        // switch to FP32 before kernel k converted)
+        B.w[i]->k_switch = k_switch < 0 ? -1 : (B.fused ? k_switch - 1 : k_switch);
         B.w[i]->K = 0;
         for (int n = 0; n < B.w[i]->nsrc; ++n) B.w[i]->K = std::max(B.w[i]->K, B.ctx[i]->host_state[n].iter);
     }
@@ -1383,27 +1657,48 @@ static int solve_batch(Batch& B) {
                 launch_basis_coef(w.h_a, w.h_b, w.h_pi, w.cj, w.st, w.W, w.h, w.J, w.maxk, w.nsrc, s);
             }
             if (form == OVL_FORM_BASIS) {
-                // s = sum_i h_i r_i, chunk by chunk; FP64 slots below k_switch, FP32 from it
+                // s = sum_i h_i r_i, chunk by chunk; FP64 slots below k_switch, FP32 from it.
+                // With the in-band check the same pass rebuilds each source's worst
+                // shifted solution x = sum_i u_i^j r_i into p64 (free after the solve).
                 const int kend = w.K + 1;
-                const int ksw = k_switch < 0 ? kend : k_switch;
+                const int ksw = w.k_switch < 0 ? kend : w.k_switch;
+                if (w.hx)
+                    launch_pick_check(w.sh.res, w.W, w.zj, w.st, w.J, w.maxk, w.nsrc, w.hx, w.zc, s);
                 bool acc = false;
                 for (int c0 = 0; c0 < kend; c0 += kSlotChunk) {
                     const int c1 = std::min(kend, c0 + kSlotChunk);
                     char* base = w.chunks[c0 / kSlotChunk];
                     const int a0 = c0, a1 = std::min(c1, ksw);
                     if (a1 > a0) {
-                        ProfScope ps(lead, s, 6, Na * w.nsrc * (16.0 * (a1 - a0) + 32.0));
-                        launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.maxk, w.st, c0,
-                                                  a0 - c0, a1 - c0, w.s64, acc, N, w.nsrc, s);
+                        ProfScope ps(lead, s, 6, Na * w.nsrc * (16.0 * (a1 - a0) + (w.hx ? 64.0 : 32.0)));
+                        launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.hx, w.maxk,
+                                                  w.st, c0, a0 - c0, a1 - c0, w.s64, w.p64, acc,
+                                                  N, w.nsrc, s);
                         acc = true;
                     }
                     const int f0 = std::max(c0, ksw), f1 = c1;
                     if (f1 > f0) {
-                        ProfScope ps(lead, s, 6, Na * w.nsrc * (8.0 * (f1 - f0) + 32.0));
-                        launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.maxk, w.st,
-                                                 c0, f0 - c0, f1 - c0, w.s64, acc, N, w.nsrc, s);
+                        ProfScope ps(lead, s, 6, Na * w.nsrc * (8.0 * (f1 - f0) + (w.hx ? 64.0 : 32.0)));
+                        launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.hx,
+                                                 w.maxk, w.st, c0, f0 - c0, f1 - c0, w.s64, w.p64,
+                                                 acc, N, w.nsrc, s);
                         acc = true;
                     }
+                }
+                if (w.hx) {
+                    // true residual of the rebuilt solution in FP64: H x (the FP64
+                    // stencil of the solve, here as H_W alone), then per-block
+                    // |b - (z x - H x)|^2 and |b|^2, copied to pinned host memory
+                    // and summed on the host after the final synchronisation
+                    launch_wilson<double>(0, w.p64, w.q64, stencil_links<double>(c, B.check_lnk),
+                                          c->g, kappa_of(c->m0), make_double2(0, 0), nullptr,
+                                          nullptr, nullptr, nullptr, 0, w.nsrc, s,
+                                          B.check_variant, B.check_lnk);
+                    launch_true_res_multi(w.b64, w.p64, w.q64, w.zc, w.cpart, kChkBlocks, N,
+                                          w.nsrc, s);
+                    HIPCHK(c, hipMemcpyAsync(w.chost, w.cpart,
+                                             (size_t)w.nsrc * kChkBlocks * sizeof(double2),
+                                             hipMemcpyDeviceToHost, s));
                 }
             }
             HIPCHK(c, hipGetLastError());
@@ -1452,7 +1747,7 @@ static int solve_batch(Batch& B) {
         double mr = 0.0;
         const char* hb = reinterpret_cast<const char*>(c->host_state);
         const int* hcnt = reinterpret_cast<const int*>(hb + state_cnt_off(w.nsrc)) +
-                          (size_t)(std::min(k_run, w.maxk) & 1) * w.nsrc * kMaxSlices;
+                          (size_t)(count_parity(w, k_run) & 1) * w.nsrc * kMaxSlices;
         const double* hmres = reinterpret_cast<const double*>(hb + state_mres_off(w.nsrc));
         for (int n = 0; n < w.nsrc; ++n)
             for (int q = 0; q < w.sh.nslices; ++q) {
@@ -1469,20 +1764,76 @@ static int solve_batch(Batch& B) {
         ovl_stats& L = c->last;
         std::memset(&L, 0, sizeof(L));
         L.iterations = w.K;
-        L.fp32_iterations = k_switch < 0 ? 0 : std::max(0, w.K - k_switch);
+        L.fp32_iterations = w.k_switch < 0 ? 0 : std::max(0, w.K - w.k_switch);
         L.n_shifts = w.J;
         L.n_active_end = na;
         L.max_est_rel_res = mr;
         L.seconds = ms * 1e-3;
-        L.stencil_variant64 = B.variant64 + kStencilVariants * B.lnk[0];
-        L.stencil_variant32 = mixed ? B.variant32 + kStencilVariants * B.lnk[1] : -1;
+        if (B.fused) {
+            L.stencil_variant64 = 1000 + B.variant64 + kIterVariants * B.lnk[0];
+            L.stencil_variant32 = mixed ? 1000 + B.variant32 + kIterVariants * B.lnk[1] : -1;
+        } else {
+            L.stencil_variant64 = B.variant64 + kStencilVariants * B.lnk[0];
+            L.stencil_variant32 = mixed ? B.variant32 + kStencilVariants * B.lnk[1] : -1;
+        }
         L.max_true_rel_res = -1.0;
+        L.mixed_true_rel_res = -1.0;
+        if (w.hx && (status == OVL_OK || status == OVL_NOT_CONVERGED)) {
+            // in-band check: the worst shift of every source, partials summed in order
+            double worst = 0.0;
+            for (int n = 0; n < w.nsrc; ++n) {
+                double tt = 0.0, bb = 0.0;
+                for (int b = 0; b < kChkBlocks; ++b) {
+                    tt += w.chost[(size_t)n * kChkBlocks + b].x;
+                    bb += w.chost[(size_t)n * kChkBlocks + b].y;
+                }
+                if (bb > 0.0) worst = std::max(worst, std::sqrt(tt / bb));
+                else if (!(bb == 0.0)) worst = bb;  // NaN propagates
+            }
+            L.max_true_rel_res = worst;
+        }
         if (status < 0) fail(c, status, "solver stopped: %s", ovl_status_string(status));
         if (status == OVL_NOT_CONVERGED)
             fail(c, status, "maxiter=%d reached with %d shifts above tol (max est. res %.3e)",
                  w.maxk, na, mr);
     }
     return status;
+}
+
+// solve_batch_once, and in mixed precision its safeguard: when every shift
+// met the tolerance by its residual estimate but the in-band FP64 check finds
+// a true residual above 10 tol in some job (the FP32 phase drifted), the
+// whole batch is solved again in FP64 and the stats of every context say so;
+// if that still misses, the status is OVL_NOT_CONVERGED.
+static int solve_batch(Batch& B) {
+    int rc = solve_batch_once(B);
+    ovl_ctx* lead = B.ctx[0];
+    if (rc != OVL_OK || lead->precision != OVL_PREC_MIXED) return rc;
+    const double limit = 10.0 * lead->tol;
+    auto failed = [&]() {
+        for (ovl_ctx* c : B.ctx)
+            if (!(c->last.max_true_rel_res <= limit) && c->last.max_true_rel_res != -1.0) return true;
+        return false;
+    };
+    if (!failed()) return rc;
+    std::vector<double> first(B.ctx.size());
+    for (size_t i = 0; i < B.ctx.size(); ++i) {
+        first[i] = B.ctx[i]->last.max_true_rel_res;
+        B.ctx[i]->precision = OVL_PREC_FP64;
+    }
+    rc = solve_batch_once(B);
+    for (size_t i = 0; i < B.ctx.size(); ++i) {
+        B.ctx[i]->precision = OVL_PREC_MIXED;
+        B.ctx[i]->last.fp64_repeat = 1;
+        B.ctx[i]->last.mixed_true_rel_res = first[i];
+    }
+    if (rc == OVL_OK && failed()) {
+        rc = OVL_NOT_CONVERGED;
+        for (ovl_ctx* c : B.ctx)
+            fail(c, rc, "true residual %.3e above 10 tol after the FP64 repeat",
+                 c->last.max_true_rel_res);
+    }
+    return rc;
 }
 
 static int solve(ovl_ctx* ctx, Work& w) {
@@ -1500,7 +1851,6 @@ static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y, 
 // rebuilt from the stored basis by the basis form; the fused and two-pass
 // forms keep neither, and report -1.  Diagnostic: synchronous.
 static int true_residuals(ovl_ctx* ctx, const Work& w) {
-    ctx->last.max_true_rel_res = -1.0;
     if (ctx->check_n <= 0 || (ctx->form != OVL_FORM_BASIS && ctx->form != OVL_FORM_REFERENCE))
         return OVL_OK;
     hipStream_t s = ctx->stream;
@@ -1551,14 +1901,15 @@ static int true_residuals(ovl_ctx* ctx, const Work& w) {
             if (bb > 0.0) worst = std::max(worst, std::sqrt(tt / bb));
         }
     }
-    ctx->last.max_true_rel_res = worst;
+    ctx->last.max_true_rel_res = std::max(ctx->last.max_true_rel_res, worst);
     return OVL_OK;
 }
 
 extern "C" int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample) {
     if (!ctx) return OVL_E_ARG;
-    if (nsample < 0 || nsample > 64) return fail(ctx, OVL_E_ARG, "nsample must be in [0, 64]");
-    ctx->check_n = nsample;
+    if (nsample < -1 || nsample > 64) return fail(ctx, OVL_E_ARG, "nsample must be in [-1, 64]");
+    ctx->check_n = nsample < 0 ? 0 : nsample;
+    ctx->inband_check = nsample >= 0;
     return OVL_OK;
 }
 
@@ -1759,28 +2110,42 @@ extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind
                          int32_t shift_chunk, double* action, ovl_stats* st) {
     if (!ctx) return OVL_E_ARG;
     DeviceGuard dg(ctx->device);
-    if (kind != 0 && kind != 1) return fail(ctx, OVL_E_ARG, "kind must be 0 (force) or 1 (gradient)");
+    if (kind != 0 && kind != 1 && kind != 2)
+        return fail(ctx, OVL_E_ARG, "kind must be 0 (force), 1 (gradient) or 2 (action only)");
     if (!ctx->gauge_set || !ctx->masses_set || ctx->z.empty())
         return fail(ctx, OVL_E_STATE, "gauge, masses and nodes must be set before ovl_force");
     int rc = check_dev_ptr(ctx, phi, "phi");
     if (rc) return rc;
-    rc = check_dev_ptr(ctx, grad, "grad");
-    if (rc) return rc;
-    if (overlaps(phi, (size_t)12 * ctx->g.V * sizeof(double2), grad,
-                 (size_t)36 * ctx->g.V * sizeof(double2)))
-        return fail(ctx, OVL_E_ARG, "grad aliases phi");
+    if (kind != 2) {
+        rc = check_dev_ptr(ctx, grad, "grad");
+        if (rc) return rc;
+        if (overlaps(phi, (size_t)12 * ctx->g.V * sizeof(double2), grad,
+                     (size_t)36 * ctx->g.V * sizeof(double2)))
+            return fail(ctx, OVL_E_ARG, "grad aliases phi");
+    }
     const int saved_form = ctx->form;
     const std::vector<double2> z0 = ctx->z, c0 = ctx->c;
     const int J = (int)z0.size();
     const int64_t N = n12(ctx);
     const int C = (shift_chunk <= 0 || shift_chunk > J) ? J : shift_chunk;
     hipStream_t s = ctx->stream;
+    bool swapped = false;
+    // the first solve's basis, table and coefficients live in the force's
+    // buffers while the second solve runs; afterwards the sets swap back
+    auto swap_basis = [&]() {
+        std::swap(ctx->slot_chunks, ctx->fslot_chunks);
+        std::swap(ctx->slot_table, ctx->fslot_table);
+        std::swap(ctx->W, ctx->fW);
+        swapped = !swapped;
+    };
     auto restore = [&]() {
+        if (swapped) swap_basis();
         ctx->form = saved_form;
         ctx->z = z0;
         ctx->c = c0;
     };
-    // 1. Y_j = (z_j - H)^-1 phi and s = sum c_j Y_j from one basis-form solve
+    // 1. one basis-form solve for phi: s = sum c_j Y_j, with Y_j = (z_j - H)^-1 phi
+    //    kept implicit in the stored basis and coefficients
     ctx->form = OVL_FORM_BASIS;
     Work w;
     rc = prepare(ctx, 1, w);
@@ -1789,18 +2154,17 @@ extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind
     const int rc1 = solve(ctx, w);
     if (rc1 < 0) { restore(); return rc1; }
     const ovl_stats st1 = ctx->last;
-    if (ctx->fY.ensure((size_t)J * N * sizeof(double2)) != hipSuccess ||
-        ctx->fpsi.ensure((size_t)N * sizeof(double2)) != hipSuccess ||
-        ctx->fX.ensure((size_t)C * N * sizeof(double2)) != hipSuccess ||
-        ctx->facc.ensure((size_t)4 * ctx->g.V * 18 * sizeof(double2)) != hipSuccess ||
-        ctx->fc.ensure((size_t)J * sizeof(double2)) != hipSuccess ||
-        ctx->fpart.ensure(512 * sizeof(double)) != hipSuccess) {
+    if (ctx->fpsi.ensure((size_t)N * sizeof(double2)) != hipSuccess ||
+        ctx->fpart.ensure(512 * sizeof(double)) != hipSuccess ||
+        (kind != 2 && (ctx->fY.ensure((size_t)C * N * sizeof(double2)) != hipSuccess ||
+                       ctx->fX.ensure((size_t)C * N * sizeof(double2)) != hipSuccess ||
+                       ctx->facc.ensure((size_t)4 * ctx->g.V * 18 * sizeof(double2)) != hipSuccess ||
+                       ctx->fc.ensure((size_t)J * sizeof(double2)) != hipSuccess))) {
         restore();
         return fail(ctx, OVL_E_OOM, "force work space allocation failed");
     }
-    rc = materialize(ctx, w, 0, J, ctx->fY.as<double2>());
-    if (rc) { restore(); return rc; }
-    HIPCHK(ctx, hipMemcpyAsync(ctx->fc.p, w.cj, J * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    if (kind != 2)
+        HIPCHK(ctx, hipMemcpyAsync(ctx->fc.p, w.cj, J * sizeof(double2), hipMemcpyDeviceToDevice, s));
     // 2. D_ov phi, psi = (1-mq)/2 gamma5 D_ov phi and S = |D_ov phi|^2
     const int npart = 256;
     launch_dov_psi(w.b64, w.s64, ctx->fpsi.as<double2>(), 0.5 * (1.0 + ctx->mq),
@@ -1808,25 +2172,38 @@ extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind
     std::vector<double> part(npart);
     HIPCHK(ctx, hipMemcpyAsync(part.data(), ctx->fpart.p, npart * sizeof(double),
                                hipMemcpyDeviceToHost, s));
-    // 3. X_j = (conj(z_j) - H)^-1 psi from a second basis-form solve at the conjugate nodes
-    for (int j = 0; j < J; ++j) ctx->z[j].y = -z0[j].y;
-    Work w2;
-    rc = prepare(ctx, 1, w2);  // synchronises the stream (so part[] is ready)
-    if (rc) { restore(); return rc; }
+    HIPCHK(ctx, hipStreamSynchronize(s));
     double S = 0.0;
     for (double v : part) S += v;
+    if (kind == 2) {
+        restore();
+        ctx->last = st1;
+        if (action) *action = S;
+        if (st) *st = st1;
+        return rc1 == OVL_NOT_CONVERGED ? OVL_NOT_CONVERGED : OVL_OK;
+    }
+    // 3. X_j = (conj(z_j) - H)^-1 psi from a second basis-form solve at the
+    //    conjugate nodes, into a basis of its own
+    swap_basis();
+    for (int j = 0; j < J; ++j) ctx->z[j].y = -z0[j].y;
+    Work w2;
+    rc = prepare(ctx, 1, w2);
+    if (rc) { restore(); return rc; }
     HIPCHK(ctx, hipMemcpyAsync(w2.b64, ctx->fpsi.p, N * sizeof(double2), hipMemcpyDeviceToDevice, s));
     const int rc2 = solve(ctx, w2);
     if (rc2 < 0) { restore(); return rc2; }
     const ovl_stats st2 = ctx->last;
-    // 4. per link: sum_j c_j X_j^dag dH Y_j, C shifts at a time
+    // 4. per link: sum_j c_j X_j^dag dH Y_j, C shifts at a time; Y_j and X_j of
+    //    the chunk are rebuilt from their bases, so at most C of each exist
     for (int j0 = 0; j0 < J; j0 += C) {
         const int jn = std::min(C, J - j0);
+        rc = materialize(ctx, w, j0, jn, ctx->fY.as<double2>());
+        if (rc) { restore(); return rc; }
         rc = materialize(ctx, w2, j0, jn, ctx->fX.as<double2>());
         if (rc) { restore(); return rc; }
-        launch_force(ctx->fX.as<double2>(), ctx->fY.as<double2>() + (size_t)j0 * N,
-                     ctx->fc.as<double2>() + j0, jn, ctx->g, ctx->U64.as<double2>(), ctx->bc,
-                     kappa_of(ctx->m0), ctx->facc.as<double2>(), j0 == 0, j0 + jn >= J, kind,
+        launch_force(ctx->fX.as<double2>(), ctx->fY.as<double2>(), ctx->fc.as<double2>() + j0, jn,
+                     ctx->g, ctx->U64.as<double2>(), ctx->bc, kappa_of(ctx->m0),
+                     ctx->facc.as<double2>(), j0 == 0, j0 + jn >= J, kind,
                      static_cast<double2*>(grad), s);
         HIPCHK(ctx, hipGetLastError());
     }
@@ -1839,7 +2216,9 @@ extern "C" int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind
     L.n_active_end = st1.n_active_end + st2.n_active_end;
     L.max_est_rel_res = std::max(st1.max_est_rel_res, st2.max_est_rel_res);
     L.seconds = st1.seconds + st2.seconds;
-    L.reserved[0] = st2.iterations;
+    L.max_true_rel_res = std::max(st1.max_true_rel_res, st2.max_true_rel_res);
+    L.fp64_repeat = st1.fp64_repeat | st2.fp64_repeat;
+    L.mixed_true_rel_res = std::max(st1.mixed_true_rel_res, st2.mixed_true_rel_res);
     if (action) *action = S;
     if (st) *st = L;
     return (rc1 == OVL_NOT_CONVERGED || rc2 == OVL_NOT_CONVERGED) ? OVL_NOT_CONVERGED : OVL_OK;

@@ -146,7 +146,10 @@ struct JobDesc {
     int vec_b0, nbe;            // this job's first block in the vector grid; blocks per source
     SrcState* st;
     ShiftDev sh;
-    double4* part_w;            // [nsrc][nsb]: <r_k, q> (re, im), ||q||^2, ||r_k||^2 per block
+    double4* part_w;            // [nsrc][nsb]: <r_k, q> (re, im), ||q||^2, ||r_k||^2 per block;
+                                // fused iteration: two such arrays, kernel k writes [k&1]
+    size_t part_stride;         // fused iteration: elements between the two partial arrays
+    size_t qpp;                 // fused iteration: elements between q[k&1 = 0] and q[1]
     // working vectors [nsrc][12 Vt], index [0] FP64, [1] FP32
     void* p[2];
     void* q[2];

@@ -10,6 +10,7 @@
 
 #include "device_util.h"
 #include "kernels.h"
+#include "seed_iter.h"
 
 namespace ovl {
 
@@ -66,12 +67,23 @@ __device__ __forceinline__ void reconstruct(int mu, R sg, cx<R> (&acc)[4][3],
 // the links are stored as their first two rows (6 elements per link) and the
 // third is rebuilt as lsgn * conj(row0 x row1), exact for SU(3); lsgn is the
 // boundary sign folded into the stored rows of that link.
-template <typename R, int RPT, int TIL, int LNK, int LT = 0>
+// Input of the fused seed iteration (FU = 1): the stencil acts on
+// r_k = r_{k-1} - a q_{k-1}, formed at each neighbour from psi = r_{k-1} and
+// q = q_{k-1} as it is loaded (a neighbour inside the LDS tile is read there,
+// where the block has already formed it).
+template <typename R, int RPT>
+struct FusedIn {
+    const C2<R>* q[RPT];
+    cx<R> a[RPT];
+};
+
+template <typename R, int RPT, int TIL, int LNK, int LT = 0, int FU = 0>
 __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
                                     const C2<R>* const (&psi)[RPT],
                                     const C2<R>* __restrict__ Um, uint32_t nb,
                                     uint32_t lsite, const C2<R>* tile, uint32_t s0, R lsgn,
-                                    const C2<R>* lut = nullptr) {
+                                    const C2<R>* lut = nullptr,
+                                    const FusedIn<R, RPT>* fi = nullptr) {
     const R sg = fwd ? R(-1) : R(1);
     constexpr uint32_t NE = LNK ? 6 : 9;  // stored elements per link
     // link element e of this hop's link: from the LDS link tile (LT = 1: the
@@ -97,6 +109,19 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
                 for (int c = 0; c < 3; ++c) {
                     const C2<R> v = tile[(uint32_t)((r * 12 + 3 * a + c) * kBlock) + lo];
                     pv[r][a][c] = mk<R>(v.x, v.y);
+                }
+    } else if constexpr (FU == 1) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const uint32_t o = tix((uint32_t)(3 * a + c), nb, 12);
+                    const cx<R> rv = ld<R>(psi[r], o), qv = ld<R>(fi->q[r], o);
+                    const cx<R> al = fi->a[r];
+                    pv[r][a][c] = mk<R>(rv.re - (al.re * qv.re - al.im * qv.im),
+                                        rv.im - (al.re * qv.im + al.im * qv.re));
                 }
     } else {
 #pragma unroll
@@ -191,13 +216,14 @@ __device__ __forceinline__ uint32_t nbr(const Geom& g, uint32_t s, const int (&c
 // lanes share a site, lane h = 0 the four forward hops and h = 1 the four
 // backward ones, so mu stays wave-uniform; HPI = 2 takes two directions per
 // iteration.
-template <typename R, int HPI, int RPT, int SPL, int TIL, int LNK, int LT = 0>
+template <typename R, int HPI, int RPT, int SPL, int TIL, int LNK, int LT = 0, int FU = 0>
 __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
                                             const C2<R>* const (&psi)[RPT],
                                             const C2<R>* __restrict__ U, const Geom& g,
                                             uint32_t s, const int (&coord)[4], int h,
                                             const C2<R>* tile, uint32_t s0,
-                                            const C2<R>* lu = nullptr) {
+                                            const C2<R>* lu = nullptr,
+                                            const FusedIn<R, RPT>* fi = nullptr) {
     const uint32_t Vt = (uint32_t)g.Vt;
     constexpr uint32_t NE = LNK ? 6 : 9;  // stored elements per link
     // boundary sign of the link a hop uses: U_mu(x) forward (last slice when
@@ -212,15 +238,15 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 #pragma unroll 1
             for (int mu = 0; mu < 4; ++mu) {
                 const uint32_t nb = nbr(g, s, coord, mu, fwd);
-                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
+                hop<R, RPT, TIL, LNK, LT, FU>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock, fi);
             }
         } else {
 #pragma unroll 1
             for (int mu = 0; mu < 4; mu += 2) {
                 const uint32_t n0 = nbr(g, s, coord, mu, fwd), n1 = nbr(g, s, coord, mu + 1, fwd);
-                hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
-                hop<R, RPT, TIL, LNK, LT>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * Vt, n1,
-                                 fwd ? s : n1, tile, s0, lsg(mu + 1, fwd), lu + (size_t)(mu + 1) * NE * kBlock);
+                hop<R, RPT, TIL, LNK, LT, FU>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock, fi);
+                hop<R, RPT, TIL, LNK, LT, FU>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * Vt, n1,
+                                 fwd ? s : n1, tile, s0, lsg(mu + 1, fwd), lu + (size_t)(mu + 1) * NE * kBlock, fi);
             }
         }
     } else if constexpr (HPI == 1) {
@@ -229,14 +255,14 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
             const int mu = d >> 1;
             const bool fwd = (d & 1) == 0;
             const uint32_t nb = nbr(g, s, coord, mu, fwd);
-            hop<R, RPT, TIL, LNK, LT>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock);
+            hop<R, RPT, TIL, LNK, LT, FU>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock, fi);
         }
     } else {
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
-            hop<R, RPT, TIL, LNK, LT>(mu, true, acc, psi, U + (size_t)mu * NE * Vt, fw, s, tile, s0, lsg(mu, true), lu + (size_t)(mu) * NE * kBlock);
-            hop<R, RPT, TIL, LNK, LT>(mu, false, acc, psi, U + (size_t)mu * NE * Vt, bw, bw, tile, s0, lsg(mu, false), lu + (size_t)(mu) * NE * kBlock);
+            hop<R, RPT, TIL, LNK, LT, FU>(mu, true, acc, psi, U + (size_t)mu * NE * Vt, fw, s, tile, s0, lsg(mu, true), lu + (size_t)(mu) * NE * kBlock, fi);
+            hop<R, RPT, TIL, LNK, LT, FU>(mu, false, acc, psi, U + (size_t)mu * NE * Vt, bw, bw, tile, s0, lsg(mu, false), lu + (size_t)(mu) * NE * kBlock, fi);
         }
     }
 }
@@ -550,6 +576,250 @@ __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __r
                                       J.zs.y, job_rk<const C2<R>>(J, k, f), J.part_w, J.st, J.sh,
                                       k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0[f]);
 }
+
+// ============================================================================
+// The fused seed iteration: one kernel per iteration of the shifted solver
+// in the basis forms, without the seed direction p.  With A = z_s - H,
+// p_k = r_k + beta_{k-1} p_{k-1} and q_k = A p_k, the direction enters only
+// through q, and q_k = A r_k + beta_{k-1} q_{k-1}.  Kernel k
+//   * reduces kernel k-1's partials to alpha_{k-1}, beta_{k-1} and the
+//     estimate of ||r_k||^2 (every block, in the same fixed order);
+//   * forms r_k = r_{k-1} - alpha_{k-1} q_{k-1} wherever it needs it: at its
+//     own sites (stored as basis slot k, or the two-pass buffer k&1) and at
+//     every neighbour of the stencil, from the loads of r_{k-1} and q_{k-1}
+//     (with the LDS tile, the block's own r_k is formed once and the
+//     neighbours inside the block read it there);
+//   * q_k = z_s r_k - H r_k + beta_{k-1} q_{k-1} into q[k&1], and the
+//     partials <r_k, q_k>, ||q_k||^2, ||r_k||^2 into part[k&1];
+//   * block (site block sb, source n) advances the shift slices sb,
+//     sb + nsb, ... by iteration k-1, and block (0, n) records the seed
+//     scalars.
+// r_{k-1}, q_{k-1} are read at neighbours while r_k, q_k are written, so
+// each lives in a buffer of its own (q and the partials alternate with
+// k&1).  Per iteration and rhs this moves 4 vectors (r_{k-1}, q_{k-1} read,
+// r_k, q_k written) instead of the two-kernel iteration's 8.
+// ============================================================================
+template <typename R, int HPI, int ORD, int TIL, int LNK>
+__device__ __forceinline__ void iter_block(const JobDesc& J, int k, unsigned tile) {
+    const int f = sizeof(R) == 4 ? 1 : 0;
+    const int nsb = J.nsb, nsrc = J.nsrc;
+    const int n = (int)uniform(ORD == 0 ? tile % (unsigned)nsrc : tile / (unsigned)nsb);
+    const int sb = (int)uniform(ORD == 0 ? tile / (unsigned)nsrc : tile % (unsigned)nsb);
+    const ShiftDev& sh = J.sh;
+    SrcState& S = J.st[n];
+    __shared__ double shm[kBlock / 64];
+    // shift slices q = sb, sb + nsb, ... belong to site block sb (a small
+    // lattice may have fewer site blocks than 256-shift slices)
+    if (!src_live_fused(S, sh, n, k)) {
+        // a finished source stays finished (its counts go to zero); past the
+        // iteration limit the counts are kept for the host
+        if (k <= sh.maxk && threadIdx.x == 0)
+            for (int q = sb; q < sh.nslices; q += nsb)
+                sh.cnt[((size_t)(k & 1) * sh.nsrc + n) * kMaxSlices + q] = 0;
+        return;
+    }
+    SeedScalars sc{};
+    sc.alpha = make_double2(0, 0);
+    sc.beta = make_double2(0, 0);
+    if (k > 0) {
+        sc = seed_scalars_from(J.part_w + (size_t)((k - 1) & 1) * J.part_stride + (size_t)n * nsb,
+                               nsb, shm);
+        if (sc.status) {
+            if (sb == 0 && threadIdx.x == 0) S.status = sc.status;
+            if (threadIdx.x == 0)
+                for (int q = sb; q < sh.nslices; q += nsb)
+                    sh.cnt[((size_t)(k & 1) * sh.nsrc + n) * kMaxSlices + q] = 0;
+            return;
+        }
+    }
+    const uint32_t V = (uint32_t)J.g.V, Vt = (uint32_t)J.g.Vt;
+    const uint32_t s = (uint32_t)sb * kBlock + threadIdx.x;
+    const bool valid = s < V;
+    const size_t n12 = (size_t)12 * Vt;
+    const C2<R>* rin = job_rk<const C2<R>>(J, k > 0 ? k - 1 : 0, f) + (size_t)n * n12;
+    C2<R>* rout = job_rk<C2<R>>(J, k, f) + (size_t)n * n12;
+    const C2<R>* qin = static_cast<const C2<R>*>(J.q[f]) + (size_t)((k - 1) & 1) * J.qpp + (size_t)n * n12;
+    C2<R>* qout = static_cast<C2<R>*>(J.q[f]) + (size_t)(k & 1) * J.qpp + (size_t)n * n12;
+    // kernel 0 applies A to r_0 = b itself: no combination and no q term
+    FusedIn<R, 1> fi;
+    fi.q[0] = k > 0 ? qin : rin;
+    fi.a[0] = mk<R>((R)sc.alpha.x, (R)sc.alpha.y);
+    const C2<R>* psi[1] = {rin};
+    const uint32_t s0 = (uint32_t)sb * kBlock;
+    __shared__ C2<R> lt[TIL ? 12 * kBlock : 1];
+    // the block's own r_k: formed once, stored as the new basis vector, and
+    // (TIL) kept in LDS for the neighbours inside the block
+    auto own_rk = [&](uint32_t comp) -> cx<R> {
+        const uint32_t o = tix(comp, s, 12);
+        const cx<R> rv = ld<R>(rin, o);
+        if (k == 0) return rv;
+        const cx<R> qv = ld<R>(qin, o);
+        const cx<R> al = fi.a[0];
+        return mk<R>(rv.re - (al.re * qv.re - al.im * qv.im), rv.im - (al.re * qv.im + al.im * qv.re));
+    };
+    if constexpr (TIL == 1) {
+        if (valid) {
+#pragma unroll
+            for (uint32_t comp = 0; comp < 12; ++comp) {
+                const cx<R> v = own_rk(comp);
+                C2<R> w;
+                w.x = v.re;
+                w.y = v.im;
+                lt[comp * kBlock + threadIdx.x] = w;
+                if (k > 0) stc<R>(rout, tix(comp, s, 12), v);
+            }
+        }
+        __syncthreads();
+    }
+    cx<R> acc[1][4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[0][a][c] = mk<R>(0, 0);
+    if (valid) {
+        uint32_t rem = s;
+        int coord[4];
+        coord[0] = (int)(rem % (uint32_t)J.g.L[0]); rem /= (uint32_t)J.g.L[0];
+        coord[1] = (int)(rem % (uint32_t)J.g.L[1]); rem /= (uint32_t)J.g.L[1];
+        coord[2] = (int)(rem % (uint32_t)J.g.L[2]);
+        coord[3] = (int)(rem / (uint32_t)J.g.L[2]);
+        dslash_site<R, HPI, 1, 1, TIL, LNK, 0, 1>(acc, psi, static_cast<const C2<R>*>(J.U[f]), J.g,
+                                                  s, coord, 0, lt, s0, nullptr, &fi);
+    }
+    double dre = 0.0, dim = 0.0, dqq = 0.0, drr = 0.0;
+    const R kap = (R)J.kappa, zr = (R)J.zs.x, zi = (R)J.zs.y;
+    const R br = (R)sc.beta.x, bi = (R)sc.beta.y;
+    const bool acc2 = J.h != nullptr && k > 0;
+    const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k] : make_double2(0, 0);
+    double2* sacc = J.s64 + (size_t)n * n12;
+    if (valid) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t comp = (uint32_t)(3 * a + c);
+                const uint32_t o = tix(comp, s, 12);
+                const cx<R> qo = k > 0 ? ld<R>(qin, o) : mk<R>(0, 0);
+                cx<R> r;
+                if constexpr (TIL == 1) {
+                    const C2<R> w = lt[comp * kBlock + threadIdx.x];
+                    r = mk<R>(w.x, w.y);
+                } else {
+                    r = ld<R>(rin, o);
+                    if (k > 0) {
+                        const cx<R> al = fi.a[0];
+                        r = mk<R>(r.re - (al.re * qo.re - al.im * qo.im),
+                                  r.im - (al.re * qo.im + al.im * qo.re));
+                        stc<R>(rout, o, r);
+                    }
+                }
+                // H r = gamma5 (r - kappa acc); q_k = z_s r - H r + beta q_{k-1}
+                cx<R> hv = r - kap * acc[0][a][c];
+                if (a >= 2) hv = -hv;
+                cx<R> q = mk<R>(zr * r.re - zi * r.im - hv.re, zr * r.im + zi * r.re - hv.im);
+                if (k > 0) {
+                    q.re += br * qo.re - bi * qo.im;
+                    q.im += br * qo.im + bi * qo.re;
+                }
+                stc<R>(qout, o, q);
+                dre += (double)r.re * (double)q.re + (double)r.im * (double)q.im;
+                dim += (double)r.re * (double)q.im - (double)r.im * (double)q.re;
+                dqq += (double)q.re * (double)q.re + (double)q.im * (double)q.im;
+                drr += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+                if (acc2) {
+                    double2 sv = sacc[o];
+                    sv.x += hk.x * (double)r.re - hk.y * (double)r.im;
+                    sv.y += hk.x * (double)r.im + hk.y * (double)r.re;
+                    sacc[o] = sv;
+                }
+            }
+        }
+    } else if (s < Vt) {
+        // padding sites of the last layout tile stay zero in every output
+#pragma unroll
+        for (uint32_t comp = 0; comp < 12; ++comp) {
+            const uint32_t o = tix(comp, s, 12);
+            stc<R>(qout, o, mk<R>(0, 0));
+            if (k > 0) stc<R>(rout, o, mk<R>(0, 0));
+        }
+    }
+    {
+        const double tr = block_sum<kBlock>(dre, shm);
+        const double ti_ = block_sum<kBlock>(dim, shm);
+        const double tq = block_sum<kBlock>(dqq, shm);
+        const double tn = block_sum<kBlock>(drr, shm);
+        if (threadIdx.x == 0)
+            J.part_w[(size_t)(k & 1) * J.part_stride + (size_t)n * nsb + sb] =
+                make_double4(tr, ti_, tq, tn);
+    }
+    if (k == 0) return;
+    // iteration k-1 of the scalars: the seed's (block (0, n)) and the shifts'
+    if (sb == 0 && threadIdx.x == 0) {
+        S.alpha[(k - 1) & 1] = sc.alpha;
+        S.beta[(k - 1) & 1] = sc.beta;
+        S.rr[(k - 1) & 1] = sc.rr;
+        S.iter = k;
+        if (sh.seed != nullptr) {
+            double2* sd = sh.seed + ((size_t)n * (sh.maxk + 1) + (k - 1)) * 3;
+            sd[0] = sc.alpha;
+            sd[1] = sc.beta;
+            sd[2] = make_double2(sc.rr, sc.rrn);
+        }
+    }
+    for (int q = sb; q < sh.nslices; q += nsb) advance_shift_slice(sh, S, n, q, k - 1, sc, shm);
+}
+
+template <typename R, int HPI, int ORD, int TIL, int LNK>
+__global__ __launch_bounds__(kBlock) void k_iter_jobs(const JobDesc* __restrict__ jobs, int njobs,
+                                                      const int* __restrict__ kread,
+                                                      int* __restrict__ kwrite) {
+    const int k = (int)uniform((uint32_t)*kread);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *kwrite = k + 1;
+    const unsigned gb = uniform(xcd_remap(blockIdx.x, gridDim.x));
+    int j = 0;
+    const int f = sizeof(R) == 4 ? 1 : 0;
+    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
+    iter_block<R, HPI, ORD, TIL, LNK>(jobs[j], k, gb - (unsigned)jobs[j].sten_b0[f]);
+}
+
+int iter_grid_blocks(const Geom& g, int nrhs) { return wilson_blocks(g) * nrhs; }
+
+// Variant v < kIterVariants of the fused iteration: hops per loop step
+// (bit 0: 1 or 2), block order (bit 1: rhs fastest or sites fastest), LDS
+// tile of the block's r_k (bit 2).
+template <typename R>
+void launch_iter_jobs(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
+                      int total_blocks, int variant, int lnk, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1) {
+    auto go = [&](auto kern) {
+        if (ev0)
+            hipExtLaunchKernelGGL(kern, dim3(total_blocks), dim3(kBlock), 0, s, ev0, ev1, 0, jobs,
+                                  njobs, kread, kwrite);
+        else
+            hipLaunchKernelGGL(kern, dim3(total_blocks), dim3(kBlock), 0, s, jobs, njobs, kread,
+                               kwrite);
+    };
+    using std::integral_constant;
+    auto pick = [&](auto H, auto O, auto T) {
+        if (lnk) go(k_iter_jobs<R, H.value, O.value, T.value, 1>);
+        else go(k_iter_jobs<R, H.value, O.value, T.value, 0>);
+    };
+    switch (variant) {
+#define OVL_IV(n)                                                                             \
+    case n:                                                                                   \
+        pick(integral_constant<int, ((n)&1) + 1>{}, integral_constant<int, ((n) >> 1) & 1>{}, \
+             integral_constant<int, ((n) >> 2) & 1>{});                                       \
+        break;
+        OVL_IV(1) OVL_IV(2) OVL_IV(3) OVL_IV(4) OVL_IV(5) OVL_IV(6) OVL_IV(7)
+#undef OVL_IV
+        default:
+            pick(integral_constant<int, 1>{}, integral_constant<int, 0>{}, integral_constant<int, 0>{});
+    }
+}
+template void launch_iter_jobs<double>(const JobDesc*, int, const int*, int*, int, int, int,
+                                       hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_iter_jobs<float>(const JobDesc*, int, const int*, int*, int, int, int,
+                                      hipStream_t, hipEvent_t, hipEvent_t);
 
 int wilson_blocks(const Geom& g) { return (int)((g.V + kBlock - 1) / kBlock); }
 // right-hand sides per block of a variant: the rhs per lane (variants < 24)

@@ -35,7 +35,7 @@ EXPORTS = [
     "ovl_last_error",
 ]
 PROFILE_CLASSES = ["stencil64", "stencil32", "vector64", "vector32", "sweep64", "sweep32",
-                   "basis_sum", "scalars"]
+                   "basis_sum", "scalars", "iter64", "iter32"]
 
 
 class Stats(ctypes.Structure):
@@ -49,7 +49,9 @@ class Stats(ctypes.Structure):
         ("stencil_variant64", ctypes.c_int32),
         ("stencil_variant32", ctypes.c_int32),
         ("max_true_rel_res", ctypes.c_double),
-        ("reserved", ctypes.c_double * 2),
+        ("fp64_repeat", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("mixed_true_rel_res", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -213,8 +215,10 @@ class Context:
         return tuple(b)
 
     def set_residual_check(self, nsample):
-        """After each apply, check the true residual of the `nsample` shifts per
-        rhs with the largest residual estimates (Stats.max_true_rel_res)."""
+        """nsample >= 1: after each apply also check the true residual of the
+        `nsample` shifts per rhs with the largest residual estimates; 0: the
+        in-band check of the basis form only (default); -1: no check
+        (Stats.max_true_rel_res)."""
         self._rc(self.lib.ovl_set_residual_check(self._h, int(nsample)), "ovl_set_residual_check")
 
     # -- operators ------------------------------------------------------------
@@ -271,19 +275,22 @@ class Context:
 
         kind 0: traceless hermitian force F (dS/dh = sum tr(Omega F) for
         U -> exp(i h Omega) U); kind 1: complex gradient G with
-        dS = Re sum conj(G) dU.  Returns (tensor [4, Lt, Lz, Ly, Lx, 3, 3], S, Stats).
+        dS = Re sum conj(G) dU; kind 2: the action alone (the tensor is None).
+        Returns (tensor [4, Lt, Lz, Ly, Lx, 3, 3] or None, S, Stats).
         """
         phi = self._spinor_in(phi)
         if phi.shape[0] != 1:
             raise ValueError("force takes one phi")
-        out = torch.empty((4,) + self.site_shape + (3, 3), dtype=torch.complex128,
-                          device=phi.device)
+        out = None
+        if kind != 2:
+            out = torch.empty((4,) + self.site_shape + (3, 3), dtype=torch.complex128,
+                              device=phi.device)
         S = ctypes.c_double()
         st = Stats()
         self._sync_stream()
         rc = self.lib.ovl_force(self._h, ctypes.c_void_p(phi.data_ptr()),
-                                ctypes.c_void_p(out.data_ptr()), int(kind), int(shift_chunk),
-                                ctypes.byref(S), ctypes.byref(st))
+                                ctypes.c_void_p(out.data_ptr() if out is not None else None),
+                                int(kind), int(shift_chunk), ctypes.byref(S), ctypes.byref(st))
         self._rc(rc, "ovl_force")
         if rc == NOT_CONVERGED and not allow_not_converged:
             raise OvlError(rc, self.lib.ovl_last_error(self._h).decode())
@@ -359,8 +366,11 @@ class OverlapAction(torch.autograd.Function):
     @staticmethod
     def forward(fctx, U, phi, context):
         context.set_gauge(U.detach().contiguous())
-        G, S, _ = context.force(phi.detach().contiguous(), kind=1)
-        fctx.save_for_backward(G)
+        if fctx.needs_input_grad[0]:
+            G, S, _ = context.force(phi.detach().contiguous(), kind=1)
+            fctx.save_for_backward(G)
+        else:  # no gradient wanted: one solve for S alone
+            _, S, _ = context.force(phi.detach().contiguous(), kind=2)
         return torch.tensor(S, dtype=torch.float64, device=U.device)
 
     @staticmethod

@@ -31,15 +31,22 @@ def test_roofline_takes_the_class_with_the_largest_time():
 
 
 def test_stored_traffic_only_for_the_measured_kernel():
-    rec = json.load(open(bench.COUNTERS))
-    src = open(os.path.join(ROOT, "paper_2204_01583_amd", "csrc", "stencil.hip"), "rb").read()
-    same_source = hashlib.sha256(src).hexdigest()[:16] == rec["kernel_source_sha256_16"]
-    got = bench.measured_traffic(rec["variant"])
-    if same_source:
-        assert got == rec["traffic_bytes_per_launch"]
-    else:
-        assert got is None
-    assert bench.measured_traffic(rec["variant"] + 1) is None   # another variant
+    for kclass in ("iter32", "stencil32"):
+        path = bench.counters_path(kclass)
+        if not os.path.exists(path):
+            assert bench.measured_traffic(kclass, 0) is None
+            continue
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2204_01583_amd", "csrc", rec["kernel_source"]),
+                   "rb").read()
+        same_source = hashlib.sha256(src).hexdigest()[:16] == rec["kernel_source_sha256_16"]
+        got = bench.measured_traffic(kclass, rec["variant"])
+        if same_source:
+            assert got == rec["traffic_bytes_per_launch"]
+        else:
+            assert got is None
+        assert bench.measured_traffic(kclass, rec["variant"] + 1) is None   # another variant
+    assert bench.measured_traffic("no_such_class", 0) is None
 
 
 def test_more_than_one_gpu_is_refused():

@@ -142,3 +142,36 @@ def test_batched_single_contour_matches_single_solves():
         assert relerr(o.cpu().numpy(), ref.cpu().numpy()) < 1e-13
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_each_size_class_against_the_oracle():
+    """One batched mixed-precision two-pass solve over one field of each size
+    class of the uneven workload (8^4, 12^4, 16^3x32; roughness 0.2, 0.27,
+    0.4) with the lead's node set: 4 stratified nodes of the 2 x 64 circle
+    with their eq. (7) weights.  Every job against the oracle's independent
+    solves on the same nodes, relative 2-norm and element-wise, to 1e-10."""
+    from oracle.contour import nodes
+    from oracle.sign import sign_by_solves
+    from tests.gpu_util import NPROC, assert_close, oracle_H
+    from paper_2204_01583_amd import ovl
+    z, c = nodes(64, *CIRCLE)
+    pick = np.array([5, 37, 69, 101])
+    jobs = [((8, 8, 8, 8), 0.2, 0), ((12, 12, 12, 12), 0.2 + 0.2 / 3, 11),
+            ((16, 16, 16, 32), 0.4, 23)]
+    ctxs, ins, refs = [], [], []
+    for dims, r, seed in jobs:
+        U = gauge(dims, r, seed)
+        b = si.gaussian_sources(dims, 1, first_seed=1000)
+        ctx = make_ctx(dims, U, precision=1, form=3, tol=1e-12, switch_res=1e-4)
+        ctxs.append(ctx)
+        ins.append(to_dev(b))
+        refs.append(sign_by_solves(oracle_H(dims, r, seed, 1.4), b[0].ravel(), z[pick], c[pick],
+                                   method="gmres", rtol=1e-14, processes=min(NPROC, 4)))
+    ctxs[0].set_nodes(z[pick], c[pick])
+    outs, st = ovl.apply_sign_batched(ctxs, ins)
+    assert st.n_active_end == 0 and st.fp32_iterations > 0
+    for (dims, _, _), o, ref in zip(jobs, outs, refs):
+        assert_close(o.cpu().numpy()[0], ref, 1e-10, f"batched {dims}")
+    for ctx in ctxs:
+        ctx.close()

@@ -138,3 +138,60 @@ def test_autograd_gradcheck():
     S.backward()
     assert U.grad is not None and U.grad.shape == U.shape
     ctx.close()
+
+
+@pytest.mark.parametrize("precision,chunk,tol", [(0, 0, 1e-10), (0, 7, 1e-10), (1, 16, 1e-8)])
+def test_force_4x4_matches_oracle_elementwise(precision, chunk, tol):
+    """4^4 (roughness 0.3, 2 x 16 circle nodes): G and F against the oracle's
+    force (independent sparse solves per node), element by element, with all
+    shifts at once and in chunks that do not divide the shift count; FP64 and
+    mixed precision."""
+    from tests.gpu_util import assert_close
+    dims, m0, mq, nq = (4, 4, 4, 4), 1.4, 0.1, 16
+    U = gauge(dims, 0.3, 0)
+    phi = si.gaussian_sources(dims, 1, first_seed=23)[0]
+    z, c = nodes(nq, *CIRCLE)
+    G_ref, F_ref, S_ref = oracle_force(U, phi, m0, mq, z, c, method="splu")
+    ctx = make_ctx(dims, U, m0, mq, nq, precision=precision, form=2, tol=1e-13 if precision == 0
+                   else 1e-12)
+    G, S, st = ctx.force(to_dev(phi), kind=1, shift_chunk=chunk)
+    F, S2, _ = ctx.force(to_dev(phi), kind=0, shift_chunk=chunk)
+    assert abs(S - S_ref) / S_ref < 1e-11 and S2 == S
+    assert_close(G.cpu().numpy(), G_ref, tol, f"G p{precision} chunk {chunk}")
+    assert_close(F.cpu().numpy(), F_ref, tol, f"F p{precision} chunk {chunk}")
+    ctx.close()
+
+
+def test_force_chunks_agree_and_action_only():
+    """The chunk size changes only which shifts are rebuilt together, not the
+    sums (every link sums its shifts in the same order): kind 1 with chunks of
+    1, 5 and all shifts is the same to rounding, and kind 2 returns the same
+    S from one solve without touching grad."""
+    dims, m0, mq, nq = (4, 4, 4, 8), 1.4, 0.1, 16
+    U = gauge(dims, 0.3, 1)
+    phi = to_dev(si.gaussian_sources(dims, 1, first_seed=29))
+    ctx = make_ctx(dims, U, m0, mq, nq, form=2, tol=1e-12)
+    G0, S0, _ = ctx.force(phi, kind=1, shift_chunk=0)
+    for chunk in (1, 5):
+        G, S, _ = ctx.force(phi, kind=1, shift_chunk=chunk)
+        assert S == S0
+        assert float((G - G0).abs().max() / G0.abs().max()) < 1e-14
+    none, S1, st = ctx.force(phi, kind=2)
+    assert none is None and S1 == S0 and st.iterations > 0
+    ctx.close()
+
+
+def test_overlap_action_forward_without_gradient():
+    """OverlapAction with a U that needs no gradient computes S alone (the
+    action-only kind), equal to the S of the gradient path."""
+    import torch
+    from paper_2204_01583_amd import ovl
+    dims = (2, 2, 2, 4)
+    U = to_dev(gauge(dims, 0.3, 4))
+    phi = to_dev(si.gaussian_sources(dims, 1, first_seed=9))
+    ctx = make_ctx(dims, gauge(dims, 0.3, 4), 1.4, 0.1, 8, form=2, tol=1e-14)
+    S_plain = ovl.OverlapAction.apply(U, phi, ctx)
+    S_grad = ovl.OverlapAction.apply(U.clone().requires_grad_(True), phi, ctx)
+    assert S_plain.requires_grad is False and S_grad.requires_grad is True
+    assert float(S_plain) == float(S_grad)
+    ctx.close()

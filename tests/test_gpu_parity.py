@@ -322,7 +322,8 @@ def test_stencil_variants(variant, links, monkeypatch):
         monkeypatch.setenv("OVL_LINKS", "full")
     dims = (4, 6, 4, 8)
     U = gauge(dims, 0.3, 1)
-    ctx = make_ctx(dims, U, nq=16, precision=1, form=2)
+    # the sweep form runs the two-kernel iteration, whose stencil is the forced variant
+    ctx = make_ctx(dims, U, nq=16, precision=1, form=1)
     H = oracle_H(dims, 0.3, 1, 1.4)
     for nrhs in (1, 3):
         b = si.gaussian_sources(dims, nrhs, first_seed=7)
@@ -555,4 +556,104 @@ def test_sign_16x16x16x16_oracle_node_sample():
         for n in range(4):
             assert_close(s[n], refs[n], tol, f"16^4 precision {precision} source {n} "
                          f"({st.iterations} iterations, {st.fp32_iterations} FP32)")
+        ctx.close()
+
+
+def test_inband_residual_check_matches_synchronous_check():
+    """The in-band check (basis form, default on) rebuilds every source's
+    worst shifted solution inside the final basis sum and reports its FP64
+    true residual; the synchronous diagnostic of the same worst shift gives
+    the same value, and -1 turns both off."""
+    dims = (4, 4, 4, 8)
+    U = gauge(dims, 0.3, 3)
+    b = to_dev(si.gaussian_sources(dims, 2, first_seed=31))
+    ctx = make_ctx(dims, U, nq=32, precision=0, form=2, tol=1e-10)
+    _, st0 = ctx.apply_sign(b)
+    assert 0.0 < st0.max_true_rel_res < 2e-10, st0.max_true_rel_res
+    ctx.set_residual_check(1)
+    _, st1 = ctx.apply_sign(b)
+    assert abs(st1.max_true_rel_res - st0.max_true_rel_res) <= 1e-6 * st0.max_true_rel_res
+    ctx.set_residual_check(-1)
+    _, st2 = ctx.apply_sign(b)
+    assert st2.max_true_rel_res == -1.0
+    assert st0.fp64_repeat == 0 and st0.mixed_true_rel_res == -1.0
+    ctx.close()
+
+
+def test_mixed_repeats_in_fp64_when_the_check_fails():
+    """Mixed precision switched to FP32 very early (at 1e-2) cannot reach a
+    1e-14 tolerance in true residual: the in-band check sees the drift, the
+    apply is solved again in FP64, and the result is the FP64 one (oracle
+    parity at 1e-11).  With the default switch at tol 1e-12 no repeat is
+    needed."""
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    b = si.gaussian_sources(c["dims"], 1)[0]
+    ref = oracle_sign(c["dims"], c["r"], c["seed"], c["m0"], c["nq"], CIRCLE, 1000)
+    ctx = make_ctx(c["dims"], U, c["m0"], c["mq"], c["nq"], precision=1, form=2, tol=1e-14,
+                   switch_res=1e-2)
+    s, st = ctx.apply_sign(to_dev(b))
+    print("repeat", st.fp64_repeat, "mixed true res", st.mixed_true_rel_res,
+          "final", st.max_true_rel_res)
+    assert st.fp64_repeat == 1 and st.mixed_true_rel_res > 1e-13
+    assert st.fp32_iterations == 0 and st.max_true_rel_res <= 1e-13
+    assert_close(s.cpu().numpy(), ref, 1e-11, "after the FP64 repeat")
+    ctx.set_solver(1, 2, tol=1e-12, switch_res=1e-4)
+    s, st = ctx.apply_sign(to_dev(b))
+    assert st.fp64_repeat == 0 and st.fp32_iterations > 0 and st.max_true_rel_res < 1e-11
+    ctx.close()
+
+
+@pytest.mark.parametrize("links", ["two-row", "full"])
+@pytest.mark.parametrize("variant", list(range(8)))
+def test_fused_iteration_variants(variant, links, monkeypatch):
+    """Every variant of the fused one-kernel iteration (hops per loop step,
+    block order, LDS tile of the block's r_k) in both link formats: basis and
+    two-pass forms, FP64 and mixed, three sources, against the oracle; on a
+    lattice with a partial 256-site block and one with a partial 64-site
+    layout tile.  The two forms run the same iterations (the same count)
+    and differ only in the order in which they sum s."""
+    monkeypatch.setenv("OVL_ITER_VARIANT", str(variant))
+    if links == "full":
+        monkeypatch.setenv("OVL_LINKS", "full")
+    fmt = 0 if links == "full" else 1
+    for dims, seed in (((6, 6, 4, 6), 2), ((3, 5, 4, 6), 5)):
+        U = gauge(dims, 0.3, seed)
+        H = oracle_H(dims, 0.3, seed, 1.4)
+        b = si.gaussian_sources(dims, 3, first_seed=9)
+        z, c = nodes(16, *CIRCLE)
+        from oracle.sign import sign_by_solves
+        refs = [sign_by_solves(H, b[n].ravel(), z, c, method="gmres", processes=NPROC)
+                for n in range(3)]
+        for precision, tol in ((0, 1e-11), (1, 1e-10)):
+            outs, iters = [], []
+            for form in (2, 3):
+                ctx = make_ctx(dims, U, nq=16, precision=precision, form=form)
+                s, st = ctx.apply_sign(to_dev(b))
+                assert st.stencil_variant64 == 1000 + variant + 8 * fmt
+                for n in range(3):
+                    assert_close(s[n].cpu().numpy(), refs[n], tol,
+                                 f"fused v{variant} {links} {dims} p{precision} f{form} {n}")
+                outs.append(s.cpu().numpy())
+                iters.append((st.iterations, st.fp32_iterations))
+                ctx.close()
+            assert iters[0] == iters[1]
+            # mixed: the basis form stores the iterate at the switch in FP32,
+            # the two-pass form adds it in FP64 (a difference of ~eps32 * switch)
+            assert relerr(outs[1], outs[0]) < (1e-13 if precision == 0 else 1e-11)
+
+
+def test_two_kernel_basis_iteration_still_matches(monkeypatch):
+    """The basis form on the two-kernel iteration (OVL_FUSED=0, with the
+    seed direction p) against the oracle, FP64 and mixed."""
+    monkeypatch.setenv("OVL_FUSED", "0")
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    b = si.gaussian_sources(c["dims"], 1)[0]
+    ref = oracle_sign(c["dims"], c["r"], c["seed"], c["m0"], c["nq"], CIRCLE, 1000)
+    for precision, tol in ((0, 1e-11), (1, 1e-10)):
+        ctx = make_ctx(c["dims"], U, c["m0"], c["mq"], c["nq"], precision=precision, form=2)
+        s, st = ctx.apply_sign(to_dev(b))
+        assert st.stencil_variant64 < 1000
+        assert_close(s.cpu().numpy(), ref, tol, f"two-kernel basis p{precision}")
         ctx.close()
