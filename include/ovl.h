@@ -169,9 +169,9 @@ int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, in
  * ||b - (z_j - H_W) x_j|| / ||b|| is computed in FP64 with one more FP64
  * stencil; the maximum over the rhs goes to ovl_stats.max_true_rel_res.  In
  * OVL_PREC_MIXED, when every shift met tol by its estimate but this true
- * residual exceeds 10 tol (the FP32 phase drifted), the apply is solved again
- * in FP64 (ovl_stats.fp64_repeat = 1); if that also misses, the call returns
- * OVL_NOT_CONVERGED.  The other forms report -1 for the in-band check.
+ * residual exceeds the bound of ovl_set_check_bound, the apply is solved
+ * again in FP64 (ovl_stats.fp64_repeat = 1); if that misses 10 tol, the call
+ * returns OVL_NOT_CONVERGED.  The other forms report -1 for the in-band check.
  * nsample >= 1 adds a synchronous diagnostic after each ovl_apply_sign /
  * ovl_apply_dov: for the nsample shifts of each rhs with the largest final
  * estimate, x_j is formed (stored by OVL_FORM_REFERENCE, rebuilt from the
@@ -180,6 +180,17 @@ int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, in
  * nsample = 0 (default) keeps the in-band check only; nsample = -1 turns the
  * in-band check off as well.  nsample in [-1, 64], else OVL_E_ARG. */
 int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample);
+
+/* The bound on the in-band true residual above which an OVL_PREC_MIXED apply
+ * is repeated in FP64 (see ovl_set_residual_check).  The FP32 phase, which
+ * starts once every shifted residual is below switch_res, adds to the true
+ * residual a drift of about eps32 * switch_res (eps32 = 2^-24) that the
+ * recurrence's estimates do not see; bound = 0 (default) takes
+ * max(10 tol, 10 eps32 switch_res), so only more drift than that triggers the
+ * repeat.  A caller that needs every apply's true residual within 10 tol sets
+ * bound = 10 tol (mixed applies whose drift exceeds it then cost an FP64
+ * solve more).  OVL_E_ARG for a negative or non-finite bound. */
+int ovl_set_check_bound(ovl_ctx* ctx, double bound);
 
 /* out = H_W in for nrhs spinors (eq. (1): H_W = gamma5 D_W(-m0)).  out must
  * not alias in. */

@@ -278,11 +278,12 @@ __device__ __forceinline__ SeedScalars seed_scalars(const JobDesc& J, int n, dou
 
 // The seed iteration's second kernel (after the stencil), for every form:
 // scalars, shift bookkeeping (the 256-shift slice of block bx), then one pass
-// over the components: r_{k+1} = r_k - alpha q and either p = r_{k+1} + beta p
-// (basis forms; two-pass second pass also s += h_{k+1} r_{k+1}) or the shift
-// sweep (fused: s += c_j alpha^j p_j; reference: x_j += alpha^j p_j; then
-// p_j = r_{k+1}/pi_{k+1} + beta^j p_j and p = r_{k+1} + beta p).  In the
-// first iteration p_j = b for every j, read from b instead.
+// over the components: r_{k+1} = r_k - alpha q (basis forms; two-pass second
+// pass also s += h_{k+1} r_{k+1}), or that with the shift sweep (fused:
+// s += c_j alpha^j p_j; reference: x_j += alpha^j p_j; then
+// p_j = r_{k+1}/pi_{k+1} + beta^j p_j).  In the first iteration p_j = b for
+// every j, read from b instead.  The seed direction p is never formed: the
+// stencil builds q_{k+1} = A r_{k+1} + beta_k q_k from r_{k+1} directly.
 template <typename R, int KIND>  // KIND 0 basis / two-pass, 1 fused sweep, 2 reference sweep
 __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, int k) {
     constexpr bool SWEEP = KIND != 0;
@@ -387,11 +388,9 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
     }
     const int64_t n12 = 12 * J.g.Vt;
     const R ar = (R)sc.alpha.x, ai = (R)sc.alpha.y;
-    const R br = (R)sc.beta.x, bi = (R)sc.beta.y;
     const C2<R>* ri = job_rk<const C2<R>>(J, k, f) + (size_t)n * n12;
     C2<R>* ro = job_rk<C2<R>>(J, k + 1, f) + (size_t)n * n12;
     const C2<R>* qq = static_cast<const C2<R>*>(J.q[f]) + (size_t)n * n12;
-    C2<R>* pp = static_cast<C2<R>*>(J.p[f]) + (size_t)n * n12;
     if constexpr (!SWEEP && sizeof(R) == 4) {
         // FP32: two components per lane in one 16-byte access of each array
         // (every vector starts 16-byte aligned and 12 Vt is even)
@@ -401,21 +400,15 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
         const float4* ri4 = reinterpret_cast<const float4*>(ri);
         const float4* qq4 = reinterpret_cast<const float4*>(qq);
         float4* ro4 = reinterpret_cast<float4*>(ro);
-        float4* pp4 = reinterpret_cast<float4*>(pp);
         const int64_t n2 = n12 / 2;
         for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n2; e += (int64_t)J.nbe * kBlock) {
-            const float4 r = ri4[e], qv = qq4[e], po = pp4[e];
-            float4 rn, pn;
+            const float4 r = ri4[e], qv = qq4[e];
+            float4 rn;
             rn.x = r.x - ((float)ar * qv.x - (float)ai * qv.y);
             rn.y = r.y - ((float)ar * qv.y + (float)ai * qv.x);
             rn.z = r.z - ((float)ar * qv.z - (float)ai * qv.w);
             rn.w = r.w - ((float)ar * qv.w + (float)ai * qv.z);
-            pn.x = rn.x + (float)br * po.x - (float)bi * po.y;
-            pn.y = rn.y + (float)br * po.y + (float)bi * po.x;
-            pn.z = rn.z + (float)br * po.z - (float)bi * po.w;
-            pn.w = rn.w + (float)br * po.w + (float)bi * po.z;
             ro4[e] = rn;
-            pp4[e] = pn;
             if (acc2) {
                 double2 s0 = sacc[2 * e], s1 = sacc[2 * e + 1];
                 s0.x += hk.x * (double)rn.x - hk.y * (double)rn.y;
@@ -431,10 +424,9 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
         const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
         double2* sacc = J.s64 + (size_t)n * n12;
         for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
-            const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e), po = ld<R>(pp, e);
+            const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e);
             const cx<R> rn = mk<R>(r.re - (ar * qv.re - ai * qv.im), r.im - (ar * qv.im + ai * qv.re));
             stc<R>(ro, e, rn);
-            stc<R>(pp, e, mk<R>(rn.re + br * po.re - bi * po.im, rn.im + br * po.im + bi * po.re));
             if (acc2) {
                 double2 sv = sacc[e];
                 sv.x += hk.x * (double)rn.re - hk.y * (double)rn.im;
@@ -479,8 +471,6 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
                 sv.y += sim;
                 acc_out[(size_t)n * n12 + e] = sv;
             }
-            const cx<R> po = ld<R>(pp, e);
-            stc<R>(pp, e, mk<R>(rv.re + br * po.re - bi * po.im, rv.im + br * po.im + bi * po.re));
         }
     }
 }

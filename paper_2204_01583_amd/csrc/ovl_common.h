@@ -151,7 +151,6 @@ struct JobDesc {
     size_t part_stride;         // fused iteration: elements between the two partial arrays
     size_t qpp;                 // fused iteration: elements between q[k&1 = 0] and q[1]
     // working vectors [nsrc][12 Vt], index [0] FP64, [1] FP32
-    void* p[2];
     void* q[2];
     void* r[2];                 // fused/reference: r in place; two-pass: r_k at r[..] + (k&1) * rpp
     size_t rpp;                 // two-pass: element offset of the second r buffer

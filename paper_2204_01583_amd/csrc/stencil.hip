@@ -364,7 +364,15 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
         for (int r = 0; r < RPT; ++r) {
             if (!on[r]) continue;
             C2<R>* o = out + (size_t)(n0 + r) * 12 * Vt;
-            const C2<R>* rd = (MODE == 1) ? rdot + (size_t)(n0 + r) * 12 * Vt : nullptr;
+            // solver form: beta_{k-1} of this rhs (written by the previous update)
+            R br = 0, bi = 0;
+            if constexpr (MODE == 1) {
+                if (k > 0) {
+                    const double2 b = stt[n0 + r].beta[(k - 1) & 1];
+                    br = (R)b.x;
+                    bi = (R)b.y;
+                }
+            }
 #pragma unroll
             for (int ai = 0; ai < NA; ++ai) {
                 const int a = SPL == 2 ? 2 * h + ai : ai;
@@ -384,16 +392,21 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
                     if constexpr (MODE == 0) {
                         stc<R>(o, tix(comp, s, 12), hv);
                     } else {
-                        // q = zs p - H p
+                        // q_k = z_s r_k - H r_k + beta_{k-1} q_{k-1}, in place (this lane
+                        // reads its own q_{k-1} before it writes q_k)
                         const R zr = (R)zsr, zi = (R)zsi;
                         cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
+                        if (k > 0) {
+                            const cx<R> qo = ld<R>(o, tix(comp, s, 12));
+                            q.re += br * qo.re - bi * qo.im;
+                            q.im += br * qo.im + bi * qo.re;
+                        }
                         stc<R>(o, tix(comp, s, 12), q);
-                        const cx<R> rv = ld<R>(rd, tix(comp, s, 12));
-                        // <r, q> = sum conj(r) q, accumulated in FP64
-                        dre[r] += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
-                        dim[r] += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
+                        // <r_k, q_k> = sum conj(r) q with r_k = p, accumulated in FP64
+                        dre[r] += (double)p.re * (double)q.re + (double)p.im * (double)q.im;
+                        dim[r] += (double)p.re * (double)q.im - (double)p.im * (double)q.re;
                         dqq[r] += (double)q.re * (double)q.re + (double)q.im * (double)q.im;
-                        drr[r] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+                        drr[r] += (double)p.re * (double)p.re + (double)p.im * (double)p.im;
                     }
                 }
             }
@@ -475,7 +488,14 @@ __device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2
         coord[3] = (int)(rem / (uint32_t)g.L[2]);
         dslash_site<R, HPI, 1, 1, 0, LNK, 1>(acc, psi, U, g, s, coord, 0, nullptr, s0, lu);
         C2<R>* o = out + (size_t)n * 12 * Vt;
-        const C2<R>* rd = (MODE == 1) ? rdot + (size_t)n * 12 * Vt : nullptr;
+        R br = 0, bi = 0;
+        if constexpr (MODE == 1) {
+            if (k > 0) {
+                const double2 b = stt[n].beta[(k - 1) & 1];
+                br = (R)b.x;
+                bi = (R)b.y;
+            }
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -489,12 +509,16 @@ __device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2
                 } else {
                     const R zr = (R)zsr, zi = (R)zsi;
                     cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
+                    if (k > 0) {
+                        const cx<R> qo = ld<R>(o, tix(comp, s, 12));
+                        q.re += br * qo.re - bi * qo.im;
+                        q.im += br * qo.im + bi * qo.re;
+                    }
                     stc<R>(o, tix(comp, s, 12), q);
-                    const cx<R> rv = ld<R>(rd, tix(comp, s, 12));
-                    dre += (double)rv.re * (double)q.re + (double)rv.im * (double)q.im;
-                    dim += (double)rv.re * (double)q.im - (double)rv.im * (double)q.re;
+                    dre += (double)p.re * (double)q.re + (double)p.im * (double)q.im;
+                    dim += (double)p.re * (double)q.im - (double)p.im * (double)q.re;
                     dqq += (double)q.re * (double)q.re + (double)q.im * (double)q.im;
-                    drr += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+                    drr += (double)p.re * (double)p.re + (double)p.im * (double)p.im;
                 }
             }
         }
@@ -538,11 +562,10 @@ __global__ __launch_bounds__(kBlock * RB) void k_wilson_jobs_lt(const JobDesc* _
     const int f = sizeof(R) == 4 ? 1 : 0;
     while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
     const JobDesc& J = jobs[j];
-    wilson_block_lt<R, 1, HPI, RB, LNK>(static_cast<const C2<R>*>(J.p[f]),
-                                        static_cast<C2<R>*>(J.q[f]),
+    wilson_block_lt<R, 1, HPI, RB, LNK>(job_rk<const C2<R>>(J, k, f), static_cast<C2<R>*>(J.q[f]),
                                         static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
-                                        J.zs.y, job_rk<const C2<R>>(J, k, f), J.part_w, J.st,
-                                        J.sh, k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0[f]);
+                                        J.zs.y, nullptr, J.part_w, J.st, J.sh, k, J.nsb, J.nsrc,
+                                        gb - (unsigned)J.sten_b0[f]);
 }
 
 template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
@@ -559,9 +582,10 @@ __global__ __launch_bounds__(kBlock * SPL) void k_wilson(const C2<R>* __restrict
                                          k, nsb, nrhs, tile);
 }
 
-// K1 over a job table: q = z_s p - H p and <r_k, q> partials for every job of
-// a batch in one launch; the iteration index k is read from device memory so
-// a captured graph can be replayed for any k.
+// K1 over a job table: q_k = z_s r_k - H r_k + beta_{k-1} q_{k-1} (in place)
+// and the partials <r_k, q_k>, ||q_k||^2, ||r_k||^2 for every job of a batch
+// in one launch; the iteration index k is read from device memory so a
+// captured graph can be replayed for any k.
 template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __restrict__ jobs, int njobs,
                                                         const int* __restrict__ kdev) {
@@ -571,10 +595,11 @@ __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __r
     const int f = sizeof(R) == 4 ? 1 : 0;
     while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
     const JobDesc& J = jobs[j];
-    wilson_block<R, 1, HPI, RPT, ORD, SPL, TIL, LNK>(static_cast<const C2<R>*>(J.p[f]), static_cast<C2<R>*>(J.q[f]),
+    wilson_block<R, 1, HPI, RPT, ORD, SPL, TIL, LNK>(job_rk<const C2<R>>(J, k, f),
+                                      static_cast<C2<R>*>(J.q[f]),
                                       static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
-                                      J.zs.y, job_rk<const C2<R>>(J, k, f), J.part_w, J.st, J.sh,
-                                      k, J.nsb, J.nsrc, gb - (unsigned)J.sten_b0[f]);
+                                      J.zs.y, nullptr, J.part_w, J.st, J.sh, k, J.nsb, J.nsrc,
+                                      gb - (unsigned)J.sten_b0[f]);
 }
 
 // ============================================================================

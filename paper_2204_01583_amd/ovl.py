@@ -28,7 +28,7 @@ BENCH_STENCIL64, BENCH_STENCIL32 = 0, 1
 EXPORTS = [
     "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
     "ovl_set_contour", "ovl_set_contour_single", "ovl_set_nodes", "ovl_set_solver",
-    "ovl_set_residual_check", "ovl_spectral_bounds", "ovl_suggest_contour",
+    "ovl_set_residual_check", "ovl_set_check_bound", "ovl_spectral_bounds", "ovl_suggest_contour",
     "ovl_apply_hw", "ovl_apply_hw_fp32", "ovl_apply_sign",
     "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
     "ovl_bench_kernel", "ovl_set_profiling", "ovl_get_profile", "ovl_status_string",
@@ -88,6 +88,7 @@ def load():
         "ovl_set_nodes": ([P, I, ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "ovl_set_solver": ([P, I, I, D, I, D, D, D], I),
         "ovl_set_residual_check": ([P, I], I),
+        "ovl_set_check_bound": ([P, D], I),
         "ovl_spectral_bounds": ([P, I, P], I),
         "ovl_suggest_contour": ([D, D, D, P, P, P], I),
         "ovl_apply_hw": ([P, P, P, I], I),
@@ -220,6 +221,11 @@ class Context:
         in-band check of the basis form only (default); -1: no check
         (Stats.max_true_rel_res)."""
         self._rc(self.lib.ovl_set_residual_check(self._h, int(nsample)), "ovl_set_residual_check")
+
+    def set_check_bound(self, bound):
+        """True-residual bound above which a mixed apply is repeated in FP64
+        (0: max(10 tol, 10 eps32 switch_res))."""
+        self._rc(self.lib.ovl_set_check_bound(self._h, float(bound)), "ovl_set_check_bound")
 
     # -- operators ------------------------------------------------------------
     def _spinor_in(self, x):
