@@ -196,6 +196,19 @@ int ovl_set_check_bound(ovl_ctx* ctx, double bound);
  * not alias in. */
 int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * out = H_W in as ovl_apply_hw, with the same argument rules, that allocates
+ * nothing.  Its work buffers (the packed input and output, 2 nrhs 12 Vt
+ * complex128, Vt the volume rounded up to 64 sites) live in a static device
+ * array of 64 MiB per GPU, held until the process ends; a larger request
+ * returns OVL_E_ARG.  The stencil choice is the one ovl_apply_hw already
+ * tuned for this nrhs on this context, else the untuned default: the tuner,
+ * which allocates, is never run.  Every context on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other streams, other threads)
+ * race.  The gauge field must be set (ovl_set_gauge allocates). */
+int ovl_apply_hw_noalloc(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs);
+
 /* The same operator through the FP32 stencil that OVL_PREC_MIXED uses after
  * its switch: `in` is rounded to complex64, the links are the context's FP32
  * copy, the arithmetic is FP32, and the result is widened to complex128 in

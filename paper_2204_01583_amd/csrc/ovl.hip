@@ -19,8 +19,37 @@
 
 using namespace ovl;
 
+// Scratch of ovl_apply_hw_noalloc: the packed input and output spinors of one
+// call.  One copy per GPU, held until the process ends.  In host code the
+// name is a host-side stand-in, not a device address: kernels and copies
+// use the per-device address from hipGetSymbolAddress (scratch_address).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 namespace {
 
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (ovl_create); null until then or if the lookup failed.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+bool g_scratch_done[kMaxDevices] = {false};
+
+void* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e == hipSuccess) {
+            g_scratch_ptr[device] = ptr;
+            g_scratch_done[device] = true;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    return g_scratch_ptr[device];
+}
 
 // A device allocation that only grows.  New memory is zeroed before ensure
 // returns, so the padding sites of the tiled layouts start at zero; every
@@ -75,6 +104,7 @@ struct ovl_ctx {
     // OVL_FUSED=1: the basis forms run the fused one-kernel iteration instead
     // of the two-kernel one (stencil, then update)
     bool fused_iter = false;
+    void* scratch = nullptr;  // this device's address of the ovl_apply_hw_noalloc scratch
     // device buffers
     DBuf U64, U32;    // links, tiled [mu][Vt/64][9][64], boundary sign folded in
     DBuf U64c, U32c;  // rows 0 and 1 only, [mu][Vt/64][6][64] (SU(3) fields)
@@ -299,6 +329,12 @@ extern "C" int ovl_create(ovl_ctx** out, const int32_t dims[4], const int32_t bc
     }
     ctx->g.V = V;
     ctx->g.Vt = (V + kTile - 1) / kTile * kTile;
+    {
+        // the no-allocation entry point's scratch on this device (set-up, with
+        // the device current; a failed lookup only disables that entry point)
+        DeviceGuard dg(device);
+        ctx->scratch = scratch_address(device);
+    }
     const char* fz = getenv("OVL_FUSED");
     ctx->fused_iter = fz && fz[0] == '1';
     *out = ctx;
@@ -927,6 +963,34 @@ extern "C" int ovl_apply_hw(ovl_ctx* ctx, const void* in, void* out, int32_t nrh
                           ctx->stream, var, lnk);
     launch_unpack_spinor64(ctx->hw_out.as<double2>(), static_cast<double2*>(out), ctx->g.V, ctx->g.Vt, nrhs,
                            ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    return OVL_OK;
+}
+
+extern "C" int ovl_apply_hw_noalloc(ovl_ctx* ctx, const void* in, void* out, int32_t nrhs) {
+    if (!ctx) return OVL_E_ARG;
+    DeviceGuard dg(ctx->device);
+    int rc = check_apply_args(ctx, in, out, nrhs, false);
+    if (rc) return rc;
+    if (!ctx->scratch) return fail(ctx, OVL_E_HIP, "the static scratch of this device is unavailable");
+    const size_t nb = (size_t)nrhs * n12(ctx) * sizeof(double2);
+    if (2 * nb > kNoAllocScratchBytes)
+        return fail(ctx, OVL_E_ARG,
+                    "nrhs %d needs %zu bytes of scratch; ovl_apply_hw_noalloc holds %zu "
+                    "(2 nrhs * 12 * Vt complex128)", nrhs, 2 * nb, kNoAllocScratchBytes);
+    // the stencil choice already tuned for this nrhs (by ovl_apply_hw), else
+    // variant 0; never the tuner, which allocates
+    int code = kStencilVariants * (ctx->links12 ? 1 : 0);
+    auto it = ctx->stencil_variant.find(std::make_pair((int)nrhs, 0));
+    if (it != ctx->stencil_variant.end()) code = it->second;
+    const int var = code % kStencilVariants, lnk = code / kStencilVariants;
+    double2* sin = static_cast<double2*>(ctx->scratch);
+    double2* sout = reinterpret_cast<double2*>(static_cast<char*>(ctx->scratch) + nb);
+    launch_pack_spinor64(static_cast<const double2*>(in), sin, ctx->g.V, ctx->g.Vt, nrhs, ctx->stream);
+    launch_wilson<double>(0, sin, sout, stencil_links<double>(ctx, lnk), ctx->g, kappa_of(ctx->m0),
+                          make_double2(0, 0), nullptr, nullptr, nullptr, nullptr, 0, nrhs,
+                          ctx->stream, var, lnk);
+    launch_unpack_spinor64(sout, static_cast<double2*>(out), ctx->g.V, ctx->g.Vt, nrhs, ctx->stream);
     HIPCHK(ctx, hipGetLastError());
     return OVL_OK;
 }

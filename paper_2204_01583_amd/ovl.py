@@ -29,7 +29,7 @@ EXPORTS = [
     "ovl_create", "ovl_destroy", "ovl_set_stream", "ovl_set_gauge", "ovl_set_masses",
     "ovl_set_contour", "ovl_set_contour_single", "ovl_set_nodes", "ovl_set_solver",
     "ovl_set_residual_check", "ovl_set_check_bound", "ovl_spectral_bounds", "ovl_suggest_contour",
-    "ovl_apply_hw", "ovl_apply_hw_fp32", "ovl_apply_sign",
+    "ovl_apply_hw", "ovl_apply_hw_noalloc", "ovl_apply_hw_fp32", "ovl_apply_sign",
     "ovl_apply_dov", "ovl_force", "ovl_apply_sign_batched", "ovl_get_stats",
     "ovl_bench_kernel", "ovl_set_profiling", "ovl_get_profile", "ovl_status_string",
     "ovl_last_error",
@@ -93,6 +93,7 @@ def load():
         "ovl_suggest_contour": ([D, D, D, P, P, P], I),
         "ovl_apply_hw": ([P, P, P, I], I),
         "ovl_apply_hw_fp32": ([P, P, P, I], I),
+        "ovl_apply_hw_noalloc": ([P, P, P, I], I),
         "ovl_apply_sign": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "ovl_apply_dov": ([P, P, P, I, ctypes.POINTER(Stats)], I),
         "ovl_force": ([P, P, P, I, I, ctypes.POINTER(D), ctypes.POINTER(Stats)], I),
