@@ -4,7 +4,7 @@ Workload (one "step"): D_ov(m_q) applied to 4 complex Gaussian sources on a
 16^4 lattice with a seeded SU(3) field (roughness 0.3, seed 0), m0 = 1.4,
 m_q = 0.1, a circle contour with 128 nodes per contour (256 shifted systems),
 seed shift 1 + 0.05i, shifted residuals to 1e-12 * ||b||, mixed precision
-(FP64, then FP32 vectors once every shifted residual is below 1e-4 ||b||),
+(FP64, then FP32 vectors once every shifted residual is below 1e-3 ||b||),
 stored seed-residual basis form.  The step runs the whole path: layout
 packing, the shifted solver (stencil, reductions, shift scalars, vector
 updates), the quadrature sum and the D_ov assembly.  Inputs are resident in
@@ -29,7 +29,11 @@ NQ = 128
 CIRCLE = (1.3, 1.2999, 1.0)
 M0, MQ = 1.4, 0.1
 TOL = 1e-12
-SWITCH = 1e-4
+# the mixed switch point: the fastest of {1e-2, 1e-3, 1e-4} whose result stays
+# within 1e-10 of the FP64 path with a margin (measured at this workload:
+# 1.5e-10, 8.9e-12 and 1.4e-12 against the FP64 path; 3.8e-11, 1.2e-12 and
+# 4.2e-13 against the oracle on its sampled nodes)
+SWITCH = 1e-3
 
 
 def log(*a):
@@ -389,7 +393,7 @@ def main():
         "config": {
             "workload": "D_ov(m_q) on 4 Gaussian sources, 16^4 SU(3) field (roughness 0.3, seed 0), "
                         "m0=1.4, m_q=0.1, circle contour 2x128 nodes, tol 1e-12, "
-                        "mixed FP64->FP32 (switch 1e-4), stored-basis shifted solver",
+                        f"mixed FP64->FP32 (switch {SWITCH:.0e}), stored-basis shifted solver",
             "lattice": list(DIMS), "sources": NSRC, "shifts": 2 * NQ,
             "iterations": st.iterations, "fp32_iterations": st.fp32_iterations,
         },
