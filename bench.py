@@ -314,7 +314,7 @@ def oracle_sample_accuracy(torch, ovl, Ud, B, pick, s_ref):
     out = {"nodes": [int(i) for i in pick], "source": 0,
            "targets": {"fp64": 1e-11, "mixed": 1e-10}}
     for label, prec, theta in (("fp64", ovl.PREC_FP64, SWITCH), ("mixed", ovl.PREC_MIXED, SWITCH),
-                               ("mixed_switch_1e-03", ovl.PREC_MIXED, 1e-3),
+                               ("mixed_switch_1e-04", ovl.PREC_MIXED, 1e-4),
                                ("mixed_switch_1e-02", ovl.PREC_MIXED, 1e-2)):
         ctx.set_solver(prec, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=theta)
         s, st = ctx.apply_sign(b0)

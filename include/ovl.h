@@ -69,7 +69,8 @@ extern "C" {
 #define OVL_PREC_FP64   0   /* every vector operation in FP64                                */
 #define OVL_PREC_MIXED  1   /* FP64 until the largest shifted residual falls below
                                `switch_res` * ||b||, then FP32 stencil and vectors; the scalar
-                               recurrences, weights and the sum stay FP64                     */
+                               recurrences, weights and the sum stay FP64 (in a batch, each
+                               context switches on its own residuals)                         */
 
 #define OVL_FORM_REFERENCE 0 /* per-shift solutions x_j kept in HBM, s = sum c_j x_j at the end */
 #define OVL_FORM_FUSED     1 /* per-shift directions p_j only; s accumulated in the same sweep  */
@@ -249,8 +250,11 @@ int ovl_force(ovl_ctx* ctx, const void* phi, void* grad, int32_t kind, int32_t s
  * settings of ctxs[0] are used for every context during the call (each
  * context's own settings are restored afterwards).  All contexts must be on
  * one device, 1 <= nctx <= 64.  Each seed-iteration stage is ONE kernel launch
- * over a job table of all contexts; chunks of 16 iterations are captured once
- * as a HIP graph and replayed (OVL_GRAPHS=0 launches eagerly instead).  The
+ * per precision over a job table of all contexts; chunks of 16 iterations are
+ * captured once as a HIP graph and replayed (OVL_GRAPHS=0 launches eagerly
+ * instead).  In MIXED precision every context switches to FP32 on its own
+ * residuals, at a 16-iteration boundary: while some iterate in FP64 and
+ * others in FP32, each stage runs the FP64 and the FP32 launch.  The
  * work follows ctxs[0]'s stream.  st (may be NULL) receives the aggregate:
  * max iterations, summed active shifts, max residual estimate. */
 int ovl_apply_sign_batched(ovl_ctx* const* ctxs, int32_t nctx, const void* const* in,

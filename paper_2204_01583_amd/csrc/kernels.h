@@ -80,6 +80,8 @@ template <typename R>
 void launch_iter_jobs(const JobDesc* jobs, int njobs, const int* kread, int* kwrite,
                       int total_blocks, int variant, int lnk, hipStream_t s,
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// job->phase = phase (0 FP64, 1 FP32) in stream order
+void launch_set_phase(JobDesc* job, int phase, hipStream_t s);
 // state block of every job into its pinned host slot (k / chunk) & 1, with k
 // read from kdev (the iteration counter after a chunk)
 void launch_export_state(const JobDesc* jobs, int njobs, const int* kdev, int chunk,

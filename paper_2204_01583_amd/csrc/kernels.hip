@@ -222,6 +222,15 @@ void launch_export_state(const JobDesc* jobs, int njobs, const int* kdev, int ch
     hipLaunchKernelGGL(k_export_state, dim3(njobs), dim3(kBlock), 0, s, jobs, kdev, chunk);
 }
 
+// One job's iteration precision, written in stream order (the job kernels
+// queued after it read the new value).
+__global__ void k_set_phase(JobDesc* __restrict__ job, int phase) {
+    if (threadIdx.x == 0) job->phase = phase;
+}
+void launch_set_phase(JobDesc* job, int phase, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(64), 0, s, job, phase);
+}
+
 void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, a, b, n);
@@ -483,8 +492,11 @@ __global__ __launch_bounds__(kBlock) void k_update_jobs(const JobDesc* __restric
                                                         const int* __restrict__ kread,
                                                         int* __restrict__ kwrite) {
     const int k = (int)uniform((uint32_t)*kread);
+    // (when both precisions run in one iteration, both launches write the
+    // same k + 1: the counter stays consistent)
     if (blockIdx.x == 0 && threadIdx.x == 0) *kwrite = k + 1;
     const VecBlock v = vec_block(jobs, njobs);
+    if (jobs[v.j].phase != (sizeof(R) == 4 ? 1 : 0)) return;  // the other precision's job
     update_block<R, KIND>(jobs[v.j], v.n, v.bx, k);
 }
 

@@ -140,7 +140,8 @@ struct ovl_ctx {
     hipStream_t ws = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     DBuf jobs_dev;                         // batch lead: JobDesc table + iteration counter
-    struct GraphCache { std::string key; hipGraphExec_t exec = nullptr; } graphs[2];
+    // chunk graphs by precision mode (1 FP64 jobs only, 2 FP32 only, 3 both)
+    struct GraphCache { std::string key; hipGraphExec_t exec = nullptr; } graphs[3];
     // per-kernel-class event timing (ovl_set_profiling)
     static constexpr int kClasses = 10;
     bool prof_on = false;
@@ -1040,6 +1041,7 @@ struct Work {
     bool fused;            // one-kernel iteration (basis forms): q and the partials double-buffered
     size_t qpp;            // fused: elements between q[0] and q[1]
     int k_switch;          // first basis slot (or iteration) held in FP32 (mixed), or -1
+    int k_conv;            // iteration before which the job was converted to FP32, or -1
     int K;                 // seed iterations of the last solve (max over sources)
     size_t rpp;            // two-pass: elements between the two r buffers
     char** slot_tab;       // basis: device table of slot-chunk bases
@@ -1314,76 +1316,98 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], const i
     d.h = nullptr;
     d.ksw = 1 << 30;
     d.form = c->form;
+    d.phase = 0;
 }
 
-// Enqueue `count` seed iterations of every job in precision R.
-template <typename R>
-void enqueue_chunk(const Batch& B, int count, hipStream_t s, bool prof,
+// Precision mode of a chunk: bit f set when some job iterates in precision f
+// (0 FP64, 1 FP32).  Each job runs in its own phase; the kernels of one
+// precision skip the blocks of jobs in the other.
+int chunk_mode(const Batch& B) {
+    int m = 0;
+    for (const JobDesc& d : B.desc) m |= 1 << d.phase;
+    return m;
+}
+
+// Enqueue `count` seed iterations of every job, each in its own precision:
+// per iteration the stencils of the precisions in `mode`, then their updates
+// (both updates of an iteration write the same next counter).
+void enqueue_chunk(const Batch& B, int mode, int count, hipStream_t s, bool prof,
                    int nact_total) {
     ovl_ctx* lead = B.ctx[0];
-    const int c32 = sizeof(R) == 4 ? 1 : 0;
-    const double es = sizeof(C2<R>);
-    double vec_b = 0, sweep_b = 0;
+    const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
+    double vec_b[2] = {0, 0}, sweep_b[2] = {0, 0};
     if (prof) {
         for (size_t i = 0; i < B.w.size(); ++i) {
+            const int f = B.desc[i].phase;
+            const double es = f ? sizeof(float2) : sizeof(double2);
             const double V = (double)B.ctx[i]->g.V, n = B.w[i]->nsrc, N = 12 * V;
-            vec_b += 3.0 * es * N * n;  // r and q read, r written
+            vec_b[f] += 3.0 * es * N * n;  // r and q read, r written
             const bool ref = B.form == OVL_FORM_REFERENCE;
-            sweep_b += N * n * (ref ? 0.0 : 32.0);  // s read and written (fused sweep)
+            sweep_b[f] += N * n * (ref ? 0.0 : 32.0);  // s read and written (fused sweep)
         }
+        const int f0 = B.desc[0].phase;
+        const double es0 = f0 ? sizeof(float2) : sizeof(double2);
         const double N0 = 12.0 * B.ctx[0]->g.V;
-        sweep_b += N0 * nact_total * (2.0 * es + (B.form == OVL_FORM_REFERENCE ? 32.0 : 0.0));
+        sweep_b[f0] += N0 * nact_total * (2.0 * es0 + (B.form == OVL_FORM_REFERENCE ? 32.0 : 0.0));
     }
-    const int var = c32 ? B.variant32 : B.variant64;
-    const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
-    if (B.fused) {
-        for (int i = 0; i < count; ++i) {
-            // bytes credited after the solve from the sources' live iterations
-            ProfScope ps(lead, s, prof ? 8 + c32 : -1, 0.0, true);
-            launch_iter_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
-                                B.kdev + ((i + 1) & 1), B.sten_total[c32], var, B.lnk[c32], s,
-                                ps.start(), ps.stop());
-        }
-        launch_export_state(B.desc_dev, (int)B.desc.size(), B.kdev + (count & 1), kChunk, s);
-        return;
-    }
+    const int vars[2] = {B.variant64, B.variant32};
+    const int nj = (int)B.desc.size();
     for (int i = 0; i < count; ++i) {
-        {
-            // bytes credited after the solve from the sources' live iterations
-            ProfScope ps(lead, s, prof ? 0 + c32 : -1, 0.0, true);
-            launch_wilson_jobs<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
-                                  B.sten_total[c32], var, B.lnk[c32], s, ps.start(), ps.stop());
+        int* kr = B.kdev + (i & 1);
+        int* kw = B.kdev + ((i + 1) & 1);
+        if (B.fused) {
+            for (int f = 0; f < 2; ++f) {
+                if (!(mode & (1 << f))) continue;
+                // bytes credited after the solve from the sources' live iterations
+                ProfScope ps(lead, s, prof ? 8 + f : -1, 0.0, true);
+                if (f) launch_iter_jobs<float>(B.desc_dev, nj, kr, kw, B.sten_total[1], vars[1],
+                                               B.lnk[1], s, ps.start(), ps.stop());
+                else launch_iter_jobs<double>(B.desc_dev, nj, kr, kw, B.sten_total[0], vars[0],
+                                              B.lnk[0], s, ps.start(), ps.stop());
+            }
+            continue;
         }
-        {
+        for (int f = 0; f < 2; ++f) {
+            if (!(mode & (1 << f))) continue;
+            // bytes credited after the solve from the sources' live iterations
+            ProfScope ps(lead, s, prof ? 0 + f : -1, 0.0, true);
+            if (f) launch_wilson_jobs<float>(B.desc_dev, nj, kr, B.sten_total[1], vars[1], B.lnk[1],
+                                             s, ps.start(), ps.stop());
+            else launch_wilson_jobs<double>(B.desc_dev, nj, kr, B.sten_total[0], vars[0], B.lnk[0],
+                                            s, ps.start(), ps.stop());
+        }
+        for (int f = 0; f < 2; ++f) {
+            if (!(mode & (1 << f))) continue;
             // K2: r update (r, q read, r written), with the sweep in the sweep forms
-            ProfScope ps(lead, s, prof ? (sweep ? 4 + c32 : 2 + c32) : -1,
-                         sweep ? vec_b + sweep_b : 0.0, true);
-            launch_iteration_update<R>(B.desc_dev, (int)B.desc.size(), B.kdev + (i & 1),
-                                       B.kdev + ((i + 1) & 1), B.vec_total, B.form, B.maxJ, s,
-                                       ps.start(), ps.stop());
+            ProfScope ps(lead, s, prof ? (sweep ? 4 + f : 2 + f) : -1,
+                         sweep ? vec_b[f] + sweep_b[f] : 0.0, true);
+            if (f) launch_iteration_update<float>(B.desc_dev, nj, kr, kw, B.vec_total, B.form,
+                                                  B.maxJ, s, ps.start(), ps.stop());
+            else launch_iteration_update<double>(B.desc_dev, nj, kr, kw, B.vec_total, B.form,
+                                                 B.maxJ, s, ps.start(), ps.stop());
         }
     }
     // the chunk's final state to the pinned host slots (the counter after an
     // even number of iterations is in slot 0)
-    launch_export_state(B.desc_dev, (int)B.desc.size(), B.kdev + (count & 1), kChunk, s);
+    launch_export_state(B.desc_dev, nj, B.kdev + (count & 1), kChunk, s);
 }
 
-// Capture (once per key) and replay a graph of kChunk iterations in precision R.
-template <typename R>
-int replay_chunk(Batch& B, hipStream_t s) {
+// Capture (once per key) and replay a graph of kChunk iterations in precision
+// mode `mode`.  The graph reads the job table from device memory at every
+// replay, so the jobs' phases may change between replays.
+int replay_chunk(Batch& B, int mode, hipStream_t s) {
     ovl_ctx* lead = B.ctx[0];
-    const int ph = sizeof(R) == 4 ? 1 : 0;
     char kb[256];
-    snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d|%d|%d", (void*)B.desc_dev, (void*)B.kdev,
-             B.desc.size(), B.sten_total[ph], B.vec_total, ph ? B.variant32 : B.variant64, B.form,
-             B.maxJ, B.lnk[ph], (int)B.fused);
-    auto& gc = lead->graphs[ph];
+    snprintf(kb, sizeof(kb), "%p|%p|%zu|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", (void*)B.desc_dev,
+             (void*)B.kdev, B.desc.size(), B.sten_total[0], B.sten_total[1], B.vec_total,
+             B.variant64, B.variant32, B.form, B.maxJ, B.lnk[0], B.lnk[1], (int)B.fused);
+    auto& gc = lead->graphs[mode - 1];
     if (!gc.exec || gc.key != kb) {
         if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
         gc.exec = nullptr;
         hipGraph_t graph;
         HIPCHK(lead, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        enqueue_chunk<R>(B, kChunk, s, false, 0);
+        enqueue_chunk(B, mode, kChunk, s, false, 0);
         HIPCHK(lead, hipStreamEndCapture(s, &graph));
         const hipError_t e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -1394,11 +1418,10 @@ int replay_chunk(Batch& B, hipStream_t s) {
     return OVL_OK;
 }
 
-int run_chunk(Batch& B, bool low, bool graphs, hipStream_t s, int nact_total) {
-    if (graphs) return low ? replay_chunk<float>(B, s) : replay_chunk<double>(B, s);
-    const bool prof = B.ctx[0]->prof_on;
-    if (low) enqueue_chunk<float>(B, kChunk, s, prof, nact_total);
-    else enqueue_chunk<double>(B, kChunk, s, prof, nact_total);
+int run_chunk(Batch& B, bool graphs, hipStream_t s, int nact_total) {
+    const int mode = chunk_mode(B);
+    if (graphs) return replay_chunk(B, mode, s);
+    enqueue_chunk(B, mode, kChunk, s, B.ctx[0]->prof_on, nact_total);
     HIPCHK(B.ctx[0], hipGetLastError());
     return OVL_OK;
 }
@@ -1454,6 +1477,14 @@ void convert_job(ovl_ctx* c, Work& w, int k, hipStream_t s) {
     }
 }
 
+// Job i of the batch iterates in FP32 from iteration k on (its vectors
+// converted after the work already queued).
+void switch_job(Batch& B, size_t i, int k, hipStream_t s) {
+    convert_job(B.ctx[i], *B.w[i], k, s);
+    B.desc[i].phase = 1;
+    launch_set_phase(B.desc_dev + i, 1, s);
+}
+
 // Parity of the newest active counts after `done` launches of the iteration:
 // the two-kernel iteration k writes counts [(k+1)&1], the fused kernel k
 // writes [k&1]; at the iteration limit the counts of the last live launch stay.
@@ -1466,6 +1497,8 @@ struct PollResult {
     bool all_done = true;
     double maxres = 0.0;
     int iters = 0, nact = 0;
+    std::vector<double> job_res;  // per job: largest shifted residual estimate
+    std::vector<char> job_done;   // per job: no live source
 };
 
 // Records ev after a chunk, whose last kernel has exported every job's state
@@ -1482,6 +1515,8 @@ PollResult read_state(Batch& B, int slot, int k_host, hipEvent_t ev, int* rc_out
     *rc_out = OVL_OK;
     if (hipEventSynchronize(ev) != hipSuccess) *rc_out = fail(B.ctx[0], OVL_E_HIP, "state wait failed");
     prof_collect(B.ctx[0]);
+    P.job_res.assign(B.w.size(), 0.0);
+    P.job_done.assign(B.w.size(), 1);
     for (size_t i = 0; i < B.w.size(); ++i) {
         ovl_ctx* c = B.ctx[i];
         Work& w = *B.w[i];
@@ -1496,12 +1531,15 @@ PollResult read_state(Batch& B, int slot, int k_host, hipEvent_t ev, int* rc_out
             int na = 0;
             for (int q = 0; q < w.sh.nslices; ++q) {
                 na += hcnt[n * kMaxSlices + q];
-                P.maxres = std::max(P.maxres, hmres[n * kMaxSlices + q]);
+                P.job_res[i] = std::max(P.job_res[i], hmres[n * kMaxSlices + q]);
             }
-            P.all_done = P.all_done && (na == 0 || S.status != OVL_OK);
+            const bool done = na == 0 || S.status != OVL_OK;
+            P.job_done[i] = P.job_done[i] && done;
+            P.all_done = P.all_done && done;
             P.iters = std::max(P.iters, S.iter);
             P.nact += na;
         }
+        P.maxres = std::max(P.maxres, P.job_res[i]);
     }
     return P;
 }
@@ -1512,9 +1550,10 @@ PollResult read_state(Batch& B, int slot, int k_host, hipEvent_t ev, int* rc_out
 // of the basis and two-pass forms, from the sources' live iterations (the
 // per-launch records cannot know them: a launch in which every source has
 // finished returns at once and moves nothing).  A source live for iterations
-// 0 .. iter-1 ran min(iter, k_switch) of them in FP64 and the rest in FP32;
+// 0 .. iter-1 ran min(iter, k_switch) of them in FP64 and the rest in FP32,
+// k_switch the iteration at which its job was converted (w.k_conv);
 // a job's links are read once per launch in which any of its sources is live.
-void credit_live_bytes(const Batch& B, int k_switch) {
+void credit_live_bytes(const Batch& B) {
     ovl_ctx* lead = B.ctx[0];
     if (!lead->prof_on) return;
     const bool sweep = B.form == OVL_FORM_FUSED || B.form == OVL_FORM_REFERENCE;
@@ -1523,6 +1562,7 @@ void credit_live_bytes(const Batch& B, int k_switch) {
         const Work& w = *B.w[i];
         const double V = (double)c->g.V;
         const SrcState* hs = reinterpret_cast<const SrcState*>(c->host_state);
+        const int k_switch = w.k_conv;
         if (B.fused) {
             // kernel k is live for a source through k = iter (its last live
             // kernel records iter = k); FP64 below the first FP32 kernel
@@ -1562,8 +1602,9 @@ void credit_live_bytes(const Batch& B, int k_switch) {
 }
 
 // Builds the job table of a batch for its current variants and link formats
-// (grid offsets per job and precision, state export slots) and uploads it.
-static int build_desc(Batch& B, hipStream_t s) {
+// (grid offsets per job and precision, state export slots), every job in
+// precision phase `phase`, and uploads it.
+static int build_desc(Batch& B, hipStream_t s, int phase = 0) {
     ovl_ctx* lead = B.ctx[0];
     B.maxJ = 0;
     B.desc.resize(B.w.size());
@@ -1580,6 +1621,7 @@ static int build_desc(Batch& B, hipStream_t s) {
         d.state_host = static_cast<char*>(hdev);
         d.state_bytes = (int)B.w[i]->state_bytes;
         d.state_stride = (int)state_slot_bytes(*B.w[i]);
+        d.phase = phase;
     }
     B.sten_total[0] = sb[0];
     B.sten_total[1] = sb[1];
@@ -1622,7 +1664,7 @@ static int tune_solver_stencil(Batch& B, hipStream_t s, int prec, bool all12, in
     for (int c = 0; c < kStencilVariants * nfmt; ++c) {
         const int v = c % kStencilVariants, lnk = c / kStencilVariants;
         if (prec) { B.variant32 = v; B.lnk[1] = lnk; } else { B.variant64 = v; B.lnk[0] = lnk; }
-        int rc = build_desc(B, s);
+        int rc = build_desc(B, s, prec);
         if (rc) return rc;
         for (size_t i = 0; i < B.w.size(); ++i) {
             rc = init_job(B.ctx[i], *B.w[i], s);
@@ -1640,11 +1682,9 @@ static int tune_solver_stencil(Batch& B, hipStream_t s, int prec, bool all12, in
         }
         HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));
         // one untimed chunk, then the timed one continues the same solve
-        if (prec) enqueue_chunk<float>(B, kChunk, s, false, 0);
-        else enqueue_chunk<double>(B, kChunk, s, false, 0);
+        enqueue_chunk(B, 1 << prec, kChunk, s, false, 0);
         HIPCHK(lead, hipEventRecord(e0, s));
-        if (prec) enqueue_chunk<float>(B, kChunk, s, false, 0);
-        else enqueue_chunk<double>(B, kChunk, s, false, 0);
+        enqueue_chunk(B, 1 << prec, kChunk, s, false, 0);
         HIPCHK(lead, hipEventRecord(e1, s));
         HIPCHK(lead, hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1750,8 +1790,8 @@ static int solve_batch_once(Batch& B) {
     }
     HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));  // outside any captured graph
 
-    bool low = false;
-    int k_switch = -1, status = OVL_OK;
+    int status = OVL_OK;
+    for (Work* w : B.w) w->k_conv = -1;
     int k_host = 0;  // iterations whose state the host has read
     int k_enq = 0;   // iterations queued
     PollResult P;
@@ -1776,21 +1816,30 @@ static int solve_batch_once(Batch& B) {
                     return fail(lead, OVL_E_STATE, "basis slots for iterations up to %d missing",
                                 k_enq + kChunk);
             }
-        int r = run_chunk(B, low, graphs, s, nact_known);
+        int r = run_chunk(B, graphs, s, nact_known);
         if (r) return r;
         k_enq += kChunk;
         const int slot = (k_enq / kChunk) & 1;
         return post_state(B, s, pev[slot]);
     };
-    // Look-ahead: while the largest shifted residual is far above the next
-    // decision point (the precision switch, then the tolerance), the chunk
-    // after the polled one is queued before the host waits, so the device
-    // does not idle through the poll.  Within a factor 10 of that point the
-    // loop polls each chunk before queueing the next, so the switch and the
-    // stop fall on the same iteration as with one chunk in flight.  A chunk
-    // queued past convergence finds no live source and returns at once.
-    // Profiling keeps one chunk in flight (its events are read at each poll).
+    // Look-ahead: while every job is far from its next decision point (its
+    // own precision switch, then the tolerance), the chunk after the polled
+    // one is queued before the host waits, so the device does not idle
+    // through the poll.  Within a factor 10 of such a point the loop polls
+    // each chunk before queueing the next, so every switch and the stop fall
+    // on the same iteration as with one chunk in flight.  A chunk queued past
+    // convergence finds no live source and returns at once.  Profiling keeps
+    // one chunk in flight (its events are read at each poll).
     const bool may_look_ahead = !lead->prof_on;
+    auto far_from_decisions = [&]() {
+        if (!(P.maxres > 10.0 * lead->tol)) return false;
+        if (!mixed) return true;
+        if (P.job_res.empty()) return P.maxres > 10.0 * lead->switch_res;  // no poll yet
+        for (size_t i = 0; i < B.w.size(); ++i)
+            if (B.desc[i].phase == 0 && !P.job_done[i] && !(P.job_res[i] > 10.0 * lead->switch_res))
+                return false;
+        return true;
+    };
     // launches the iteration may take: the two-kernel iteration k < maxk; the
     // fused kernel k <= maxk (kernel k advances the shifts by iteration k-1)
     const int klim = B.fused ? maxk + 1 : maxk;
@@ -1799,9 +1848,7 @@ static int solve_batch_once(Batch& B) {
             rc = queue_chunk();
             if (rc) return rc;
         }
-        const double next_point = (mixed && !low) ? lead->switch_res : lead->tol;
-        if (may_look_ahead && k_enq == k_host + kChunk && k_enq < klim &&
-            P.maxres > 10.0 * next_point) {
+        if (may_look_ahead && k_enq == k_host + kChunk && k_enq < klim && far_from_decisions()) {
             rc = queue_chunk();
             if (rc) return rc;
         }
@@ -1813,13 +1860,17 @@ static int solve_batch_once(Batch& B) {
         nact_known = P.nact;
         if (P.status != OVL_OK) { status = P.status; break; }
         if (P.all_done) break;
-        if (mixed && !low && P.maxres < lead->switch_res && k_host < klim) {
-            // relaxed precision: from here the remaining corrections are small
-            // enough that FP32 vectors perturb the result by ~eps32 * switch_res.
-            // The conversion follows any chunk still queued.
-            low = true;
-            k_switch = k_enq;
-            for (size_t i = 0; i < B.w.size(); ++i) convert_job(B.ctx[i], *B.w[i], k_enq, s);
+        if (mixed && k_host < klim) {
+            // relaxed precision, job by job: once a job's largest shifted
+            // residual is below switch_res the remaining corrections are small
+            // enough that FP32 vectors perturb its result by ~eps32 * switch_res.
+            // The conversion follows any chunk still queued; the other jobs
+            // go on in their own precision.
+            for (size_t i = 0; i < B.w.size(); ++i)
+                if (B.desc[i].phase == 0 && !P.job_done[i] && P.job_res[i] < lead->switch_res) {
+                    B.w[i]->k_conv = k_enq;
+                    switch_job(B, i, k_enq, s);
+                }
             HIPCHK(lead, hipGetLastError());
         }
     }
@@ -1837,13 +1888,14 @@ static int solve_batch_once(Batch& B) {
     if (((k_host / kChunk) & 1) != 0)
         for (size_t i = 0; i < B.w.size(); ++i)
             memcpy(B.ctx[i]->host_state, host_slot(B.ctx[i], *B.w[i], 1), B.w[i]->state_bytes);
-    credit_live_bytes(B, k_switch);
+    credit_live_bytes(B);
     const int k_run = k_host;
     if (status == OVL_OK && !P.all_done) status = OVL_NOT_CONVERGED;
     for (size_t i = 0; i < B.w.size(); ++i) {
         // first slot holding FP32 (the fused kernel k reads slot k-1, which the
         // switch to FP32 before kernel k converted)
-        B.w[i]->k_switch = k_switch < 0 ? -1 : (B.fused ? k_switch - 1 : k_switch);
+        const int kc = B.w[i]->k_conv;
+        B.w[i]->k_switch = kc < 0 ? -1 : (B.fused ? kc - 1 : kc);
         B.w[i]->K = 0;
         for (int n = 0; n < B.w[i]->nsrc; ++n) B.w[i]->K = std::max(B.w[i]->K, B.ctx[i]->host_state[n].iter);
     }
@@ -1915,20 +1967,19 @@ static int solve_batch_once(Batch& B) {
                 launch_s_init(w.b64, w.h, w.maxk, w.s64, w.N, w.nsrc, s);
                 B.desc[i].h = w.h;
                 B.desc[i].state_host = nullptr;  // the host keeps the first pass's final state
+                B.desc[i].phase = 0;
             }
             HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(), B.desc.size() * sizeof(JobDesc),
                                         hipMemcpyHostToDevice, s));
             HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));
-            bool low2 = false;
             for (int k2 = 0; k2 < k_run; k2 += kChunk) {
-                if (mixed && !low2 && k2 == k_switch) {
-                    low2 = true;
-                    for (size_t i = 0; i < B.w.size(); ++i) convert_job(B.ctx[i], *B.w[i], k2, s);
-                }
-                rc = run_chunk(B, low2, graphs, s, nact_known);
+                // every job switches at the iteration of its first pass
+                for (size_t i = 0; i < B.w.size(); ++i)
+                    if (mixed && B.w[i]->k_conv == k2) switch_job(B, i, k2, s);
+                rc = run_chunk(B, graphs, s, nact_known);
                 if (rc) return rc;
             }
-            credit_live_bytes(B, k_switch);  // the second pass repeats the same iterations
+            credit_live_bytes(B);  // the second pass repeats the same iterations
             HIPCHK(lead, hipGetLastError());
         }
     }
@@ -2003,10 +2054,10 @@ static int solve_batch_once(Batch& B) {
 }
 
 // The bound on the in-band true residual of a mixed-precision apply.  The
-// FP32 phase starts when every shifted residual is below switch_res; from
-// there on FP32 matvecs and vectors add to the true residual a drift of
-// about eps32 * switch_res (measured: 3.7e-10 at switch 1e-2), which the
-// recurrence's estimates do not see.  Default: max(10 tol, 10 eps32
+// FP32 phase of a job starts when its every shifted residual is below
+// switch_res; from there on FP32 matvecs and vectors add to the true
+// residual a drift of about eps32 * switch_res (measured: 3.7e-10 at switch
+// 1e-2), which the recurrence's estimates do not see.  Default: max(10 tol, 10 eps32
 // switch_res), so a repeat means more drift than that mechanism gives.
 static double mixed_check_bound(const ovl_ctx* c) {
     if (c->check_bound > 0.0) return c->check_bound;

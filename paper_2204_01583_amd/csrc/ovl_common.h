@@ -163,6 +163,8 @@ struct JobDesc {
     const double2* h;           // two-pass, second pass: h[src][i] weights of r_i
     int ksw;                    // first FP32 iteration (slots from it hold FP32), or large
     int form;                   // OVL_FORM_* of this solve
+    int phase;                  // precision of this job's iterations now: 0 FP64, 1 FP32 (the
+                                // kernels of the other precision skip its blocks)
     // state export at the end of each chunk: the state block (SrcState array,
     // active counts, residual maxima; state_bytes, a multiple of 8) goes to
     // pinned host slot (k / chunk) & 1, state_stride bytes apart; none if

@@ -562,6 +562,7 @@ __global__ __launch_bounds__(kBlock * RB) void k_wilson_jobs_lt(const JobDesc* _
     const int f = sizeof(R) == 4 ? 1 : 0;
     while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
     const JobDesc& J = jobs[j];
+    if (J.phase != f) return;  // this job iterates in the other precision
     wilson_block_lt<R, 1, HPI, RB, LNK>(job_rk<const C2<R>>(J, k, f), static_cast<C2<R>*>(J.q[f]),
                                         static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
                                         J.zs.y, nullptr, J.part_w, J.st, J.sh, k, J.nsb, J.nsrc,
@@ -595,6 +596,7 @@ __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __r
     const int f = sizeof(R) == 4 ? 1 : 0;
     while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
     const JobDesc& J = jobs[j];
+    if (J.phase != f) return;  // this job iterates in the other precision
     wilson_block<R, 1, HPI, RPT, ORD, SPL, TIL, LNK>(job_rk<const C2<R>>(J, k, f),
                                       static_cast<C2<R>*>(J.q[f]),
                                       static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
@@ -804,6 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_jobs(const JobDesc* __restrict_
     int j = 0;
     const int f = sizeof(R) == 4 ? 1 : 0;
     while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
+    if (jobs[j].phase != f) return;  // this job iterates in the other precision
     iter_block<R, HPI, ORD, TIL, LNK>(jobs[j], k, gb - (unsigned)jobs[j].sten_b0[f]);
 }
 
