@@ -103,27 +103,26 @@ def measured_traffic(kclass, variant):
     return rec.get("traffic_bytes_per_launch")
 
 
-def batched_uneven(torch, ovl):
-    """12 seeded fields of sizes 8^4, 12^4 and 16^3x32 (four each, roughness
-    0.2 .. 0.4), 8 Gaussian sources each, 2 x 64 nodes, mixed precision,
-    two-pass basis form, all in one batched solve (one launch per stage over
-    the job table, graph-captured chunks)."""
+def batched_run(torch, ovl, fields, nsrc, workload):
+    """One batched solve over several seeded fields, mixed precision,
+    two-pass basis form, 2 x 64 nodes (one launch per stage and precision
+    over the job table, graph-captured chunks), against the same jobs solved
+    one context at a time and against the batch in FP64.  fields: (dims,
+    roughness, seed) per job."""
     import numpy as np
     import seeded_inputs as si
-    sizes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32)]
     ctxs, ins = [], []
-    for si_, dims in enumerate(sizes):
-        for i in range(4):
-            r = 0.2 + 0.2 * i / 3
-            U = si.gauge_field(dims, r, seed=10 * si_ + i)
-            c = ovl.Context(dims, device=0)
-            c.set_gauge(torch.from_numpy(U).to("cuda:0"))
-            c.set_masses(M0, MQ)
-            c.set_contour(64, *CIRCLE)
-            c.set_solver(ovl.PREC_MIXED, ovl.FORM_TWOPASS, tol=TOL, maxiter=4000, switch_res=SWITCH)
-            ctxs.append(c)
-            ins.append(torch.from_numpy(np.ascontiguousarray(
-                si.gaussian_sources(dims, 8, first_seed=1000))).to("cuda:0"))
+    for dims, r, seed in fields:
+        U = si.gauge_field(dims, r, seed=seed)
+        c = ovl.Context(dims, device=0)
+        c.set_gauge(torch.from_numpy(U).to("cuda:0"))
+        c.set_masses(M0, MQ)
+        c.set_contour(64, *CIRCLE)
+        c.set_solver(ovl.PREC_MIXED, ovl.FORM_TWOPASS, tol=TOL, maxiter=4000, switch_res=SWITCH)
+        ctxs.append(c)
+        ins.append(torch.from_numpy(np.ascontiguousarray(
+            si.gaussian_sources(dims, nsrc, first_seed=1000))).to("cuda:0"))
+
     def timed(fn):
         fn()                                          # warm-up (graphs, tuning, buffers)
         torch.cuda.synchronize()
@@ -137,32 +136,50 @@ def batched_uneven(torch, ovl):
             c.set_solver(prec, ovl.FORM_TWOPASS, tol=TOL, maxiter=4000, switch_res=SWITCH)
 
     dt, (outs, st) = timed(lambda: ovl.apply_sign_batched(ctxs, ins))
-    # the same 12 jobs one context at a time (same settings, same kernels)
+    per_job = [(c.stats().iterations, c.stats().fp32_iterations) for c in ctxs]
+    # the same jobs one context at a time (same settings, same kernels)
     dt_seq, seq = timed(lambda: [c.apply_sign(x)[0] for c, x in zip(ctxs, ins)])
     # the batch in FP64
     set_all(ovl.PREC_FP64)
     dt64, (outs64, st64) = timed(lambda: ovl.apply_sign_batched(ctxs, ins))
     set_all(ovl.PREC_MIXED)
-    # every job's batched result against its own single solve (the same
-    # iterations in one launch per stage) and against the FP64 batch
+    # every job's batched result against its own single solve and against
+    # the FP64 batch
     err_single = max(float((o - r).norm() / r.norm()) for o, r in zip(outs, seq))
-    err_fp64 = {}
-    for i, name in ((0, "8x8x8x8_r0.2"), (4, "12x12x12x12_r0.2"), (11, "16x16x16x32_r0.4")):
-        err_fp64[name] = float((outs[i] - outs64[i]).norm() / outs64[i].norm())
-    err_fp64["max_over_jobs"] = max(float((o - r).norm() / r.norm()) for o, r in zip(outs, outs64))
+    err_fp64 = max(float((o - r).norm() / r.norm()) for o, r in zip(outs, outs64))
     for c in ctxs:
         c.close()
-    nsrc = 8 * len(ctxs)
-    return {"workload": "12 fields (4 x 8^4, 4 x 12^4, 4 x 16^3x32; roughness 0.2-0.4), 8 sources "
-                        "each, 2x64 nodes, mixed, two-pass form, one batched solve",
-            "seconds": round(dt, 4), "applies_per_s": round(nsrc / dt, 3),
-            "iterations": st.iterations, "fp32_iterations": st.fp32_iterations,
+    napp = nsrc * len(ctxs)
+    return {"workload": workload,
+            "seconds": round(dt, 4), "applies_per_s": round(napp / dt, 3),
+            "iterations": st.iterations,
+            "per_job_iterations_fp32": per_job,
             "sequential_seconds": round(dt_seq, 4),
             "speedup_vs_sequential": round(dt_seq / dt, 3),
             "fp64_seconds": round(dt64, 4), "fp64_iterations": st64.iterations,
             "speedup_vs_fp64_batch": round(dt64 / dt, 3),
             "max_err_vs_single_solves": err_single,
-            "err_vs_fp64_batch": err_fp64}
+            "max_err_vs_fp64_batch": err_fp64}
+
+
+def batched_uneven(torch, ovl):
+    """12 seeded fields of sizes 8^4, 12^4 and 16^3x32 (four each, roughness
+    0.2 .. 0.4), 8 Gaussian sources each."""
+    sizes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32)]
+    fields = [(dims, 0.2 + 0.2 * i / 3, 10 * k + i) for k, dims in enumerate(sizes)
+              for i in range(4)]
+    return batched_run(torch, ovl, fields, 8,
+                       "12 fields (4 x 8^4, 4 x 12^4, 4 x 16^3x32; roughness 0.2-0.4), 8 sources "
+                       "each, 2x64 nodes, mixed, two-pass form, one batched solve")
+
+
+def batched_small(torch, ovl):
+    """16 seeded 8^4 fields (the paper's lattice size; roughness 0.2 .. 0.4),
+    4 Gaussian sources each: jobs too small to fill the GPU one at a time."""
+    fields = [((8, 8, 8, 8), 0.2 + 0.2 * (i % 4) / 3, 100 + i) for i in range(16)]
+    return batched_run(torch, ovl, fields, 4,
+                       "16 fields 8^4 (roughness 0.2-0.4), 4 sources each, 2x64 nodes, mixed, "
+                       "two-pass form, one batched solve")
 
 
 def force_workload(torch, ovl):
@@ -505,7 +522,12 @@ def main():
     if not args.no_batch:
         log("batched uneven lattices")
         rec["batched"] = batched_uneven(torch, ovl)
-        log(f"batched: {rec['batched']['seconds']}s, {rec['batched']['applies_per_s']} applies/s")
+        log(f"batched: {rec['batched']['seconds']}s, {rec['batched']['applies_per_s']} applies/s, "
+            f"x{rec['batched']['speedup_vs_sequential']} vs one at a time")
+        log("batched 8^4 lattices")
+        rec["batched_small"] = batched_small(torch, ovl)
+        log(f"batched 8^4: {rec['batched_small']['seconds']}s, "
+            f"x{rec['batched_small']['speedup_vs_sequential']} vs one at a time")
     if not args.no_force:
         log("force")
         try:

@@ -883,13 +883,16 @@ static int iter_variant(ovl_ctx* ctx, int nrhs, int prec) {
         d.slot_bytes = vec;
         d.ksw = 1 << 30;
         d.form = OVL_FORM_BASIS;
+        d.phase = prec;
         if (hipMemcpyAsync(jd, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream) != hipSuccess) break;
         auto run = [&]() {
             // kread = kwrite: every timed launch is kernel 1
             if (prec)
-                launch_iter_jobs<float>(jd, 1, kdev, kdev + 1, d.sten_nb[1], v, lnk, ctx->stream);
+                launch_iter_jobs<float>(jd, 1, kdev, kdev + 1, job_grid_blocks(d.sten_nb[1]), v,
+                                        lnk, ctx->stream);
             else
-                launch_iter_jobs<double>(jd, 1, kdev, kdev + 1, d.sten_nb[0], v, lnk, ctx->stream);
+                launch_iter_jobs<double>(jd, 1, kdev, kdev + 1, job_grid_blocks(d.sten_nb[0]), v,
+                                         lnk, ctx->stream);
         };
         run();
         std::vector<float> t;
@@ -1294,7 +1297,7 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], const i
         d.sten_b0[f] = sten_b0[f];
         d.sten_nb[f] = w.fused ? iter_grid_blocks(c->g, w.nsrc)
                                : wilson_grid_blocks(c->g, w.nsrc, variant[f]);
-        sten_b0[f] += d.sten_nb[f];
+        sten_b0[f] += job_grid_blocks(d.sten_nb[f]);
     }
     d.vec_b0 = vec_b0;
     d.nbe = w.nbe;

@@ -135,6 +135,10 @@ struct ShiftDev {
 // one launch advances every job of a batch by one stage.
 constexpr int kMaxJobs = 64;
 constexpr int kSlotChunk = 32;  // basis form: residual slots per allocation
+// Grid blocks a job owns in a job-table stencil launch: its block count
+// padded to a multiple of 8 (one per XCD), so every job starts on XCD 0.
+inline __host__ __device__ int job_grid_blocks(int nb) { return (nb + 7) & ~7; }
+
 struct JobDesc {
     Geom g;
     double kappa;
@@ -142,7 +146,9 @@ struct JobDesc {
     const void* U[2];           // links, [0] FP64 [1] FP32 (internal layout)
     int nsrc;
     int nsb;                    // site blocks of the stencil
-    int sten_b0[2], sten_nb[2]; // this job's blocks in the FP64 / FP32 stencil grid
+    int sten_b0[2], sten_nb[2]; // this job's blocks in the FP64 / FP32 stencil grid: it owns
+                                // [sten_b0, sten_b0 + job_grid_blocks(sten_nb)), sten_b0 a
+                                // multiple of 8
     int vec_b0, nbe;            // this job's first block in the vector grid; blocks per source
     SrcState* st;
     ShiftDev sh;

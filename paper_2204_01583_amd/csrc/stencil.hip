@@ -552,21 +552,40 @@ __global__ __launch_bounds__(kBlock * RB) void k_wilson_lt(const C2<R>* __restri
                                            k, nsb, nrhs, tile);
 }
 
+// Block -> (job, tile) of a job-table stencil launch.  Job j owns blocks
+// [sten_b0, sten_b0 + pad8(sten_nb)) of the grid, sten_b0 a multiple of 8,
+// so its blocks go round-robin over all eight XCDs like those of a launch of
+// its own (dispatch assigns block b to XCD b mod 8), and within the job the
+// XCD-aware remap groups neighbouring tiles on one XCD.  A job that has
+// finished, or iterates in the other precision, thus leaves every XCD, not
+// a contiguous few, to the jobs still running.  Returns false for the
+// job's padding blocks and for jobs in the other precision phase.
+__device__ __forceinline__ bool job_tile(const JobDesc* __restrict__ jobs, int njobs, int f,
+                                         int& j, unsigned& tile) {
+    const unsigned b = blockIdx.x;
+    j = 0;
+    while (j + 1 < njobs && b >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
+    const JobDesc& J = jobs[j];
+    if (J.phase != f) return false;  // this job iterates in the other precision
+    const unsigned nb = (unsigned)J.sten_nb[f];
+    tile = uniform(xcd_remap(b - (unsigned)J.sten_b0[f], (nb + 7u) & ~7u));
+    return tile < nb;
+}
+
 template <typename R, int HPI, int RB, int LNK>
 __global__ __launch_bounds__(kBlock * RB) void k_wilson_jobs_lt(const JobDesc* __restrict__ jobs,
                                                                 int njobs,
                                                                 const int* __restrict__ kdev) {
     const int k = (int)uniform((uint32_t)*kdev);
-    const unsigned gb = uniform(xcd_remap(blockIdx.x, gridDim.x));
-    int j = 0;
     const int f = sizeof(R) == 4 ? 1 : 0;
-    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
+    int j;
+    unsigned tile;
+    if (!job_tile(jobs, njobs, f, j, tile)) return;
     const JobDesc& J = jobs[j];
-    if (J.phase != f) return;  // this job iterates in the other precision
     wilson_block_lt<R, 1, HPI, RB, LNK>(job_rk<const C2<R>>(J, k, f), static_cast<C2<R>*>(J.q[f]),
                                         static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
                                         J.zs.y, nullptr, J.part_w, J.st, J.sh, k, J.nsb, J.nsrc,
-                                        gb - (unsigned)J.sten_b0[f]);
+                                        tile);
 }
 
 template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
@@ -591,17 +610,16 @@ template <typename R, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
 __global__ __launch_bounds__(kBlock * SPL) void k_wilson_jobs(const JobDesc* __restrict__ jobs, int njobs,
                                                         const int* __restrict__ kdev) {
     const int k = (int)uniform((uint32_t)*kdev);
-    const unsigned gb = uniform(xcd_remap(blockIdx.x, gridDim.x));
-    int j = 0;
     const int f = sizeof(R) == 4 ? 1 : 0;
-    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
+    int j;
+    unsigned tile;
+    if (!job_tile(jobs, njobs, f, j, tile)) return;
     const JobDesc& J = jobs[j];
-    if (J.phase != f) return;  // this job iterates in the other precision
     wilson_block<R, 1, HPI, RPT, ORD, SPL, TIL, LNK>(job_rk<const C2<R>>(J, k, f),
                                       static_cast<C2<R>*>(J.q[f]),
                                       static_cast<const C2<R>*>(J.U[f]), J.g, (R)J.kappa, J.zs.x,
                                       J.zs.y, nullptr, J.part_w, J.st, J.sh, k, J.nsb, J.nsrc,
-                                      gb - (unsigned)J.sten_b0[f]);
+                                      tile);
 }
 
 // ============================================================================
@@ -802,12 +820,11 @@ __global__ __launch_bounds__(kBlock) void k_iter_jobs(const JobDesc* __restrict_
                                                       int* __restrict__ kwrite) {
     const int k = (int)uniform((uint32_t)*kread);
     if (blockIdx.x == 0 && threadIdx.x == 0) *kwrite = k + 1;
-    const unsigned gb = uniform(xcd_remap(blockIdx.x, gridDim.x));
-    int j = 0;
     const int f = sizeof(R) == 4 ? 1 : 0;
-    while (j + 1 < njobs && gb >= (unsigned)jobs[j + 1].sten_b0[f]) ++j;
-    if (jobs[j].phase != f) return;  // this job iterates in the other precision
-    iter_block<R, HPI, ORD, TIL, LNK>(jobs[j], k, gb - (unsigned)jobs[j].sten_b0[f]);
+    int j;
+    unsigned tile;
+    if (!job_tile(jobs, njobs, f, j, tile)) return;
+    iter_block<R, HPI, ORD, TIL, LNK>(jobs[j], k, tile);
 }
 
 int iter_grid_blocks(const Geom& g, int nrhs) { return wilson_blocks(g) * nrhs; }
