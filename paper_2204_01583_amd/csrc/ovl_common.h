@@ -18,26 +18,48 @@ template <typename R> struct cx {
 };
 
 template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+
+// Element accesses to device buffers.  Every vector, link and state buffer
+// the kernels read through ld / stc is global memory, and the accesses go
+// through address-space-1 pointers: the compiler then emits global (not
+// flat) loads and stores, also where the base pointer was read from memory
+// (a job table) and not passed as a kernel argument.  A flat load may be
+// served by LDS, so the compiler can only wait for all of them at once
+// (vmcnt and lgkmcnt both zero); global loads complete in order and are
+// waited for one by one, which keeps a hop's loads in flight together.
+// LDS tiles are read directly, never through these helpers.
+#define OVL_GLOBAL __attribute__((address_space(1)))
+template <typename R> struct nvec;   // native two-element vector, no constructors
+template <> struct nvec<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct nvec<float>  { typedef float  __attribute__((ext_vector_type(2))) type; };
 template <typename R> __device__ __forceinline__ cx<R> ld(const C2<R>* p, int64_t i) {
-    C2<R> v = p[i];
+    typedef const OVL_GLOBAL typename nvec<R>::type G;
+    const typename nvec<R>::type v = ((G*)p)[i];
     return cx<R>{v.x, v.y};
 }
 // 32-bit element index from a wave-uniform base: the byte offset is formed
 // in 32 bits, so the load can use a scalar base plus one VGPR offset.
 template <typename R> __device__ __forceinline__ cx<R> ld(const C2<R>* p, uint32_t i) {
-    const uint32_t off = i * (uint32_t)sizeof(C2<R>);
-    C2<R> v = *reinterpret_cast<const C2<R>*>(reinterpret_cast<const char*>(p) + off);
+    typedef const OVL_GLOBAL typename nvec<R>::type G;
+    const OVL_GLOBAL char* b = (const OVL_GLOBAL char*)p;
+    const typename nvec<R>::type v = *(G*)(b + i * (uint32_t)sizeof(C2<R>));
     return cx<R>{v.x, v.y};
 }
 template <typename R> __device__ __forceinline__ void stc(C2<R>* p, uint32_t i, cx<R> v) {
-    C2<R> w; w.x = v.re; w.y = v.im;
-    const uint32_t off = i * (uint32_t)sizeof(C2<R>);
-    *reinterpret_cast<C2<R>*>(reinterpret_cast<char*>(p) + off) = w;
+    typedef OVL_GLOBAL typename nvec<R>::type G;
+    OVL_GLOBAL char* b = (OVL_GLOBAL char*)p;
+    typename nvec<R>::type w;
+    w.x = v.re;
+    w.y = v.im;
+    *(G*)(b + i * (uint32_t)sizeof(C2<R>)) = w;
 }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 template <typename R> __device__ __forceinline__ void stc(C2<R>* p, int64_t i, cx<R> v) {
-    C2<R> w; w.x = v.re; w.y = v.im;
-    p[i] = w;
+    typedef OVL_GLOBAL typename nvec<R>::type G;
+    typename nvec<R>::type w;
+    w.x = v.re;
+    w.y = v.im;
+    ((G*)p)[i] = w;
 }
 template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }

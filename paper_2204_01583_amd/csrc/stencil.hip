@@ -77,14 +77,23 @@ struct FusedIn {
     cx<R> a[RPT];
 };
 
+// The operands of one hop: the neighbour spinor of every rhs and the stored
+// elements of the link, loaded before any of them is used (hop_load), then
+// consumed by hop_apply.  Keeping the two apart lets a caller issue the
+// loads of two hops before the first hop's projection, which branches on mu
+// (loads placed after such a branch wait for the earlier ones to return).
+template <typename R, int RPT>
+struct HopIn {
+    cx<R> pv[RPT][4][3];
+    cx<R> m[3][3];
+};
+
 template <typename R, int RPT, int TIL, int LNK, int LT = 0, int FU = 0>
-__device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
-                                    const C2<R>* const (&psi)[RPT],
-                                    const C2<R>* __restrict__ Um, uint32_t nb,
-                                    uint32_t lsite, const C2<R>* tile, uint32_t s0, R lsgn,
-                                    const C2<R>* lut = nullptr,
-                                    const FusedIn<R, RPT>* fi = nullptr) {
-    const R sg = fwd ? R(-1) : R(1);
+__device__ __forceinline__ void hop_load(HopIn<R, RPT>& d, const C2<R>* const (&psi)[RPT],
+                                         const C2<R>* __restrict__ Um, uint32_t nb,
+                                         uint32_t lsite, const C2<R>* tile, uint32_t s0,
+                                         const C2<R>* lut = nullptr,
+                                         const FusedIn<R, RPT>* fi = nullptr) {
     constexpr uint32_t NE = LNK ? 6 : 9;  // stored elements per link
     // link element e of this hop's link: from the LDS link tile (LT = 1: the
     // forward links of the block's sites, [NE][256] for this mu) when the
@@ -98,7 +107,6 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
         }
         return ld<R>(Um, tix(e, lsite, NE));
     };
-    cx<R> pv[RPT][4][3];
     const uint32_t lo = nb - s0;
     if (TIL && lo < (uint32_t)kBlock) {
 #pragma unroll
@@ -108,7 +116,7 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const C2<R> v = tile[(uint32_t)((r * 12 + 3 * a + c) * kBlock) + lo];
-                    pv[r][a][c] = mk<R>(v.x, v.y);
+                    d.pv[r][a][c] = mk<R>(v.x, v.y);
                 }
     } else if constexpr (FU == 1) {
 #pragma unroll
@@ -120,8 +128,8 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
                     const uint32_t o = tix((uint32_t)(3 * a + c), nb, 12);
                     const cx<R> rv = ld<R>(psi[r], o), qv = ld<R>(fi->q[r], o);
                     const cx<R> al = fi->a[r];
-                    pv[r][a][c] = mk<R>(rv.re - (al.re * qv.re - al.im * qv.im),
-                                        rv.im - (al.re * qv.im + al.im * qv.re));
+                    d.pv[r][a][c] = mk<R>(rv.re - (al.re * qv.re - al.im * qv.im),
+                                          rv.im - (al.re * qv.im + al.im * qv.re));
                 }
     } else {
 #pragma unroll
@@ -129,53 +137,38 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pv[r][a][c] = ld<R>(psi[r], tix((uint32_t)(3 * a + c), nb, 12));
+                for (int c = 0; c < 3; ++c)
+                    d.pv[r][a][c] = ld<R>(psi[r], tix((uint32_t)(3 * a + c), nb, 12));
     }
+#pragma unroll
+    for (int a = 0; a < (LNK ? 2 : 3); ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) d.m[a][b] = lload((uint32_t)(3 * a + b));
+}
+
+template <typename R, int RPT, int LNK>
+__device__ __forceinline__ void hop_apply(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
+                                          HopIn<R, RPT>& d, R lsgn) {
+    const R sg = fwd ? R(-1) : R(1);
     cx<R> h[RPT][2][3];
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            project<R>(mu, sg, pv[r][0][c], pv[r][1][c], pv[r][2][c], pv[r][3][c], h[r][0][c],
-                       h[r][1][c]);
+            project<R>(mu, sg, d.pv[r][0][c], d.pv[r][1][c], d.pv[r][2][c], d.pv[r][3][c],
+                       h[r][0][c], h[r][1][c]);
+    if constexpr (LNK == 1) {
+        // row 2 = lsgn * conj(row0 x row1)
+        const cx<R> c0 = d.m[0][1] * d.m[1][2] - d.m[0][2] * d.m[1][1];
+        const cx<R> c1 = d.m[0][2] * d.m[1][0] - d.m[0][0] * d.m[1][2];
+        const cx<R> c2 = d.m[0][0] * d.m[1][1] - d.m[0][1] * d.m[1][0];
+        d.m[2][0] = mk<R>(lsgn * c0.re, -lsgn * c0.im);
+        d.m[2][1] = mk<R>(lsgn * c1.re, -lsgn * c1.im);
+        d.m[2][2] = mk<R>(lsgn * c2.re, -lsgn * c2.im);
+    }
     // element (a,b) of the hop matrix: U[a][b] forward, conj(U[b][a]) backward
     const R ci = fwd ? R(1) : R(-1);
     cx<R> u[RPT][2][3];
-    if constexpr (LNK == 1) {
-        cx<R> m[3][3];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) m[a][b] = lload((uint32_t)(3 * a + b));
-        // row 2 = lsgn * conj(row0 x row1)
-        const cx<R> c0 = m[0][1] * m[1][2] - m[0][2] * m[1][1];
-        const cx<R> c1 = m[0][2] * m[1][0] - m[0][0] * m[1][2];
-        const cx<R> c2 = m[0][0] * m[1][1] - m[0][1] * m[1][0];
-        m[2][0] = mk<R>(lsgn * c0.re, -lsgn * c0.im);
-        m[2][1] = mk<R>(lsgn * c1.re, -lsgn * c1.im);
-        m[2][2] = mk<R>(lsgn * c2.re, -lsgn * c2.im);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                u[r][0][a] = mk<R>(0, 0);
-                u[r][1][a] = mk<R>(0, 0);
-            }
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                cx<R> l = fwd ? m[a][b] : m[b][a];
-                l.im *= ci;
-#pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    fma_(u[r][0][a], l, h[r][0][b]);
-                    fma_(u[r][1][a], l, h[r][1][b]);
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) reconstruct<R>(mu, sg, acc[r], u[r]);
-        return;
-    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -185,8 +178,7 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
         }
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const uint32_t e = fwd ? (uint32_t)(3 * a + b) : (uint32_t)(3 * b + a);
-            cx<R> l = lload(e);
+            cx<R> l = fwd ? d.m[a][b] : d.m[b][a];
             l.im *= ci;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -197,6 +189,18 @@ __device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
     }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) reconstruct<R>(mu, sg, acc[r], u[r]);
+}
+
+template <typename R, int RPT, int TIL, int LNK, int LT = 0, int FU = 0>
+__device__ __forceinline__ void hop(int mu, bool fwd, cx<R> (&acc)[RPT][4][3],
+                                    const C2<R>* const (&psi)[RPT],
+                                    const C2<R>* __restrict__ Um, uint32_t nb,
+                                    uint32_t lsite, const C2<R>* tile, uint32_t s0, R lsgn,
+                                    const C2<R>* lut = nullptr,
+                                    const FusedIn<R, RPT>* fi = nullptr) {
+    HopIn<R, RPT> d;
+    hop_load<R, RPT, TIL, LNK, LT, FU>(d, psi, Um, nb, lsite, tile, s0, lut, fi);
+    hop_apply<R, RPT, LNK>(mu, fwd, acc, d, lsgn);
 }
 
 __device__ __forceinline__ uint32_t nbr(const Geom& g, uint32_t s, const int (&coord)[4], int mu,
@@ -244,9 +248,16 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 #pragma unroll 1
             for (int mu = 0; mu < 4; mu += 2) {
                 const uint32_t n0 = nbr(g, s, coord, mu, fwd), n1 = nbr(g, s, coord, mu + 1, fwd);
-                hop<R, RPT, TIL, LNK, LT, FU>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, n0, fwd ? s : n0, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock, fi);
-                hop<R, RPT, TIL, LNK, LT, FU>(mu + 1, fwd, acc, psi, U + (size_t)(mu + 1) * NE * Vt, n1,
-                                 fwd ? s : n1, tile, s0, lsg(mu + 1, fwd), lu + (size_t)(mu + 1) * NE * kBlock, fi);
+                // both hops' loads are issued before either is used
+                HopIn<R, RPT> d0, d1;
+                hop_load<R, RPT, TIL, LNK, LT, FU>(d0, psi, U + (size_t)mu * NE * Vt, n0,
+                                                   fwd ? s : n0, tile, s0,
+                                                   lu + (size_t)(mu) * NE * kBlock, fi);
+                hop_load<R, RPT, TIL, LNK, LT, FU>(d1, psi, U + (size_t)(mu + 1) * NE * Vt, n1,
+                                                   fwd ? s : n1, tile, s0,
+                                                   lu + (size_t)(mu + 1) * NE * kBlock, fi);
+                hop_apply<R, RPT, LNK>(mu, fwd, acc, d0, lsg(mu, fwd));
+                hop_apply<R, RPT, LNK>(mu + 1, fwd, acc, d1, lsg(mu + 1, fwd));
             }
         }
     } else if constexpr (HPI == 1) {
@@ -261,8 +272,14 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
-            hop<R, RPT, TIL, LNK, LT, FU>(mu, true, acc, psi, U + (size_t)mu * NE * Vt, fw, s, tile, s0, lsg(mu, true), lu + (size_t)(mu) * NE * kBlock, fi);
-            hop<R, RPT, TIL, LNK, LT, FU>(mu, false, acc, psi, U + (size_t)mu * NE * Vt, bw, bw, tile, s0, lsg(mu, false), lu + (size_t)(mu) * NE * kBlock, fi);
+            // both hops' loads are issued before either is used
+            HopIn<R, RPT> d0, d1;
+            hop_load<R, RPT, TIL, LNK, LT, FU>(d0, psi, U + (size_t)mu * NE * Vt, fw, s, tile, s0,
+                                               lu + (size_t)(mu) * NE * kBlock, fi);
+            hop_load<R, RPT, TIL, LNK, LT, FU>(d1, psi, U + (size_t)mu * NE * Vt, bw, bw, tile, s0,
+                                               lu + (size_t)(mu) * NE * kBlock, fi);
+            hop_apply<R, RPT, LNK>(mu, true, acc, d0, lsg(mu, true));
+            hop_apply<R, RPT, LNK>(mu, false, acc, d1, lsg(mu, false));
         }
     }
 }
@@ -373,19 +390,34 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
                     bi = (R)b.y;
                 }
             }
+            // every load of the site's own r_k and q_{k-1} is issued before the
+            // first store: o may alias psi as far as the compiler knows, so a
+            // load placed after a store would wait for it
+            cx<R> pv[NA][3], qv[NA][3];
 #pragma unroll
             for (int ai = 0; ai < NA; ++ai) {
                 const int a = SPL == 2 ? 2 * h + ai : ai;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const uint32_t comp = (uint32_t)(3 * a + c);
-                    cx<R> p;
                     if constexpr (TIL == 1) {
                         const C2<R> w = lt[(r * 12 + (int)comp) * kBlock + threadIdx.x];
-                        p = mk<R>(w.x, w.y);
+                        pv[ai][c] = mk<R>(w.x, w.y);
                     } else {
-                        p = ld<R>(psi[r], tix(comp, s, 12));
+                        pv[ai][c] = ld<R>(psi[r], tix(comp, s, 12));
                     }
+                    qv[ai][c] = mk<R>(0, 0);
+                    if constexpr (MODE == 1)
+                        if (k > 0) qv[ai][c] = ld<R>(o, tix(comp, s, 12));
+                }
+            }
+#pragma unroll
+            for (int ai = 0; ai < NA; ++ai) {
+                const int a = SPL == 2 ? 2 * h + ai : ai;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const uint32_t comp = (uint32_t)(3 * a + c);
+                    const cx<R> p = pv[ai][c];
                     // D psi = psi - kappa acc ; H = gamma5 D
                     cx<R> hv = p - kappa * acc[r][ai][c];
                     if (a >= 2) hv = -hv;
@@ -393,14 +425,12 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
                         stc<R>(o, tix(comp, s, 12), hv);
                     } else {
                         // q_k = z_s r_k - H r_k + beta_{k-1} q_{k-1}, in place (this lane
-                        // reads its own q_{k-1} before it writes q_k)
+                        // read its own q_{k-1} above, before any write of q_k)
                         const R zr = (R)zsr, zi = (R)zsi;
                         cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
-                        if (k > 0) {
-                            const cx<R> qo = ld<R>(o, tix(comp, s, 12));
-                            q.re += br * qo.re - bi * qo.im;
-                            q.im += br * qo.im + bi * qo.re;
-                        }
+                        const cx<R> qo = qv[ai][c];
+                        q.re += br * qo.re - bi * qo.im;
+                        q.im += br * qo.im + bi * qo.re;
                         stc<R>(o, tix(comp, s, 12), q);
                         // <r_k, q_k> = sum conj(r) q with r_k = p, accumulated in FP64
                         dre[r] += (double)p.re * (double)q.re + (double)p.im * (double)q.im;
@@ -496,12 +526,24 @@ __device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2
                 bi = (R)b.y;
             }
         }
+        // the site's own r_k and q_{k-1} are loaded before the first store
+        cx<R> pv[4][3], qv[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t comp = (uint32_t)(3 * a + c);
+                pv[a][c] = ld<R>(psi[0], tix(comp, s, 12));
+                qv[a][c] = mk<R>(0, 0);
+                if constexpr (MODE == 1)
+                    if (k > 0) qv[a][c] = ld<R>(o, tix(comp, s, 12));
+            }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const uint32_t comp = (uint32_t)(3 * a + c);
-                const cx<R> p = ld<R>(psi[0], tix(comp, s, 12));
+                const cx<R> p = pv[a][c];
                 cx<R> hv = p - kappa * acc[0][a][c];
                 if (a >= 2) hv = -hv;
                 if constexpr (MODE == 0) {
@@ -509,11 +551,9 @@ __device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2
                 } else {
                     const R zr = (R)zsr, zi = (R)zsi;
                     cx<R> q = mk<R>(zr * p.re - zi * p.im - hv.re, zr * p.im + zi * p.re - hv.im);
-                    if (k > 0) {
-                        const cx<R> qo = ld<R>(o, tix(comp, s, 12));
-                        q.re += br * qo.re - bi * qo.im;
-                        q.im += br * qo.im + bi * qo.re;
-                    }
+                    const cx<R> qo = qv[a][c];
+                    q.re += br * qo.re - bi * qo.im;
+                    q.im += br * qo.im + bi * qo.re;
                     stc<R>(o, tix(comp, s, 12), q);
                     dre += (double)p.re * (double)q.re + (double)p.im * (double)q.im;
                     dim += (double)p.re * (double)q.im - (double)p.im * (double)q.re;
@@ -738,19 +778,29 @@ __device__ __forceinline__ void iter_block(const JobDesc& J, int k, unsigned til
     const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k] : make_double2(0, 0);
     double2* sacc = J.s64 + (size_t)n * n12;
     if (valid) {
+        // every load of the site's own vectors is issued before the first
+        // store (the outputs may alias the inputs as far as the compiler knows)
+        cx<R> qv[12], rv[12];
+#pragma unroll
+        for (int comp = 0; comp < 12; ++comp) {
+            const uint32_t o = tix((uint32_t)comp, s, 12);
+            qv[comp] = k > 0 ? ld<R>(qin, o) : mk<R>(0, 0);
+            if constexpr (TIL == 1) {
+                const C2<R> w = lt[comp * kBlock + threadIdx.x];
+                rv[comp] = mk<R>(w.x, w.y);
+            } else {
+                rv[comp] = ld<R>(rin, o);
+            }
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const uint32_t comp = (uint32_t)(3 * a + c);
                 const uint32_t o = tix(comp, s, 12);
-                const cx<R> qo = k > 0 ? ld<R>(qin, o) : mk<R>(0, 0);
-                cx<R> r;
-                if constexpr (TIL == 1) {
-                    const C2<R> w = lt[comp * kBlock + threadIdx.x];
-                    r = mk<R>(w.x, w.y);
-                } else {
-                    r = ld<R>(rin, o);
+                const cx<R> qo = qv[comp];
+                cx<R> r = rv[comp];
+                if constexpr (TIL == 0) {
                     if (k > 0) {
                         const cx<R> al = fi.a[0];
                         r = mk<R>(r.re - (al.re * qo.re - al.im * qo.im),
