@@ -349,6 +349,22 @@ def oracle_sample_accuracy(torch, ovl, Ud, B, pick, s_ref):
     return out
 
 
+def stencil_rows(ctx, ovl):
+    """H_W alone (ovl_bench_kernel) on the bench field at 1024 and 4
+    right-hand sides, FP64 and FP32: 25.8 / 12.9 GB per launch at 1024, far
+    above the 256 MB last-level cache."""
+    sten = {}
+    for label, which, n in [("fp64_n1024", ovl.BENCH_STENCIL64, 1024),
+                            ("fp32_n1024", ovl.BENCH_STENCIL32, 1024),
+                            ("fp64_n4", ovl.BENCH_STENCIL64, 4), ("fp32_n4", ovl.BENCH_STENCIL32, 4)]:
+        ms, nb = ctx.bench_kernel(which, n, 5 if n > 64 else 50)
+        sten[label] = {"avg_ms": round(ms, 4), "GB/s": round(nb / (ms * 1e-3) / 1e9, 1),
+                       "frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "algorithmic_bytes": nb}
+        log(f"stencil {label}: {sten[label]['GB/s']} GB/s")
+    return sten
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +378,9 @@ def main():
     ap.add_argument("--only-steps", action="store_true",
                     help="only the warm-up and timed steps and the profiled application that "
                          "gives the roofline (for profiler runs)")
+    ap.add_argument("--only-stencil", action="store_true",
+                    help="only the stand-alone stencil rows (for counter runs of the n = 1024 "
+                         "stencil); prints {\"stencil\": ...}")
     ap.add_argument("--cpu-nodes", type=int, default=16)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="copy this many GiB once before the steps (reference kernel of known "
@@ -386,6 +405,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log(f"calibration copy of {args.calib_copy_gib} GiB done")
+    if args.only_stencil:
+        print(json.dumps({"stencil": stencil_rows(ctx, ovl)}), flush=True)
+        ctx.close()
+        return
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         out, st = ctx.apply_dov(Bd)
@@ -511,16 +534,7 @@ def main():
         rec["paper_workload"] = paper_workload(torch, ovl)
 
     # ---- the stencil on a batch far larger than the 256 MB last-level cache
-    sten = {}
-    for label, which, n in [("fp64_n1024", ovl.BENCH_STENCIL64, 1024),
-                            ("fp32_n1024", ovl.BENCH_STENCIL32, 1024),
-                            ("fp64_n4", ovl.BENCH_STENCIL64, 4), ("fp32_n4", ovl.BENCH_STENCIL32, 4)]:
-        ms, nb = ctx.bench_kernel(which, n, 5 if n > 64 else 50)
-        sten[label] = {"avg_ms": round(ms, 4), "GB/s": round(nb / (ms * 1e-3) / 1e9, 1),
-                       "frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                       "algorithmic_bytes": nb}
-        log(f"stencil {label}: {sten[label]['GB/s']} GB/s")
-    rec["stencil"] = sten
+    rec["stencil"] = stencil_rows(ctx, ovl)
     ctx.close()
     if not args.no_batch:
         log("batched uneven lattices")
