@@ -164,7 +164,9 @@ int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, in
 /* True-residual checks of the recurrence's residual estimates (shift j stops
  * on the estimate ||r_k|| / |pi_k^j|, not on its true residual).
  * In-band check (OVL_FORM_BASIS, on by default): after every solve, the
- * shift of each rhs with the largest final estimate has its solution
+ * shift of each rhs that stayed active longest (ties: the largest final
+ * estimate; every converged shift ends just below tol, and the one active
+ * longest ran through the most FP32 iterations of a mixed solve) has its solution
  * x_j = sum_i u_i^j r_i rebuilt in the same pass over the stored basis that
  * forms the sum s (one more output vector), and its true residual
  * ||b - (z_j - H_W) x_j|| / ||b|| is computed in FP64 with one more FP64
@@ -174,8 +176,8 @@ int ovl_set_solver(ovl_ctx* ctx, int32_t precision, int32_t form, double tol, in
  * again in FP64 (ovl_stats.fp64_repeat = 1); if that misses 10 tol, the call
  * returns OVL_NOT_CONVERGED.  The other forms report -1 for the in-band check.
  * nsample >= 1 adds a synchronous diagnostic after each ovl_apply_sign /
- * ovl_apply_dov: for the nsample shifts of each rhs with the largest final
- * estimate, x_j is formed (stored by OVL_FORM_REFERENCE, rebuilt from the
+ * ovl_apply_dov: for the nsample shifts of each rhs first in that order (the
+ * reference form: largest final estimate), x_j is formed (stored by OVL_FORM_REFERENCE, rebuilt from the
  * stored basis by OVL_FORM_BASIS) and its true residual computed with one
  * more stencil; max_true_rel_res becomes the maximum of both checks.
  * nsample = 0 (default) keeps the in-band check only; nsample = -1 turns the
@@ -185,8 +187,8 @@ int ovl_set_residual_check(ovl_ctx* ctx, int32_t nsample);
 /* The bound on the in-band true residual above which an OVL_PREC_MIXED apply
  * is repeated in FP64 (see ovl_set_residual_check).  The FP32 phase, which
  * starts once every shifted residual is below switch_res, adds to the true
- * residual a drift of about eps32 * switch_res (eps32 = 2^-24) that the
- * recurrence's estimates do not see; bound = 0 (default) takes
+ * residual a drift of a few eps32 * switch_res (eps32 = 2^-24; measured 2 to
+ * 3 eps32 switch_res at 16^4) that the recurrence's estimates do not see; bound = 0 (default) takes
  * max(10 tol, 10 eps32 switch_res), so only more drift than that triggers the
  * repeat.  A caller that needs every apply's true residual within 10 tol sets
  * bound = 10 tol (mixed applies whose drift exceeds it then cost an FP64

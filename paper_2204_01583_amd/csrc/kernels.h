@@ -100,14 +100,14 @@ void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t 
 void launch_basis_coef(const double2* h_a, const double2* h_b, const double2* h_pi,
                        const double2* c, const SrcState* st, double2* W, double2* h, int J,
                        int maxk, int nsrc, hipStream_t s);
-// s[src] (+)= sum_{l in [l0,l1)} h[src][g0+l] * slot_l[src] over one chunk of slots of type R;
-// with hx non-null also xc[src] (+)= sum_l hx[src][g0+l] * slot_l[src] in the same pass
-template <typename R>
-void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_stride,
-                       const double2* h, const double2* hx, int maxk, const SrcState* st, int g0,
-                       int l0, int l1, double2* sacc, double2* xc, bool accumulate, int64_t n12,
-                       int nsrc, hipStream_t s);
-// per source, the shift with the largest final residual estimate: its basis
+// s_n = sum_{i < min(kend, iter_n + 1)} h[n][i] r_i over every stored slot in
+// one launch (and x_n with the coefficients hx when non-null); slots below
+// ksw FP64, from ksw FP32; chunks is the device table of slot-chunk bases
+void launch_basis_sum(char* const* chunks, size_t slot_bytes, int kend, int ksw, const double2* h,
+                      const double2* hx, int maxk, const SrcState* st, double2* sacc, double2* xc,
+                      int64_t n12, int nsrc, hipStream_t s);
+// per source, the shift that stayed active longest (latest nonzero basis
+// coefficient), ties to the largest final residual estimate: its basis
 // coefficients W[src][i][j] into hx[src][i] and its node z[j] into zc[src]
 void launch_pick_check(const double* res, const double2* W, const double2* z, const SrcState* st,
                        int J, int maxk, int nsrc, double2* hx, double2* zc, hipStream_t s);

@@ -406,13 +406,15 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
         const bool acc2 = J.h != nullptr;
         const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
         double2* sacc = J.s64 + (size_t)n * n12;
-        const float4* ri4 = reinterpret_cast<const float4*>(ri);
-        const float4* qq4 = reinterpret_cast<const float4*>(qq);
-        float4* ro4 = reinterpret_cast<float4*>(ro);
+        // (global address-space pointers: global, not flat, loads and stores)
+        typedef float __attribute__((ext_vector_type(4))) F4;
+        const OVL_GLOBAL F4* ri4 = (const OVL_GLOBAL F4*)ri;
+        const OVL_GLOBAL F4* qq4 = (const OVL_GLOBAL F4*)qq;
+        OVL_GLOBAL F4* ro4 = (OVL_GLOBAL F4*)ro;
         const int64_t n2 = n12 / 2;
         for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n2; e += (int64_t)J.nbe * kBlock) {
-            const float4 r = ri4[e], qv = qq4[e];
-            float4 rn;
+            const F4 r = ri4[e], qv = qq4[e];
+            F4 rn;
             rn.x = r.x - ((float)ar * qv.x - (float)ai * qv.y);
             rn.y = r.y - ((float)ar * qv.y + (float)ai * qv.x);
             rn.z = r.z - ((float)ar * qv.z - (float)ai * qv.w);
@@ -637,174 +639,59 @@ void launch_basis_coef(const double2* h_a, const double2* h_b, const double2* h_
                        W, c, st, h, J, maxk);
 }
 
-// s[src] = (s[src] +) sum_l h[src][g0 + l] * slot_l[src] over local slots
-// l0 <= l < l1 of one contiguous chunk whose slot 0 is global slot g0;
-// slots at or beyond K_src + 1 are skipped (they were never written).  With
-// hx != null the same pass also forms xc[src] (+)= sum_l hx[src][g0 + l] *
-// slot_l[src]: one shifted solution, rebuilt for its true-residual check at
-// the cost of one more output stream.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_gemv(const C2<R>* __restrict__ slots,
-                                                 int64_t slot_stride, int64_t src_stride,
-                                                 const double2* __restrict__ h,
-                                                 const double2* __restrict__ hx, int maxk,
-                                                 const SrcState* __restrict__ st, int g0, int l0,
-                                                 int l1, double2* __restrict__ sacc,
-                                                 double2* __restrict__ xc, int accumulate,
-                                                 int64_t n12) {
-    const int n = blockIdx.y;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= n12) return;
-    const int K = st[n].iter + 1;  // r_0 .. r_K exist; h is zero beyond K-1
-    const int lend = (K - g0) < l1 ? (K - g0) : l1;
-    double re = 0.0, im = 0.0, xr = 0.0, xi = 0.0;
-    const double2* hh = h + (int64_t)n * (maxk + 1) + g0;
-    const double2* hc = hx ? hx + (int64_t)n * (maxk + 1) + g0 : nullptr;
-    const C2<R>* base = slots + n * src_stride + e;
-    for (int l = l0; l < lend; ++l) {
-        const double2 c = hh[l];
-        const C2<R> v = base[(int64_t)l * slot_stride];
-        re += c.x * (double)v.x - c.y * (double)v.y;
-        im += c.x * (double)v.y + c.y * (double)v.x;
-        if (hc) {
-            const double2 u = hc[l];
-            xr += u.x * (double)v.x - u.y * (double)v.y;
-            xi += u.x * (double)v.y + u.y * (double)v.x;
-        }
-    }
-    double2 o = make_double2(re, im);
-    if (accumulate) {
-        const double2 prev = sacc[n * n12 + e];
-        o.x += prev.x;
-        o.y += prev.y;
-    }
-    sacc[n * n12 + e] = o;
-    if (hc) {
-        double2 ox = make_double2(xr, xi);
-        if (accumulate) {
-            const double2 prev = xc[n * n12 + e];
-            ox.x += prev.x;
-            ox.y += prev.y;
-        }
-        xc[n * n12 + e] = ox;
-    }
-}
-
-// FP32 slots, two elements per lane: the same sums in the same order as k_gemv
-__global__ __launch_bounds__(kBlock) void k_gemv2(const float4* __restrict__ slots,
-                                                  int64_t slot_stride2, int64_t src_stride2,
-                                                  const double2* __restrict__ h,
-                                                  const double2* __restrict__ hx, int maxk,
-                                                  const SrcState* __restrict__ st, int g0, int l0,
-                                                  int l1, double2* __restrict__ sacc,
-                                                  double2* __restrict__ xc, int accumulate,
-                                                  int64_t n12) {
-    const int n = blockIdx.y;
-    const int64_t e2 = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // element pair
-    if (2 * e2 >= n12) return;
-    const int K = st[n].iter + 1;  // r_0 .. r_K exist; h is zero beyond K-1
-    const int lend = (K - g0) < l1 ? (K - g0) : l1;
-    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
-    double xr0 = 0.0, xi0 = 0.0, xr1 = 0.0, xi1 = 0.0;
-    const double2* hh = h + (int64_t)n * (maxk + 1) + g0;
-    const double2* hc = hx ? hx + (int64_t)n * (maxk + 1) + g0 : nullptr;
-    const float4* base = slots + n * src_stride2 + e2;
-    for (int l = l0; l < lend; ++l) {
-        const double2 c = hh[l];
-        const float4 v = base[(int64_t)l * slot_stride2];
-        re0 += c.x * (double)v.x - c.y * (double)v.y;
-        im0 += c.x * (double)v.y + c.y * (double)v.x;
-        re1 += c.x * (double)v.z - c.y * (double)v.w;
-        im1 += c.x * (double)v.w + c.y * (double)v.z;
-        if (hc) {
-            const double2 u = hc[l];
-            xr0 += u.x * (double)v.x - u.y * (double)v.y;
-            xi0 += u.x * (double)v.y + u.y * (double)v.x;
-            xr1 += u.x * (double)v.z - u.y * (double)v.w;
-            xi1 += u.x * (double)v.w + u.y * (double)v.z;
-        }
-    }
-    double2 o0 = make_double2(re0, im0), o1 = make_double2(re1, im1);
-    double2* out = sacc + n * n12 + 2 * e2;
-    if (accumulate) {
-        const double2 p0 = out[0], p1 = out[1];
-        o0.x += p0.x;
-        o0.y += p0.y;
-        o1.x += p1.x;
-        o1.y += p1.y;
-    }
-    out[0] = o0;
-    out[1] = o1;
-    if (hc) {
-        double2 x0 = make_double2(xr0, xi0), x1 = make_double2(xr1, xi1);
-        double2* xo = xc + n * n12 + 2 * e2;
-        if (accumulate) {
-            const double2 p0 = xo[0], p1 = xo[1];
-            x0.x += p0.x;
-            x0.y += p0.y;
-            x1.x += p1.x;
-            x1.y += p1.y;
-        }
-        xo[0] = x0;
-        xo[1] = x1;
-    }
-}
-template <typename R>
-void launch_basis_gemv(const void* slots, int64_t slot_stride, int64_t src_stride,
-                       const double2* h, const double2* hx, int maxk, const SrcState* st, int g0,
-                       int l0, int l1, double2* sacc, double2* xc, bool accumulate, int64_t n12,
-                       int nsrc, hipStream_t s) {
-    if constexpr (sizeof(R) == 4) {
-        // two elements per lane in one 16-byte access per slot (12 Vt and the
-        // element strides are even, the slot bases 16-byte aligned)
-        dim3 grid((unsigned)((n12 / 2 + kBlock - 1) / kBlock), nsrc);
-        hipLaunchKernelGGL(k_gemv2, grid, dim3(kBlock), 0, s, (const float4*)slots, slot_stride / 2,
-                           src_stride / 2, h, hx, maxk, st, g0, l0, l1, sacc, xc, (int)accumulate,
-                           n12);
-        return;
-    }
-    dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock), nsrc);
-    hipLaunchKernelGGL(k_gemv<R>, grid, dim3(kBlock), 0, s, (const C2<R>*)slots, slot_stride,
-                       src_stride, h, hx, maxk, st, g0, l0, l1, sacc, xc, (int)accumulate, n12);
-}
-template void launch_basis_gemv<double>(const void*, int64_t, int64_t, const double2*,
-                                        const double2*, int, const SrcState*, int, int, int,
-                                        double2*, double2*, bool, int64_t, int, hipStream_t);
-template void launch_basis_gemv<float>(const void*, int64_t, int64_t, const double2*,
-                                       const double2*, int, const SrcState*, int, int, int,
-                                       double2*, double2*, bool, int64_t, int, hipStream_t);
-
-// The in-band residual check: for every source pick the shift with the
-// largest final residual estimate res[src][j] (ties: the lower j), and copy
-// its basis coefficients u_i^j = W[src][i][j] into hx[src][i] (zero beyond
-// the source's iteration count) and its node into zc[src].  One block per source.
+// The in-band residual check: for every source pick one shift (below), and
+// copy its basis coefficients u_i^j = W[src][i][j] into hx[src][i] (zero
+// beyond the source's iteration count) and its node into zc[src].  One block
+// per source.
 __global__ __launch_bounds__(kBlock) void k_pick_check(const double* __restrict__ res,
                                                        const double2* __restrict__ W,
                                                        const double2* __restrict__ z,
                                                        const SrcState* __restrict__ st, int J,
                                                        int maxk, double2* __restrict__ hx,
                                                        double2* __restrict__ zc) {
+    // The checked shift is the one that stayed active longest (its last
+    // nonzero coefficient u_i^j comes latest), ties to the largest final
+    // estimate, then the lower index.  Every converged shift ends with an
+    // estimate just below the tolerance, so the estimate alone does not tell
+    // which shift ran through the most FP32 iterations of a mixed solve; the
+    // one active longest carries the most of their rounding.
     const int n = blockIdx.x;
+    const int K = st[n].iter;
+    const double2* Wn = W + (size_t)n * (maxk + 1) * J;
+    int bl = -1;
     double best = -1.0;
     int bj = 0;
     for (int j = threadIdx.x; j < J; j += kBlock) {
+        int last = -1;
+        for (int i = K - 1; i >= 0; --i) {
+            const double2 u = Wn[(size_t)i * J + j];
+            if (u.x != 0.0 || u.y != 0.0) {
+                last = i;
+                break;
+            }
+        }
         const double v = res[(size_t)n * J + j];
-        if (v > best) {  // strided scan: j increases, so ties keep the lower j
+        if (last > bl || (last == bl && v > best)) {  // j increases: ties keep the lower j
+            bl = last;
             best = v;
             bj = j;
         }
     }
-    // block argmax, ties to the lower index
+    // block argmax of (last, estimate), ties to the lower index
+    __shared__ int sl[kBlock];
     __shared__ double sv[kBlock];
     __shared__ int sj[kBlock];
+    sl[threadIdx.x] = bl;
     sv[threadIdx.x] = best;
     sj[threadIdx.x] = bj;
     __syncthreads();
     for (int o = kBlock / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
+            const int la = sl[threadIdx.x], lb = sl[threadIdx.x + o];
             const double a = sv[threadIdx.x], b = sv[threadIdx.x + o];
             const int ja = sj[threadIdx.x], jb = sj[threadIdx.x + o];
-            if (b > a || (b == a && jb < ja)) {
+            if (lb > la || (lb == la && (b > a || (b == a && jb < ja)))) {
+                sl[threadIdx.x] = lb;
                 sv[threadIdx.x] = b;
                 sj[threadIdx.x] = jb;
             }
@@ -812,7 +699,6 @@ __global__ __launch_bounds__(kBlock) void k_pick_check(const double* __restrict_
         __syncthreads();
     }
     const int j = sj[0];
-    const int K = st[n].iter;
     for (int i = threadIdx.x; i <= maxk; i += kBlock)
         hx[(size_t)n * (maxk + 1) + i] =
             i < K ? W[((size_t)n * (maxk + 1) + i) * J + j] : make_double2(0, 0);
@@ -934,15 +820,20 @@ __global__ __launch_bounds__(kBlock) void k_materialize(char* const* __restrict_
     double re[JG], im[JG];
 #pragma unroll
     for (int q = 0; q < JG; ++q) re[q] = im[q] = 0.0;
+    // the slot bases come from a table in memory: the loads go through
+    // global address-space pointers (global, not flat, loads)
+    typedef double __attribute__((ext_vector_type(2))) D2;
+    typedef float __attribute__((ext_vector_type(2))) F2;
     for (int i = 0; i < K; ++i) {
-        const char* slot = chunks[i / kSlotChunk] + (size_t)(i % kSlotChunk) * slot_bytes;
+        const OVL_GLOBAL char* slot =
+            (const OVL_GLOBAL char*)chunks[i / kSlotChunk] + (size_t)(i % kSlotChunk) * slot_bytes;
         double vr, vi;
         if (i < ksw) {
-            const double2 v = reinterpret_cast<const double2*>(slot)[eoff + e];
+            const D2 v = ((const OVL_GLOBAL D2*)slot)[eoff + e];
             vr = v.x;
             vi = v.y;
         } else {
-            const float2 v = reinterpret_cast<const float2*>(slot)[eoff + e];
+            const F2 v = ((const OVL_GLOBAL F2*)slot)[eoff + e];
             vr = v.x;
             vi = v.y;
         }
@@ -970,6 +861,67 @@ void launch_materialize(char* const* chunks, size_t slot_bytes, int K, int ksw, 
         hipLaunchKernelGGL(k_materialize<kMatGroup>, grid, dim3(kBlock), 0, s, chunks, slot_bytes,
                            K, ksw, W, J, j0 + q0, m, Y + (size_t)q0 * n12, n12, eoff);
     }
+}
+
+// Basis form, the whole sum in one pass over the stored slots: for source n
+// (grid.y) s_n = sum_{i < K_n} h[n][i] r_i, K_n = min(kend, iter_n + 1), and
+// with hx also x_n = sum_i hx[n][i] r_i (the in-band check's solution).
+// Slots below ksw hold FP64, from ksw on FP32 packed at the slot base; slot i
+// is chunks[i / kSlotChunk] + (i % kSlotChunk) slot_bytes, source n at
+// element n n12.  Each output is written once, and the terms are added in
+// slot order.
+__global__ __launch_bounds__(kBlock) void k_basis_sum(char* const* __restrict__ chunks,
+                                                      size_t slot_bytes, int kend, int ksw,
+                                                      const double2* __restrict__ h,
+                                                      const double2* __restrict__ hx, int maxk,
+                                                      const SrcState* __restrict__ st,
+                                                      double2* __restrict__ sacc,
+                                                      double2* __restrict__ xc, int64_t n12) {
+    typedef double __attribute__((ext_vector_type(2))) D2;
+    typedef float __attribute__((ext_vector_type(2))) F2;
+    const int n = blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n12) return;
+    const int kn = st[n].iter + 1;
+    const int K = kend < kn ? kend : kn;
+    const int k64 = ksw < K ? ksw : K;
+    const int64_t off = (int64_t)n * n12 + e;
+    const double2* hh = h + (int64_t)n * (maxk + 1);
+    const double2* hc = hx ? hx + (int64_t)n * (maxk + 1) : nullptr;
+    double re = 0.0, im = 0.0, xr = 0.0, xi = 0.0;
+    auto term = [&](int i, double vr, double vi) {
+        const double2 c = hh[i];
+        re += c.x * vr - c.y * vi;
+        im += c.x * vi + c.y * vr;
+        if (hc) {
+            const double2 u = hc[i];
+            xr += u.x * vr - u.y * vi;
+            xi += u.x * vi + u.y * vr;
+        }
+    };
+#pragma unroll 4
+    for (int i = 0; i < k64; ++i) {
+        const OVL_GLOBAL char* slot =
+            (const OVL_GLOBAL char*)chunks[i / kSlotChunk] + (size_t)(i % kSlotChunk) * slot_bytes;
+        const D2 v = ((const OVL_GLOBAL D2*)slot)[off];
+        term(i, v.x, v.y);
+    }
+#pragma unroll 4
+    for (int i = k64; i < K; ++i) {
+        const OVL_GLOBAL char* slot =
+            (const OVL_GLOBAL char*)chunks[i / kSlotChunk] + (size_t)(i % kSlotChunk) * slot_bytes;
+        const F2 v = ((const OVL_GLOBAL F2*)slot)[off];
+        term(i, (double)v.x, (double)v.y);
+    }
+    sacc[off] = make_double2(re, im);
+    if (hc) xc[off] = make_double2(xr, xi);
+}
+void launch_basis_sum(char* const* chunks, size_t slot_bytes, int kend, int ksw, const double2* h,
+                      const double2* hx, int maxk, const SrcState* st, double2* sacc, double2* xc,
+                      int64_t n12, int nsrc, hipStream_t s) {
+    const dim3 grid((unsigned)((n12 + kBlock - 1) / kBlock), (unsigned)nsrc);
+    hipLaunchKernelGGL(k_basis_sum, grid, dim3(kBlock), 0, s, chunks, slot_bytes, kend, ksw, h, hx,
+                       maxk, st, sacc, xc, n12);
 }
 
 // t = b - (z x - H x) over one source; partial[blk] = (|t|^2, |b|^2) of the block

@@ -1914,33 +1914,24 @@ static int solve_batch_once(Batch& B) {
                 launch_basis_coef(w.h_a, w.h_b, w.h_pi, w.cj, w.st, w.W, w.h, w.J, w.maxk, w.nsrc, s);
             }
             if (form == OVL_FORM_BASIS) {
-                // s = sum_i h_i r_i, chunk by chunk; FP64 slots below k_switch, FP32 from it.
-                // With the in-band check the same pass rebuilds each source's worst
-                // shifted solution x = sum_i u_i^j r_i into p64 (free after the solve).
+                // s = sum_i h_i r_i over every stored slot in one pass; FP64 slots
+                // below k_switch, FP32 from it.  With the in-band check the same
+                // pass rebuilds each source's checked shifted solution
+                // x = sum_i u_i^j r_i into p64 (free after the solve).
                 const int kend = w.K + 1;
                 const int ksw = w.k_switch < 0 ? kend : w.k_switch;
                 if (w.hx)
                     launch_pick_check(w.sh.res, w.W, w.zj, w.st, w.J, w.maxk, w.nsrc, w.hx, w.zc, s);
-                bool acc = false;
-                for (int c0 = 0; c0 < kend; c0 += kSlotChunk) {
-                    const int c1 = std::min(kend, c0 + kSlotChunk);
-                    char* base = w.chunks[c0 / kSlotChunk];
-                    const int a0 = c0, a1 = std::min(c1, ksw);
-                    if (a1 > a0) {
-                        ProfScope ps(lead, s, 6, Na * w.nsrc * (16.0 * (a1 - a0) + (w.hx ? 64.0 : 32.0)));
-                        launch_basis_gemv<double>(base, (int64_t)w.nsrc * N, N, w.h, w.hx, w.maxk,
-                                                  w.st, c0, a0 - c0, a1 - c0, w.s64, w.p64, acc,
-                                                  N, w.nsrc, s);
-                        acc = true;
-                    }
-                    const int f0 = std::max(c0, ksw), f1 = c1;
-                    if (f1 > f0) {
-                        ProfScope ps(lead, s, 6, Na * w.nsrc * (8.0 * (f1 - f0) + (w.hx ? 64.0 : 32.0)));
-                        launch_basis_gemv<float>(base, (int64_t)w.nsrc * N * 2, N, w.h, w.hx,
-                                                 w.maxk, w.st, c0, f0 - c0, f1 - c0, w.s64, w.p64,
-                                                 acc, N, w.nsrc, s);
-                        acc = true;
-                    }
+                {
+                    // every stored slot in one launch, s (and x) written once; the
+                    // device table must hold every chunk up to slot kend - 1
+                    if (!slots_cover(w, kend - 1))
+                        return fail(lead, OVL_E_STATE, "basis slots up to %d not in the table",
+                                    kend - 1);
+                    const int n64 = std::min(kend, ksw), n32 = kend - n64;
+                    ProfScope ps(lead, s, 6, Na * w.nsrc * (16.0 * n64 + 8.0 * n32 + (w.hx ? 32.0 : 16.0)));
+                    launch_basis_sum(w.slot_tab, w.slot_bytes, kend, ksw, w.h, w.hx, w.maxk, w.st,
+                                     w.s64, w.p64, N, w.nsrc, s);
                 }
                 if (w.hx) {
                     // true residual of the rebuilt solution in FP64: H x (the FP64
@@ -2059,9 +2050,11 @@ static int solve_batch_once(Batch& B) {
 // The bound on the in-band true residual of a mixed-precision apply.  The
 // FP32 phase of a job starts when its every shifted residual is below
 // switch_res; from there on FP32 matvecs and vectors add to the true
-// residual a drift of about eps32 * switch_res (measured: 3.7e-10 at switch
-// 1e-2), which the recurrence's estimates do not see.  Default: max(10 tol, 10 eps32
-// switch_res), so a repeat means more drift than that mechanism gives.
+// residual a drift of a few eps32 * switch_res (measured at 16^4 on the
+// shift active longest: 1.9e-9, 1.3e-10 and 1.9e-11 at switch 1e-2, 1e-3
+// and 1e-4, 2 to 3 eps32 switch_res), which the recurrence's estimates do
+// not see.  Default: max(10 tol, 10 eps32 switch_res), so a repeat means
+// more drift than that mechanism gives.
 static double mixed_check_bound(const ovl_ctx* c) {
     if (c->check_bound > 0.0) return c->check_bound;
     const double eps32 = 5.960464477539063e-8;  // 2^-24
@@ -2142,7 +2135,30 @@ static int true_residuals(ovl_ctx* ctx, const Work& w) {
         std::vector<int> order(J);
         for (int j = 0; j < J; ++j) order[j] = j;
         const double* e = est.data() + (size_t)n * J;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e[a] > e[b]; });
+        // basis form: shifts that stayed active longest first (last nonzero
+        // coefficient u_i^j), as the in-band check picks them; then the
+        // largest final estimate (the only order for the reference form)
+        std::vector<int> last(J, 0);
+        if (ctx->form == OVL_FORM_BASIS && w.W) {
+            const int K = hs[n].iter;
+            std::vector<double2> Wn((size_t)std::max(K, 1) * J);
+            if (K > 0)
+                HIPCHK(ctx, hipMemcpy(Wn.data(), w.W + (size_t)n * (w.maxk + 1) * J,
+                                      (size_t)K * J * sizeof(double2), hipMemcpyDeviceToHost));
+            for (int j = 0; j < J; ++j) {
+                last[j] = -1;
+                for (int i = K - 1; i >= 0; --i) {
+                    const double2 u = Wn[(size_t)i * J + j];
+                    if (u.x != 0.0 || u.y != 0.0) {
+                        last[j] = i;
+                        break;
+                    }
+                }
+            }
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return last[a] != last[b] ? last[a] > last[b] : e[a] > e[b];
+        });
         const int m = std::min(ctx->check_n, J);
         for (int q = 0; q < m; ++q) {
             const int j = order[q];
