@@ -662,14 +662,17 @@ __global__ __launch_bounds__(kBlock) void k_pick_check(const double* __restrict_
     double best = -1.0;
     int bj = 0;
     for (int j = threadIdx.x; j < J; j += kBlock) {
-        int last = -1;
-        for (int i = K - 1; i >= 0; --i) {
-            const double2 u = Wn[(size_t)i * J + j];
-            if (u.x != 0.0 || u.y != 0.0) {
-                last = i;
-                break;
-            }
+        // u_i^j is nonzero while the shift is active and zero from its
+        // deactivation on (its history then holds zeros): bisect for the
+        // last nonzero coefficient, about log2 K loads
+        int lo = -1, hi = K;  // Wn[lo] nonzero (or lo = -1), Wn[hi] zero (or hi = K)
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            const double2 u = Wn[(size_t)mid * J + j];
+            if (u.x != 0.0 || u.y != 0.0) lo = mid;
+            else hi = mid;
         }
+        const int last = lo;
         const double v = res[(size_t)n * J + j];
         if (last > bl || (last == bl && v > best)) {  // j increases: ties keep the lower j
             bl = last;

@@ -2146,14 +2146,15 @@ static int true_residuals(ovl_ctx* ctx, const Work& w) {
                 HIPCHK(ctx, hipMemcpy(Wn.data(), w.W + (size_t)n * (w.maxk + 1) * J,
                                       (size_t)K * J * sizeof(double2), hipMemcpyDeviceToHost));
             for (int j = 0; j < J; ++j) {
-                last[j] = -1;
-                for (int i = K - 1; i >= 0; --i) {
-                    const double2 u = Wn[(size_t)i * J + j];
-                    if (u.x != 0.0 || u.y != 0.0) {
-                        last[j] = i;
-                        break;
-                    }
+                // the same bisection as the in-band pick (nonzero while active)
+                int lo = -1, hi = K;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) / 2;
+                    const double2 u = Wn[(size_t)mid * J + j];
+                    if (u.x != 0.0 || u.y != 0.0) lo = mid;
+                    else hi = mid;
                 }
+                last[j] = lo;
             }
         }
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {

@@ -705,3 +705,37 @@ def test_basis_iteration_kinds_match_the_oracle(fused, monkeypatch):
         assert (st.stencil_variant64 >= 1000) == (fused == "1")
         assert_close(s.cpu().numpy(), ref, tol, f"fused={fused} basis p{precision}")
         ctx.close()
+
+
+@pytest.fixture(scope="module")
+def eig_4x4():
+    """Dense eigendecomposition of the 4^4 parity field's H_W (3072 x 3072)."""
+    from oracle.sign import eigh_dense
+    c = CFG0
+    return eigh_dense(oracle_H(c["dims"], c["r"], c["seed"], c["m0"]))
+
+
+@pytest.mark.parametrize("precision,form,nq", [(0, 2, 1024), (1, 2, 1024), (0, 3, 1024),
+                                               (0, 1, 512), (1, 1, 512)])
+def test_maximum_shift_counts_against_the_oracle(precision, form, nq, eig_4x4):
+    """The largest node sets the library takes: 2 x 1024 = 2048 shifts (eight
+    256-shift slices) in the basis and two-pass forms, 2 x 512 = 1024 in the
+    sweep form, whose per-shift directions are limited to that.  The 4^4
+    field (roughness 0.3) and two sources against the oracle's dense
+    eigendecomposition route, s = V F(lam) V^dag b with the same nodes and
+    weights, element by element."""
+    from oracle.sign import sign_by_eigh
+    c = CFG0
+    U = gauge(c["dims"], c["r"], c["seed"])
+    b = si.gaussian_sources(c["dims"], 2, first_seed=61)
+    ctx = make_ctx(c["dims"], U, c["m0"], c["mq"], nq, precision=precision, form=form,
+                   tol=1e-13 if precision == 0 else 1e-12)
+    s, st = ctx.apply_sign(to_dev(b))
+    assert st.n_shifts == 2 * nq and st.n_active_end == 0
+    z, w = nodes(nq, *CIRCLE)
+    H = oracle_H(c["dims"], c["r"], c["seed"], c["m0"])
+    tol = 1e-11 if precision == 0 else 1e-10
+    for i in range(2):
+        ref, _ = sign_by_eigh(H, b[i].ravel(), z, w, eig=eig_4x4)
+        assert_close(s[i].cpu().numpy(), ref, tol, f"{2 * nq} shifts, form {form}, prec {precision}")
+    ctx.close()
