@@ -470,14 +470,15 @@ def main():
     err = relerrs(s_mix, s64)
     rec["accuracy"] = {"mixed_vs_fp64_rel_err": err, "max": max(err), "target": 1e-10}
     log(f"mixed vs fp64 err {max(err):.2e}")
-    # true residuals ||b - (z_j - H) x_j|| / ||b|| of the 2 shifts per source with
-    # the largest residual estimates, x_j rebuilt from the stored basis
+    # true residuals ||b - (z_j - H) x_j|| / ||b|| of the shift per source that
+    # stayed active longest (in-band) and of the first two in that order
+    # (synchronous), x_j rebuilt from the stored basis
     for label, prec in (("fp64", ovl.PREC_FP64), ("mixed", ovl.PREC_MIXED)):
         ctx.set_solver(prec, ovl.FORM_BASIS, tol=TOL, maxiter=3000, switch_res=SWITCH)
         ctx.set_residual_check(2)
         _, stc = ctx.apply_sign(Bd)
         ctx.set_residual_check(0)
-        rec["accuracy"][f"{label}_true_rel_res_worst_shifts"] = stc.max_true_rel_res
+        rec["accuracy"][f"{label}_true_rel_res_checked_shifts"] = stc.max_true_rel_res
         rec["accuracy"][f"{label}_est_rel_res"] = stc.max_est_rel_res
         log(f"{label}: true residual {stc.max_true_rel_res:.2e} (estimate {stc.max_est_rel_res:.2e})")
     ctx.set_solver(ovl.PREC_FP64, ovl.FORM_BASIS, tol=TOL, maxiter=3000)
@@ -495,7 +496,7 @@ def main():
                                  "err_vs_fp64": max(relerrs(sm, s64)),
                                  "iterations": stm.iterations,
                                  "fp32_iterations": stm.fp32_iterations,
-                                 "true_rel_res_worst_shift": stm.max_true_rel_res,
+                                 "true_rel_res_checked_shift": stm.max_true_rel_res,
                                  "fp64_repeat": stm.fp64_repeat}
         log(f"switch {theta:.0e}: {sweep[f'{theta:.0e}']}")
         del sm

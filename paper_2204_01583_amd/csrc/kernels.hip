@@ -238,12 +238,12 @@ void launch_convert_64_to_32(const double2* a, float2* b, int64_t n, hipStream_t
 
 // ============================================================================
 // The seed iteration k is two kernels:
-//   K1  q = z_s p - H p with per-block <r_k, q>, ||q||^2, ||r_k||^2
-//       (k_wilson, mode 1)
+//   K1  q_k = z_s r_k - H r_k + beta_{k-1} q_{k-1} with per-block <r_k, q_k>,
+//       ||q_k||^2, ||r_k||^2 (k_wilson_jobs, mode 1)
 //   K2  alpha_k, beta_k (every block, from K1's partials), shifted pi_{k+1},
 //       alpha^j, beta^j, residual estimates and deactivation (blocks
 //       0..nslices-1 own one 256-shift slice each, one lane per shift), then
-//       r <- r - alpha q together with p <- r + beta p or the shift sweep.
+//       r_{k+1} = r_k - alpha_k q_k, alone or with the shift sweep.
 // Quantities written in iteration k live in parity (k&1) or mod-3 buffers, so
 // no block reads what another block of the same kernel writes:
 //   SrcState.rr[k&1] = ||r_k||^2, alpha[k&1], beta[k&1];

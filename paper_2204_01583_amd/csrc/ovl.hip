@@ -123,8 +123,8 @@ struct ovl_ctx {
     int host_state_n = 0;
     DBuf bench_a, bench_b, bench_c, tune_state, tune_flush, chk;
     int check_n = 0;  // shifts per source whose true residual is checked after a solve
-    // in-band check (basis form): the true residual of every source's worst
-    // shift, fused into the final basis sum; off when false
+    // in-band check (basis form): the true residual of one shift per source
+    // (the one active longest), fused into the final basis sum; off when false
     bool inband_check = true;
     double check_bound = 0.0;  // > 0: the mixed repeat bound set by the caller
     DBuf chkdev;                   // hx [nsrc][maxk+1] | zc [nsrc] | partials [nsrc][kChkBlocks]
@@ -2026,7 +2026,7 @@ static int solve_batch_once(Batch& B) {
         L.max_true_rel_res = -1.0;
         L.mixed_true_rel_res = -1.0;
         if (w.hx && (status == OVL_OK || status == OVL_NOT_CONVERGED)) {
-            // in-band check: the worst shift of every source, partials summed in order
+            // in-band check: the checked shift of every source, partials summed in order
             double worst = 0.0;
             for (int n = 0; n < w.nsrc; ++n) {
                 double tt = 0.0, bb = 0.0;
@@ -2108,8 +2108,9 @@ static int solve(ovl_ctx* ctx, Work& w) {
 static int materialize(ovl_ctx* ctx, const Work& w, int j0, int jn, double2* Y, int n, int K);
 
 // True residuals ||b - (z_j - H) x_j|| / ||b|| of the last solve for the
-// ctx->check_n shifts of each source with the largest final residual
-// estimates (ties: lower j).  x_j is stored by the reference form and
+// first ctx->check_n shifts of each source in the in-band check's order
+// (active longest, then largest final estimate, then lower j; the reference
+// form by the estimate alone).  x_j is stored by the reference form and
 // rebuilt from the stored basis by the basis form; the fused and two-pass
 // forms keep neither, and report -1.  Diagnostic: synchronous.
 static int true_residuals(ovl_ctx* ctx, const Work& w) {
