@@ -1282,6 +1282,7 @@ struct Batch {
     int check_variant = 0, check_lnk = 0;  // H_W stencil of the in-band check
     JobDesc* desc_dev = nullptr;
     int* kdev = nullptr;
+    std::vector<char> retired;  // jobs taken out of the grids (every source finished)
 };
 
 void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], const int (&lnk)[2],
@@ -1327,8 +1328,9 @@ void fill_desc(ovl_ctx* c, Work& w, JobDesc& d, const int (&variant)[2], const i
 // precision skip the blocks of jobs in the other.
 int chunk_mode(const Batch& B) {
     int m = 0;
-    for (const JobDesc& d : B.desc) m |= 1 << d.phase;
-    return m;
+    for (size_t i = 0; i < B.desc.size(); ++i)
+        if (B.retired.empty() || !B.retired[i]) m |= 1 << B.desc[i].phase;
+    return m ? m : 1;
 }
 
 // Enqueue `count` seed iterations of every job, each in its own precision:
@@ -1422,6 +1424,8 @@ int replay_chunk(Batch& B, int mode, hipStream_t s) {
 }
 
 int run_chunk(Batch& B, bool graphs, hipStream_t s, int nact_total) {
+    if (B.vec_total <= 0 || B.sten_total[0] <= 0 || B.sten_total[1] <= 0)
+        return fail(B.ctx[0], OVL_E_STATE, "a chunk with no job left in the grids");
     const int mode = chunk_mode(B);
     if (graphs) return replay_chunk(B, mode, s);
     enqueue_chunk(B, mode, kChunk, s, B.ctx[0]->prof_on, nact_total);
@@ -1602,6 +1606,28 @@ void credit_live_bytes(const Batch& B) {
             if (!sweep) lead->prof_bytes[2 + f] += 3.0 * 12.0 * V * es * sum;
         }
     }
+}
+
+// Grid ranges of a batch: every job's blocks in the stencil grid of each
+// precision and in the vector grid, in job order.  A retired job (every
+// source finished) gets an empty range, so its blocks are no longer
+// launched; a block never resolves to an empty range, whose job keeps its
+// block counts.
+static void layout_grids(Batch& B, const std::vector<char>& retired) {
+    int sb[2] = {0, 0}, vb = 0;
+    for (size_t i = 0; i < B.desc.size(); ++i) {
+        JobDesc& d = B.desc[i];
+        const bool live = retired.empty() || !retired[i];
+        for (int f = 0; f < 2; ++f) {
+            d.sten_b0[f] = sb[f];
+            if (live) sb[f] += job_grid_blocks(d.sten_nb[f]);
+        }
+        d.vec_b0 = vb;
+        if (live) vb += d.nbe * d.nsrc;
+    }
+    B.sten_total[0] = sb[0];
+    B.sten_total[1] = sb[1];
+    B.vec_total = vb;
 }
 
 // Builds the job table of a batch for its current variants and link formats
@@ -1801,6 +1827,8 @@ static int solve_batch_once(Batch& B) {
     P.maxres = 1.0;
     int nact_known = 0;
     for (size_t i = 0; i < B.w.size(); ++i) nact_known += B.w[i]->J * B.w[i]->nsrc;
+    std::vector<char>& retired = B.retired;
+    retired.assign(B.w.size(), 0);
     hipEvent_t pev[2];
     HIPCHK(lead, hipEventCreateWithFlags(&pev[0], hipEventDisableTiming));
     HIPCHK(lead, hipEventCreateWithFlags(&pev[1], hipEventDisableTiming));
@@ -1875,6 +1903,24 @@ static int solve_batch_once(Batch& B) {
                     switch_job(B, i, k_enq, s);
                 }
             HIPCHK(lead, hipGetLastError());
+        }
+        // a batch's finished jobs leave the grids (after any chunk still
+        // queued); their active counts are cleared in both parities, so every
+        // later read of their state finds them finished
+        if (!B.fused && B.w.size() > 1) {
+            bool change = false;
+            for (size_t i = 0; i < B.w.size(); ++i)
+                if (P.job_done[i] && !retired[i]) {
+                    retired[i] = 1;
+                    change = true;
+                    HIPCHK(lead, hipMemsetAsync(B.w[i]->sh.cnt, 0,
+                                                (size_t)2 * B.w[i]->nsrc * kMaxSlices * sizeof(int), s));
+                }
+            if (change) {
+                layout_grids(B, retired);
+                HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(),
+                                            B.desc.size() * sizeof(JobDesc), hipMemcpyHostToDevice, s));
+            }
         }
     }
     // a chunk queued past the last poll: its state is the final one
@@ -1963,13 +2009,31 @@ static int solve_batch_once(Batch& B) {
                 B.desc[i].state_host = nullptr;  // the host keeps the first pass's final state
                 B.desc[i].phase = 0;
             }
+            std::fill(retired.begin(), retired.end(), 0);
+            layout_grids(B, retired);
             HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(), B.desc.size() * sizeof(JobDesc),
                                         hipMemcpyHostToDevice, s));
             HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));
             for (int k2 = 0; k2 < k_run; k2 += kChunk) {
-                // every job switches at the iteration of its first pass
-                for (size_t i = 0; i < B.w.size(); ++i)
+                // every job switches at the iteration of its first pass, and
+                // leaves the grids once the iterations of its first pass are done
+                bool change = false;
+                for (size_t i = 0; i < B.w.size(); ++i) {
                     if (mixed && B.w[i]->k_conv == k2) switch_job(B, i, k2, s);
+                    if (!B.fused && B.w.size() > 1 && !retired[i] && B.w[i]->K <= k2) {
+                        retired[i] = 1;
+                        change = true;
+                    }
+                }
+                if (change) {
+                    layout_grids(B, retired);
+                    // every job done: the first pass's last chunks (queued
+                    // ahead of its final poll) have nothing left to repeat
+                    if (B.vec_total == 0) break;
+                    HIPCHK(lead, hipMemcpyAsync(B.desc_dev, B.desc.data(),
+                                                B.desc.size() * sizeof(JobDesc),
+                                                hipMemcpyHostToDevice, s));
+                }
                 rc = run_chunk(B, graphs, s, nact_known);
                 if (rc) return rc;
             }
