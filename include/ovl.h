@@ -285,7 +285,13 @@ int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
  * OVL_STENCIL_VARIANT=v forces variant v (two-row links for SU(3) fields
  * unless OVL_LINKS=full), OVL_AUTOTUNE=0 keeps variant 0, and
  * OVL_AUTOTUNE_CACHE=path persists the choices as a JSON object, and
- * OVL_AUTOTUNE_VERBOSE=1 prints every candidate's time to stderr.
+ * OVL_AUTOTUNE_VERBOSE=1 prints every candidate's time to stderr.  The basis
+ * forms time their stencil inside the solve (the first chunk of a real
+ * solve, discarded).  OVL_FUSED=1, read when a context is created, makes
+ * the basis forms run one fused kernel per seed
+ * iteration instead of the stencil and update kernels (slower on MI355X;
+ * kept as a parity-tested alternative), with OVL_ITER_VARIANT=v forcing its
+ * variant v < 8.
  * Buffers are internal scratch (contents arbitrary but finite). */
 int ovl_bench_kernel(ovl_ctx* ctx, int32_t which, int32_t nrhs, int32_t reps,
                      double* avg_ms, double* bytes);
