@@ -236,6 +236,14 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
         const int edge = fwd ? g.L[mu] - 1 : 0;
         return (coord[mu] == edge && g.bc[mu] < 0) ? R(-1) : R(1);
     };
+    // Direction of step i of the one-lane-per-site loops (2-bit field i of
+    // kOrd): FP64 z, x, y, t and FP32 x, z, y, t.  The order decides how long
+    // after the block's LDS tile fill (and its neighbours' fills) each
+    // neighbour is read, and so how many of those reads L2 still serves: at
+    // 16^4 x 4 sources in the solver, z before the LDS-served x and y hops
+    // took the FP64 stencil from 55.4 to 52 us per launch against the order
+    // x, y, z, t; t or z first slowed the FP32 one by 2-5%.
+    constexpr unsigned kOrd = sizeof(R) == 8 ? 0xD2u : 0xD8u;
     if constexpr (SPL == 2) {
         const bool fwd = h == 0;
         if constexpr (HPI == 1) {
@@ -263,14 +271,15 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
     } else if constexpr (HPI == 1) {
 #pragma unroll 1
         for (int d = 0; d < 8; ++d) {
-            const int mu = d >> 1;
+            const int mu = (int)((kOrd >> (2 * (d >> 1))) & 3u);
             const bool fwd = (d & 1) == 0;
             const uint32_t nb = nbr(g, s, coord, mu, fwd);
             hop<R, RPT, TIL, LNK, LT, FU>(mu, fwd, acc, psi, U + (size_t)mu * NE * Vt, nb, fwd ? s : nb, tile, s0, lsg(mu, fwd), lu + (size_t)(mu) * NE * kBlock, fi);
         }
     } else {
 #pragma unroll 1
-        for (int mu = 0; mu < 4; ++mu) {
+        for (int i = 0; i < 4; ++i) {
+            const int mu = (int)((kOrd >> (2 * i)) & 3u);
             const uint32_t fw = nbr(g, s, coord, mu, true), bw = nbr(g, s, coord, mu, false);
             // both hops' loads are issued before either is used
             HopIn<R, RPT> d0, d1;
