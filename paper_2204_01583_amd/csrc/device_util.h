@@ -29,6 +29,56 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
+// Four block sums at once, each in the order of block_sum (so each result
+// is bitwise that of block_sum), with one pair of barriers instead of four:
+// the four butterflies are independent and overlap.  sh holds 4 NT/64 values.
+template <int NT>
+__device__ __forceinline__ void block_sum4(double (&v)[4], double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh[i * (NT / 64) + w] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) t += sh[i * (NT / 64) + q];
+        v[i] = t;
+    }
+    __syncthreads();
+}
+
+// A block sum and a block maximum at once (each in the order of block_sum /
+// block_max), with one pair of barriers.  sh holds 2 NT/64 values.
+template <int NT>
+__device__ __forceinline__ void block_sum_max(double& s, double& m, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        m = fmax(m, __shfl_xor(m, o, 64));
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        sh[w] = s;
+        sh[NT / 64 + w] = m;
+    }
+    __syncthreads();
+    double ts = 0.0, tm = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        ts += sh[i];
+        tm = fmax(tm, sh[NT / 64 + i]);
+    }
+    __syncthreads();
+    s = ts;
+    m = tm;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_max(double v, double* sh) {
 #pragma unroll

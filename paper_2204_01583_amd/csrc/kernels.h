@@ -54,7 +54,8 @@ void launch_wilson(int mode, const C2<R>* in, C2<R>* out, const C2<R>* U, const 
 int wilson_blocks(const Geom& g);
 
 // ---- seed iteration over a job table (device-side iteration counter kdev) --
-int vec_blocks(int64_t n12, int nslices);
+// Blocks per source of the vector kernels (see kernels.hip).
+int vec_blocks(int64_t n12, int nslices, bool slice_blocks);
 int wilson_grid_blocks(const Geom& g, int nrhs, int variant);
 // K1 for every job: q = z_s p - H p, <r_k, q> partials.  For this launch and
 // the next: non-null ev0/ev1 take the kernel's own start and end timestamps

@@ -261,11 +261,14 @@ __device__ __forceinline__ double sum_partials_re<double>(const double* p, int n
     for (int b = threadIdx.x; b < nb; b += kBlock) v += p[b];
     return block_sum<kBlock>(v, sh);
 }
-int vec_blocks(int64_t n12, int nslices) {
+int vec_blocks(int64_t n12, int nslices, bool slice_blocks) {
     int nb = (int)((n12 + 4 * kBlock - 1) / (4 * kBlock));
     if (nb > 512) nb = 512;
-    if (nb < nslices) nb = nslices;
-    return nb;
+    // slice_blocks (update kernel of the basis forms): one more block per
+    // 256-shift slice, which advances the slice while the others share the
+    // vector pass; otherwise every block also takes vector work
+    if (slice_blocks) return nb + nslices;
+    return nb < nslices ? nslices : nb;
 }
 
 // Decode a vector-grid block: job, source n and block bx of nbe for it.
@@ -299,7 +302,7 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
     const int f = sizeof(R) == 4 ? 1 : 0;
     const ShiftDev& sh = J.sh;
     SrcState& S = J.st[n];
-    __shared__ double shm[kBlock / 64];
+    __shared__ double shm[4 * kBlock / 64];
     int* cnt_next = sh.cnt + ((size_t)((k + 1) & 1) * sh.nsrc + n) * kMaxSlices;
     if (!src_live(S, sh, n, k)) {
         // a finished source stays finished; at the iteration limit the counts
@@ -364,8 +367,8 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
                     sh.h_pi[ho + sh.J] = act ? t.pn : make_double2(1, 0);
                 }
             }
-            const double tot = block_sum<kBlock>((double)stay, shm);
-            const double mx = block_max<kBlock>(act ? t.res : 0.0, shm);
+            double tot = (double)stay, mx = act ? t.res : 0.0;  // (shm: 2 kBlock/64 values)
+            block_sum_max<kBlock>(tot, mx, shm);
             if (threadIdx.x == 0) {
                 cnt_next[bx] = (int)(tot + 0.5);
                 sh.mres[(size_t)n * kMaxSlices + bx] = mx;
@@ -397,6 +400,12 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
     }
     const int64_t n12 = 12 * J.g.Vt;
     const R ar = (R)sc.alpha.x, ai = (R)sc.alpha.y;
+    // basis forms: the blocks that advance a shift slice (bx < nslices) take
+    // no part in the vector pass, which the other nbe - nslices blocks share,
+    // so the slice bookkeeping runs beside it instead of before a share of it
+    const int64_t vbx = SWEEP ? bx : bx - sh.nslices;
+    const int64_t vnb = SWEEP ? J.nbe : J.nbe - sh.nslices;
+    if (vbx < 0) return;
     const C2<R>* ri = job_rk<const C2<R>>(J, k, f) + (size_t)n * n12;
     C2<R>* ro = job_rk<C2<R>>(J, k + 1, f) + (size_t)n * n12;
     const C2<R>* qq = static_cast<const C2<R>*>(J.q[f]) + (size_t)n * n12;
@@ -412,7 +421,7 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
         const OVL_GLOBAL F4* qq4 = (const OVL_GLOBAL F4*)qq;
         OVL_GLOBAL F4* ro4 = (OVL_GLOBAL F4*)ro;
         const int64_t n2 = n12 / 2;
-        for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n2; e += (int64_t)J.nbe * kBlock) {
+        for (int64_t e = vbx * kBlock + threadIdx.x; e < n2; e += vnb * kBlock) {
             const F4 r = ri4[e], qv = qq4[e];
             F4 rn;
             rn.x = r.x - ((float)ar * qv.x - (float)ai * qv.y);
@@ -434,7 +443,7 @@ __device__ __forceinline__ void update_block(const JobDesc& J, int n, int bx, in
         const bool acc2 = J.h != nullptr;
         const double2 hk = acc2 ? J.h[(size_t)n * (sh.maxk + 1) + k + 1] : make_double2(0, 0);
         double2* sacc = J.s64 + (size_t)n * n12;
-        for (int64_t e = (int64_t)bx * kBlock + threadIdx.x; e < n12; e += (int64_t)J.nbe * kBlock) {
+        for (int64_t e = vbx * kBlock + threadIdx.x; e < n12; e += vnb * kBlock) {
             const cx<R> r = ld<R>(ri, e), qv = ld<R>(qq, e);
             const cx<R> rn = mk<R>(r.re - (ar * qv.re - ai * qv.im), r.im - (ar * qv.im + ai * qv.re));
             stc<R>(ro, e, rn);
@@ -541,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_s_init(const double2* __restrict__ b
 }
 void launch_s_init(const double2* b, const double2* h, int maxk, double2* s, int64_t n12, int nsrc,
                    hipStream_t st) {
-    hipLaunchKernelGGL(k_s_init, dim3(vec_blocks(n12, 1), nsrc), dim3(kBlock), 0, st, b, h, maxk,
+    hipLaunchKernelGGL(k_s_init, dim3(vec_blocks(n12, 1, false), nsrc), dim3(kBlock), 0, st, b, h, maxk,
                        s, n12);
 }
 
@@ -774,7 +783,7 @@ __global__ __launch_bounds__(kBlock) void k_init_state(SrcState* __restrict__ st
 }
 void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t n12,
                        const ShiftDev& sh, hipStream_t s) {
-    const int nb = vec_blocks(n12, sh.nslices);
+    const int nb = vec_blocks(n12, sh.nslices, false);
     hipLaunchKernelGGL(k_norm2, dim3(nb, sh.nsrc), dim3(kBlock), 0, s, b, partial, n12);
     hipLaunchKernelGGL(k_init_state, dim3(sh.nslices, sh.nsrc), dim3(kBlock), 0, s, st, partial,
                        nb, sh);

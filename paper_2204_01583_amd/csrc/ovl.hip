@@ -1137,7 +1137,7 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     }
     const int nslices = (J + 255) / 256;
     w.nbw = wilson_blocks(ctx->g);
-    w.nbe = vec_blocks(N, nslices);
+    w.nbe = vec_blocks(N, nslices, basis || twopass);
     HIPCHK(ctx, ctx->part_w.ensure(nq * (size_t)nsrc * w.nbw * sizeof(double4)));
     HIPCHK(ctx, ctx->part_b.ensure((size_t)nsrc * w.nbe * sizeof(double)));
     w.state_bytes = state_bytes_for(nsrc);

@@ -26,10 +26,12 @@ __device__ __forceinline__ SeedScalars seed_scalars_from(const double4* pw, int 
         a2 += v.z;
         a3 += v.w;
     }
-    a0 = block_sum<kBlock>(a0, shm);
-    a1 = block_sum<kBlock>(a1, shm);
-    a2 = block_sum<kBlock>(a2, shm);
-    a3 = block_sum<kBlock>(a3, shm);
+    double a[4] = {a0, a1, a2, a3};
+    block_sum4<kBlock>(a, shm);  // shm: 4 kBlock/64 values
+    a0 = a[0];
+    a1 = a[1];
+    a2 = a[2];
+    a3 = a[3];
     SeedScalars r;
     const double2 rq = make_double2(a0, a1);
     r.rr = a3;
@@ -108,8 +110,8 @@ __device__ __forceinline__ void advance_shift_slice(const ShiftDev& sh, const Sr
             sh.h_pi[ho + sh.J] = act ? t.pn : make_double2(1, 0);
         }
     }
-    const double tot = block_sum<kBlock>((double)stay, shm);
-    const double mx = block_max<kBlock>(act ? t.res : 0.0, shm);
+    double tot = (double)stay, mx = act ? t.res : 0.0;  // (shm: 2 kBlock/64 values)
+    block_sum_max<kBlock>(tot, mx, shm);
     if (threadIdx.x == 0) {
         cnt_next[slice] = (int)(tot + 0.5);
         sh.mres[(size_t)n * kMaxSlices + slice] = mx;

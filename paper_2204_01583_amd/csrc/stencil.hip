@@ -452,15 +452,13 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
         }
     }
     if constexpr (MODE == 1) {
-        __shared__ double shd[NT / 64];
+        __shared__ double shd[4 * NT / 64];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const double tr = block_sum<NT>(dre[r], shd);
-            const double ti_ = block_sum<NT>(dim[r], shd);
-            const double tq = block_sum<NT>(dqq[r], shd);
-            const double tn = block_sum<NT>(drr[r], shd);
+            double t[4] = {dre[r], dim[r], dqq[r], drr[r]};
+            block_sum4<NT>(t, shd);
             if (on[r] && threadIdx.x == 0)
-                partial[(int64_t)(n0 + r) * nsb + sb] = make_double4(tr, ti_, tq, tn);
+                partial[(int64_t)(n0 + r) * nsb + sb] = make_double4(t[0], t[1], t[2], t[3]);
         }
     }
 }
@@ -573,16 +571,14 @@ __device__ __forceinline__ void wilson_block_lt(const C2<R>* __restrict__ in, C2
         }
     }
     if constexpr (MODE == 1) {
-        __shared__ double shd[NT / 64];
+        __shared__ double shd[4 * NT / 64];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const bool mine = w == r;
-            const double tr = block_sum<NT>(mine ? dre : 0.0, shd);
-            const double ti_ = block_sum<NT>(mine ? dim : 0.0, shd);
-            const double tq = block_sum<NT>(mine ? dqq : 0.0, shd);
-            const double tn = block_sum<NT>(mine ? drr : 0.0, shd);
+            double t[4] = {mine ? dre : 0.0, mine ? dim : 0.0, mine ? dqq : 0.0, mine ? drr : 0.0};
+            block_sum4<NT>(t, shd);
             if (onr[r] && threadIdx.x == 0)
-                partial[(int64_t)(grp * RB + r) * nsb + sb] = make_double4(tr, ti_, tq, tn);
+                partial[(int64_t)(grp * RB + r) * nsb + sb] = make_double4(t[0], t[1], t[2], t[3]);
         }
     }
 }
@@ -701,7 +697,7 @@ __device__ __forceinline__ void iter_block(const JobDesc& J, int k, unsigned til
     const int sb = (int)uniform(ORD == 0 ? tile / (unsigned)nsrc : tile % (unsigned)nsb);
     const ShiftDev& sh = J.sh;
     SrcState& S = J.st[n];
-    __shared__ double shm[kBlock / 64];
+    __shared__ double shm[4 * kBlock / 64];
     // shift slices q = sb, sb + nsb, ... belong to site block sb (a small
     // lattice may have fewer site blocks than 256-shift slices)
     if (!src_live_fused(S, sh, n, k)) {
@@ -848,13 +844,11 @@ __device__ __forceinline__ void iter_block(const JobDesc& J, int k, unsigned til
         }
     }
     {
-        const double tr = block_sum<kBlock>(dre, shm);
-        const double ti_ = block_sum<kBlock>(dim, shm);
-        const double tq = block_sum<kBlock>(dqq, shm);
-        const double tn = block_sum<kBlock>(drr, shm);
+        double t[4] = {dre, dim, dqq, drr};
+        block_sum4<kBlock>(t, shm);
         if (threadIdx.x == 0)
             J.part_w[(size_t)(k & 1) * J.part_stride + (size_t)n * nsb + sb] =
-                make_double4(tr, ti_, tq, tn);
+                make_double4(t[0], t[1], t[2], t[3]);
     }
     if (k == 0) return;
     // iteration k-1 of the scalars: the seed's (block (0, n)) and the shifts'
