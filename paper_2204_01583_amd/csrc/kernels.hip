@@ -581,71 +581,113 @@ void launch_sum_ref(const double2* xj, const double2* c, double2* sacc, int J, i
 // basis forms
 // ============================================================================
 // x_j = sum_i u_i^j r_i with u_i^j = P_i^j / pi_i^j,
-// P_i^j = alpha_i^j + beta_i^j P_{i+1}^j (alpha^j recorded as 0 once shift j
-// stopped, which freezes x_j exactly as the sweep does).  One thread per
-// shift runs the backward recursion; W[src][i][j] = u_i^j.
+// P_i^j = alpha_i^j + beta_i^j P_{i+1}^j, P_K^j = 0 (alpha^j recorded as 0
+// once shift j stopped, which freezes x_j exactly as the sweep does).  The
+// backward recursion is split over kSeg segments of i per shift, so that
+// kSeg lanes share it: each lane composes its segment's affine maps
+// (P_lo = A + B P_hi), one lane per shift chains the segment ends from
+// P_K = 0, and each lane then runs the recursion over its segment from its
+// P_hi, storing P_i^j in W[src][i][j]; the row kernel below divides by
+// pi_i^j in place, in parallel over (i, j).  Block: kCoefShifts shifts x
+// kSeg segments of one source.
+constexpr int kSeg = 16, kCoefShifts = kBlock / kSeg;
 __global__ __launch_bounds__(kBlock) void k_coef(const double2* __restrict__ h_a,
                                                  const double2* __restrict__ h_b,
-                                                 const double2* __restrict__ h_pi,
-                                                 const double2* __restrict__ c,
                                                  const SrcState* __restrict__ st,
                                                  double2* __restrict__ W, int J, int maxk) {
+    __shared__ double2 lA[kSeg][kCoefShifts], lB[kSeg][kCoefShifts], lP[kSeg][kCoefShifts];
     const int n = blockIdx.y;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= J) return;
+    const int jl = (int)(threadIdx.x % kCoefShifts), seg = (int)(threadIdx.x / kCoefShifts);
+    const int j = blockIdx.x * kCoefShifts + jl;
+    const bool on = j < J;
     const int K = st[n].iter;
+    const int len = (K + kSeg - 1) / kSeg;
+    const int lo = seg * len < K ? seg * len : K, hi = lo + len < K ? lo + len : K;
     const int64_t hb = (int64_t)n * (maxk + 1) * J;
-    // The loads of a group of U steps do not depend on the recurrence: issue
-    // them together, then run the U steps, so a step costs arithmetic rather
-    // than a memory latency.  Same operations in the same order as one step
-    // at a time.
-    constexpr int U = 8;
-    double2 P = make_double2(0, 0);
-    for (int i0 = K - 1; i0 >= 0; i0 -= U) {
-        double2 a[U], b[U], pi[U];
+    // loads of U steps are issued before the steps that use them
+    constexpr int U = 16;
+    // 1. this segment's map: P_lo = A + B P_hi
+    double2 A = make_double2(0, 0), B = make_double2(1, 0);
+    for (int i0 = hi - 1; on && i0 >= lo; i0 -= U) {
+        double2 a[U], b[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 - u;
-            if (i >= 0) {
-                const int64_t o = hb + (int64_t)i * J + j;
-                a[u] = h_a[o];
-                b[u] = h_b[o];
-                pi[u] = (i == 0) ? make_double2(1, 0) : h_pi[o];
+        for (int u = 0; u < U; ++u)
+            if (i0 - u >= lo) {
+                a[u] = h_a[hb + (int64_t)(i0 - u) * J + j];
+                b[u] = h_b[hb + (int64_t)(i0 - u) * J + j];
             }
-        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 - u;
-            if (i >= 0) {
-                P = cadd(a[u], cmul(b[u], P));
-                W[hb + (int64_t)i * J + j] = cdiv(P, pi[u]);
+        for (int u = 0; u < U; ++u)
+            if (i0 - u >= lo) {
+                A = cadd(a[u], cmul(b[u], A));
+                B = cmul(b[u], B);
             }
+    }
+    lA[seg][jl] = A;
+    lB[seg][jl] = B;
+    __syncthreads();
+    // 2. segment ends, from the last segment (P_K = 0) down
+    if (seg == 0) {
+        double2 P = make_double2(0, 0);
+        for (int q = kSeg - 1; q >= 0; --q) {
+            lP[q][jl] = P;  // P at the segment's upper end
+            P = cadd(lA[q][jl], cmul(lB[q][jl], P));
         }
     }
+    __syncthreads();
+    // 3. the recursion over this segment from its upper end
+    double2 P = lP[seg][jl];
+    for (int i0 = hi - 1; on && i0 >= lo; i0 -= U) {
+        double2 a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 - u >= lo) {
+                a[u] = h_a[hb + (int64_t)(i0 - u) * J + j];
+                b[u] = h_b[hb + (int64_t)(i0 - u) * J + j];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 - u >= lo) {
+                P = cadd(a[u], cmul(b[u], P));
+                W[hb + (int64_t)(i0 - u) * J + j] = P;
+            }
+    }
 }
-// h[src][i] = sum_j c_j W[src][i][j] (fixed order)
-__global__ __launch_bounds__(kBlock) void k_hsum(const double2* __restrict__ W,
+// Row i of source n, one wave per row: u_i^j = P_i^j / pi_i^j (pi_0 = 1)
+// over P in W, and h[src][i] = sum_j c_j u_i^j with lane l adding the shifts
+// j = l, l + 64, ... in that order, then a butterfly over the lanes (a fixed
+// order; the row is read in coalesced 1 KiB pieces).  Rows from the source's
+// iteration count on get h = 0.
+__global__ __launch_bounds__(kBlock) void k_hsum(double2* __restrict__ W,
+                                                 const double2* __restrict__ h_pi,
                                                  const double2* __restrict__ c,
                                                  const SrcState* __restrict__ st,
                                                  double2* __restrict__ h, int J, int maxk) {
     const int n = blockIdx.y;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i > maxk) return;
+    const int i = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int l = (int)(threadIdx.x & 63);
+    if (i > maxk) return;  // wave-uniform
     const int K = st[n].iter;
     double2 t = make_double2(0, 0);
     if (i < K) {
-        const double2* w = W + ((int64_t)n * (maxk + 1) + i) * J;
-        for (int j = 0; j < J; ++j) t = cadd(t, cmul(c[j], w[j]));
+        const int64_t o = ((int64_t)n * (maxk + 1) + i) * J;
+        for (int j = l; j < J; j += 64) {
+            const double2 u = i == 0 ? W[o + j] : cdiv(W[o + j], h_pi[o + j]);
+            W[o + j] = u;
+            t = cadd(t, cmul(c[j], u));
+        }
     }
-    h[(int64_t)n * (maxk + 1) + i] = t;
+    t.x = wave_sum(t.x);
+    t.y = wave_sum(t.y);
+    if (l == 0) h[(int64_t)n * (maxk + 1) + i] = t;
 }
 void launch_basis_coef(const double2* h_a, const double2* h_b, const double2* h_pi,
                        const double2* c, const SrcState* st, double2* W, double2* h, int J,
                        int maxk, int nsrc, hipStream_t s) {
-    hipLaunchKernelGGL(k_coef, dim3((J + kBlock - 1) / kBlock, nsrc), dim3(kBlock), 0, s, h_a,
-                       h_b, h_pi, c, st, W, J, maxk);
-    hipLaunchKernelGGL(k_hsum, dim3((maxk + 1 + kBlock - 1) / kBlock, nsrc), dim3(kBlock), 0, s,
-                       W, c, st, h, J, maxk);
+    hipLaunchKernelGGL(k_coef, dim3((J + kCoefShifts - 1) / kCoefShifts, nsrc), dim3(kBlock), 0, s,
+                       h_a, h_b, st, W, J, maxk);
+    hipLaunchKernelGGL(k_hsum, dim3((maxk + 1 + kBlock / 64 - 1) / (kBlock / 64), nsrc),
+                       dim3(kBlock), 0, s, W, h_pi, c, st, h, J, maxk);
 }
 
 // The in-band residual check: for every source pick one shift (below), and
