@@ -294,6 +294,20 @@ __device__ __forceinline__ void dslash_site(cx<R> (&acc)[RPT][4][3],
 }
 
 
+// With rhs groups fastest, the XCD-aware remap hands each XCD a run of nsb/8
+// consecutive site blocks.  Where a site block is one whole (z, t) plane
+// (Lx Ly = kBlock sites, no padding) and Lz is even and Lt a multiple of 4,
+// that run is Lt/8 whole t-slices; this maps it to a Lz/2 x Lt/4 patch of
+// (z, t) planes instead, whose z and t faces (the neighbours the XCD reads
+// from the others') are 3/4 the size.  A bijection of the site blocks, so
+// the per-block partials keep their indices and summation order.
+__device__ __forceinline__ int plane_patch(int sb, const Geom& g, int nsb) {
+    const int Lz = g.L[2], Lt = g.L[3];
+    if (g.L[0] * g.L[1] != kBlock || nsb != Lz * Lt || (Lz & 1) || (Lt & 3)) return sb;
+    const int per = nsb / 8, x = sb / per, q = sb % per, zl = Lz / 2;
+    return (x & 1) * zl + q % zl + Lz * ((x >> 1) * (Lt / 4) + q / zl);
+}
+
 // Body of the stencil for one block, `tile` being the block's position in
 // the (site tile, rhs group) space after the XCD-aware remap.
 template <typename R, int MODE, int HPI, int RPT, int ORD, int SPL, int TIL, int LNK>
@@ -311,7 +325,8 @@ __device__ __forceinline__ void wilson_block(const C2<R>* __restrict__ in, C2<R>
     // neighbours were fetched moments earlier by the same XCD (many rhs).
     const int ngrp = (nrhs + RPT - 1) / RPT;
     const int n0 = (int)uniform(ORD == 0 ? tile % (unsigned)ngrp : tile / (unsigned)nsb) * RPT;
-    const int sb = (int)uniform(ORD == 0 ? tile / (unsigned)ngrp : tile % (unsigned)nsb);
+    const int sb = (int)uniform(ORD == 0 ? plane_patch((int)(tile / (unsigned)ngrp), g, nsb)
+                                         : (int)(tile % (unsigned)nsb));
     bool on[RPT];
     bool any = false;
 #pragma unroll
