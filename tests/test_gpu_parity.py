@@ -358,6 +358,36 @@ def test_stencil_variants(variant, links, monkeypatch):
     ctx.close()
 
 
+@pytest.mark.parametrize("variant", [v for v in range(24) if not v & 4])
+def test_stencil_plane_patch(variant, monkeypatch):
+    """Rhs-fastest variants on a lattice of whole 16 x 16 (z, t) planes, where
+    each XCD's run of planes is mapped to a (z, t) patch: H_W in both
+    precisions against the oracle, element by element, and the FP64 shifted
+    solve (job-table stencil, whose block partials sit at the permuted site
+    blocks' indices) against the same solve with the site-fastest twin
+    variant, whose blocks are not permuted."""
+    dims = (16, 16, 4, 8)
+    U = gauge(dims, 0.3, 5)
+    H = oracle_H(dims, 0.3, 5, 1.4)
+    b = si.gaussian_sources(dims, 3, first_seed=11)
+    sols = []
+    for v in (variant, variant | 4):
+        monkeypatch.setenv("OVL_STENCIL_VARIANT", str(v))
+        ctx = make_ctx(dims, U, nq=16, precision=0, form=2)
+        if v == variant:
+            out = ctx.apply_hw(to_dev(b)).cpu().numpy()
+            out32 = ctx.apply_hw_fp32(to_dev(b)).cpu().numpy()
+            for i in range(3):
+                ref = H @ b[i].ravel()
+                assert maxerr(out[i], ref) < 1e-14, ("fp64", i)
+                assert maxerr(out32[i], ref) < 1e-6, ("fp32", i)
+        s, st = ctx.apply_sign(to_dev(b))
+        assert st.stencil_variant64 == v + 28  # two-row links (SU(3) field)
+        sols.append(s.cpu().numpy())
+        ctx.close()
+    assert_close(sols[0], sols[1], 1e-12, f"sign, variant {variant} against {variant | 4}")
+
+
 def test_single_contour_against_oracle():
     """The one-contour form 2 P_+ - 1 (opt-in) against the oracle's direct
     solves with the same nodes and constant term, in FP64 and mixed."""
