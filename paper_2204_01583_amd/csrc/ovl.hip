@@ -1668,7 +1668,8 @@ static int build_desc(Batch& B, hipStream_t s, int phase = 0) {
 // precision prec: every variant in every allowed link format runs one chunk
 // of kChunk real iterations of this batch from its initial state (in FP32
 // from iteration 0 for prec 1), timed with events on the solve stream; the
-// fastest choice goes to *code.  The runs are discarded (the solve starts
+// four fastest run twice more, and the choice with the fastest run goes to
+// *code.  The runs are discarded (the solve starts
 // again from the initial state), so results do not depend on the tuning.  In
 // the solver the stencil reads vectors the previous kernel has just written,
 // which a stand-alone timing (cold caches, or warm from repeated launches on
@@ -1688,9 +1689,8 @@ static int tune_solver_stencil(Batch& B, hipStream_t s, int prec, bool all12, in
         hipEvent_t a, b;
         ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } evg{e0, e1};
-    double best_t = 1e30;
-    int best = kStencilVariants * (nfmt - 1);
-    for (int c = 0; c < kStencilVariants * nfmt; ++c) {
+    // one timed chunk of choice c (after an untimed one, from the initial state)
+    auto time_choice = [&](int c, float* ms) -> int {
         const int v = c % kStencilVariants, lnk = c / kStencilVariants;
         if (prec) { B.variant32 = v; B.lnk[1] = lnk; } else { B.variant64 = v; B.lnk[0] = lnk; }
         int rc = build_desc(B, s, prec);
@@ -1710,22 +1710,40 @@ static int tune_solver_stencil(Batch& B, hipStream_t s, int prec, bool all12, in
                 return fail(lead, OVL_E_STATE, "basis slots for the tuning chunks are missing");
         }
         HIPCHK(lead, hipMemsetAsync(B.kdev, 0, 2 * sizeof(int), s));
-        // one untimed chunk, then the timed one continues the same solve
         enqueue_chunk(B, 1 << prec, kChunk, s, false, 0);
         HIPCHK(lead, hipEventRecord(e0, s));
         enqueue_chunk(B, 1 << prec, kChunk, s, false, 0);
         HIPCHK(lead, hipEventRecord(e1, s));
         HIPCHK(lead, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(lead, hipEventElapsedTime(&ms, e0, e1));
+        HIPCHK(lead, hipEventElapsedTime(ms, e0, e1));
         if (verbose)
             fprintf(stderr, "ovl in-solver tune %s: choice %d (variant %d, %s links) %.2f us/iteration\n",
-                    prec ? "fp32" : "fp64", c, v, lnk ? "two-row" : "full", ms * 1e3 / kChunk);
-        if (ms < best_t) {
-            best_t = ms;
-            best = c;
-        }
+                    prec ? "fp32" : "fp64", c, v, lnk ? "two-row" : "full", *ms * 1e3 / kChunk);
+        return OVL_OK;
+    };
+    // every choice once, then the fastest few twice more each: a choice's
+    // time is its fastest run, so one slow sample does not decide between
+    // choices a few per cent apart
+    const int nc = kStencilVariants * nfmt;
+    std::vector<float> t(nc);
+    for (int c = 0; c < nc; ++c) {
+        int rc = time_choice(c, &t[c]);
+        if (rc) return rc;
     }
+    std::vector<int> order(nc);
+    for (int c = 0; c < nc; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t[a] < t[b]; });
+    constexpr int kFinalists = 4, kRepeats = 2;
+    for (int rep = 0; rep < kRepeats; ++rep)
+        for (int f = 0; f < kFinalists && f < nc; ++f) {
+            float ms = 0.f;
+            int rc = time_choice(order[f], &ms);
+            if (rc) return rc;
+            t[order[f]] = std::min(t[order[f]], ms);
+        }
+    int best = order[0];
+    for (int f = 1; f < kFinalists && f < nc; ++f)
+        if (t[order[f]] < t[best]) best = order[f];
     *code = best;
     return OVL_OK;
 }
