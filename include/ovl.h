@@ -286,8 +286,9 @@ int ovl_get_stats(const ovl_ctx* ctx, ovl_stats* st);
  * unless OVL_LINKS=full), OVL_AUTOTUNE=0 keeps variant 0, and
  * OVL_AUTOTUNE_CACHE=path persists the choices as a JSON object, and
  * OVL_AUTOTUNE_VERBOSE=1 prints every candidate's time to stderr.  The basis
- * forms time their stencil inside the solve (the first chunk of a real
- * solve, discarded).  OVL_FUSED=1, read when a context is created, makes
+ * forms time their stencil inside the solve (a chunk of a real solve from
+ * its initial state, discarded; the four fastest choices are timed twice
+ * more and each keeps its fastest run).  OVL_FUSED=1, read when a context is created, makes
  * the basis forms run one fused kernel per seed
  * iteration instead of the stencil and update kernels (slower on MI355X;
  * kept as a parity-tested alternative), with OVL_ITER_VARIANT=v forcing its
