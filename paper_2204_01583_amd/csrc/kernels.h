@@ -56,6 +56,8 @@ int wilson_blocks(const Geom& g);
 // ---- seed iteration over a job table (device-side iteration counter kdev) --
 // Blocks per source of the vector kernels (see kernels.hip).
 int vec_blocks(int64_t n12, int nslices, bool slice_blocks);
+// Doubles launch_init_state writes into its partial buffer (nsrc sources).
+size_t init_partials(int64_t n12, int nslices, int nsrc);
 int wilson_grid_blocks(const Geom& g, int nrhs, int variant);
 // K1 for every job: q = z_s p - H p, <r_k, q> partials.  For this launch and
 // the next: non-null ev0/ev1 take the kernel's own start and end timestamps

@@ -263,11 +263,15 @@ __device__ __forceinline__ double sum_partials_re<double>(const double* p, int n
 }
 int vec_blocks(int64_t n12, int nslices, bool slice_blocks) {
     int nb = (int)((n12 + 4 * kBlock - 1) / (4 * kBlock));
+    // slice_blocks (update kernel of the basis forms): at most 256 vector
+    // blocks per source, each block reducing the stencil partials once for
+    // more of the vector (at 16^4 x 4 the update took 3.33 / 5.75 ms per
+    // step in FP64 / FP32 with 256, 3.46 / 5.95 with 512, 3.36 / 6.28 with
+    // 1024, and more with 128 or 192), plus one block per 256-shift slice,
+    // which advances the slice while the others share the vector pass.
+    // Otherwise up to 512 blocks, every one also taking vector work.
+    if (slice_blocks) return (nb > 256 ? 256 : nb) + nslices;
     if (nb > 512) nb = 512;
-    // slice_blocks (update kernel of the basis forms): one more block per
-    // 256-shift slice, which advances the slice while the others share the
-    // vector pass; otherwise every block also takes vector work
-    if (slice_blocks) return nb + nslices;
     return nb < nslices ? nslices : nb;
 }
 
@@ -823,9 +827,12 @@ __global__ __launch_bounds__(kBlock) void k_init_state(SrcState* __restrict__ st
         st[n] = S;
     }
 }
+size_t init_partials(int64_t n12, int nslices, int nsrc) {
+    return (size_t)nsrc * vec_blocks(n12, nslices, false);
+}
 void launch_init_state(SrcState* st, const double2* b, double* partial, int64_t n12,
                        const ShiftDev& sh, hipStream_t s) {
-    const int nb = vec_blocks(n12, sh.nslices, false);
+    const int nb = vec_blocks(n12, sh.nslices, false);  // partial holds init_partials(...)
     hipLaunchKernelGGL(k_norm2, dim3(nb, sh.nsrc), dim3(kBlock), 0, s, b, partial, n12);
     hipLaunchKernelGGL(k_init_state, dim3(sh.nslices, sh.nsrc), dim3(kBlock), 0, s, st, partial,
                        nb, sh);

@@ -1139,7 +1139,9 @@ int prepare(ovl_ctx* ctx, int nsrc, Work& w) {
     w.nbw = wilson_blocks(ctx->g);
     w.nbe = vec_blocks(N, nslices, basis || twopass);
     HIPCHK(ctx, ctx->part_w.ensure(nq * (size_t)nsrc * w.nbw * sizeof(double4)));
-    HIPCHK(ctx, ctx->part_b.ensure((size_t)nsrc * w.nbe * sizeof(double)));
+    // ||b||^2 partials of the initialisation: one per block of its own grid
+    // (launch_init_state), which is not the update kernel's
+    HIPCHK(ctx, ctx->part_b.ensure(init_partials(N, nslices, nsrc) * sizeof(double)));
     w.state_bytes = state_bytes_for(nsrc);
     HIPCHK(ctx, ctx->state.ensure(w.state_bytes));
     w.part_w = ctx->part_w.as<double4>();
@@ -1446,6 +1448,8 @@ int init_job(ovl_ctx* c, Work& w, hipStream_t s) {
     }
     if (form == OVL_FORM_FUSED) HIPCHK(c, hipMemsetAsync(w.s64, 0, vec64, s));
     if (form == OVL_FORM_REFERENCE) HIPCHK(c, hipMemsetAsync(w.xj, 0, vec64 * w.J, s));
+    if (c->part_b.bytes < init_partials(w.N, w.sh.nslices, w.nsrc) * sizeof(double))
+        return fail(c, OVL_E_STATE, "initialisation partials buffer too small");
     launch_init_state(w.st, w.b64, w.part_b, w.N, w.sh, s);
     HIPCHK(c, hipGetLastError());
     return OVL_OK;

@@ -62,6 +62,32 @@ def test_lookahead_equals_chunk_by_chunk(precision, form):
     ctx.close()
 
 
+def test_init_partials_beyond_the_update_grid():
+    """A lattice whose initial ||b||^2 reduction runs more blocks per source
+    (up to 512) than the basis forms' update kernel (256 plus one per shift
+    slice): the reduction's partials have a buffer of their own size, and
+    the basis and two-pass forms, batched and alone, agree with the FP64
+    sweep form (a regression test for partials once sized by the update
+    grid)."""
+    from paper_2204_01583_amd import ovl
+    dims = (16, 16, 16, 6)  # 12 V / 1024 = 288 > 256 blocks
+    U = gauge(dims, 0.3, 4)
+    b = to_dev(si.gaussian_sources(dims, 2, first_seed=500))
+    ref_ctx = make_ctx(dims, U, nq=16, precision=0, form=1)
+    ref, _ = ref_ctx.apply_sign(b)
+    ref = ref.cpu().numpy()
+    ref_ctx.close()
+    for form in (2, 3):
+        ctx = make_ctx(dims, U, nq=16, precision=0, form=form)
+        s, _ = ctx.apply_sign(b)
+        err = relerr(s.cpu().numpy(), ref)
+        print(f"form {form} against the sweep form: {err:.2e}")
+        assert err < 1e-12
+        outs, _ = ovl.apply_sign_batched([ctx], [b])
+        assert relerr(outs[0].cpu().numpy(), ref) < 1e-12
+        ctx.close()
+
+
 def test_twopass_equals_basis():
     dims = (8, 8, 8, 8)
     U = gauge(dims, 0.3, 0)
